@@ -1,0 +1,64 @@
+"""Planted mistakes in a copy of the oracle must each fail at least one pin.
+
+Each case edits one expression of the oracle's C source (a dropped term, a
+wrong sign, a swapped operand, a wrong constant), compiles the copy with the
+oracle's own flags into a temporary library, and runs the pins against it.
+CPU only; the real oracle is untouched.
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins as P
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "omnitrack_oracle.c")
+
+MUTATIONS = {
+    "mismatch_sign": ("double d = A[k] - B;", "double d = B - A[k];"),
+    "b_uses_wrong_gradient": ("bx += d * X[k];", "bx += d * Y[k];"),
+    "inverse_offdiag_sign": ("(G2 * bx - G1 * by)", "(G2 * bx + G1 * by)"),
+    "coarse_to_fine_no_doubling_x": ("gx = 2.0 * (gx + nux);", "gx = (gx + nux);"),
+    "coarse_to_fine_no_doubling_y": ("gy = 2.0 * (gy + nuy);", "gy = (gy + nuy);"),
+    "level_scale": ("const double cx = ux / scale", "const double cx = ux / (scale + 0.5)"),
+    "window_template_offset": ("A[k] = orc_bilinear_u8(C->prev[l], w, h, cx + ox, cy + oy);",
+                               "A[k] = orc_bilinear_u8(C->prev[l], w, h, cx + oy, cy + ox);"),
+    "pyramid_rounding": ("(uint8_t)((s + 128) >> 8)", "(uint8_t)((s + 127) >> 8)"),
+    "pyramid_kernel": ("K5[5] = {1, 4, 6, 4, 1}", "K5[5] = {1, 4, 6, 4, 2}"),
+    "scharr_weights": ("S3[3] = {3, 10, 3}", "S3[3] = {3, 10, 4}"),
+    "bilinear_weights_swapped": ("a * (1 - b) * f10 + (1 - a) * b * f01",
+                                 "(1 - a) * b * f10 + a * (1 - b) * f01"),
+    "gradient_scale": ("/ 32.0;\n                Y[k]", "/ 16.0;\n                Y[k]"),
+    "gate_divisor": ("double lam = orc_min_eig(Gm) / N;", "double lam = orc_min_eig(Gm) / (N + 1);"),
+    "gate_ignored": ("if (!(lam >= C->min_eig))", "if (!(lam >= 0.0))"),
+    "eigen_sign": ("return m - sqrt(d * d + G[1] * G[1]);", "return m + sqrt(d * d + G[1] * G[1]);"),
+    "err_normaliser": ("*err = e / N;", "*err = e / (N - 1);"),
+    "even_median": ("0.5 * (v[c / 2 - 1] + v[c / 2])", "v[c / 2]"),
+    "box_lost_points_counted": ("box_id[i] == b && status[i] == 1", "box_id[i] == b"),
+    "out_of_frame_check": ("nx > W0 - 1 || ny > H0 - 1)", "nx > W0 + 5 || ny > H0 + 5)"),
+    "convergence_test": ("if (ex * ex + ey * ey < C->eps * C->eps) break;",
+                         "if (ex * ex + ey * ey < C->eps) break;"),
+}
+
+
+def _run_pins():
+    failed = []
+    for chk in P.ALL + [lambda: P.check_pyr_down_library(direct=True)]:
+        try:
+            chk()
+        except AssertionError:
+            failed.append(getattr(chk, "__name__", "pin"))
+    return failed
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(orc, tmp_path, name):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    mutated = tmp_path / "mut.c"
+    mutated.write_text(src.replace(old, new, 1))
+    lib = oracle.compile_to(str(mutated), str(tmp_path / "libmut.so"))
+    with oracle.use_library(lib):
+        failed = _run_pins()
+    assert failed, f"no pin caught the planted mistake {name}"
