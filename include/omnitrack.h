@@ -1,0 +1,228 @@
+/*
+ * omnitrack.h -- C ABI of the MI355X (gfx950) pyramidal Lucas-Kanade box
+ * tracker.
+ *
+ * The operation is the tracking stage of OmniTrack (arXiv 1910.06017,
+ * Sec. V-A): given two consecutive frames I_{t-1}, I_t and the boxes
+ * S_{t-1} of the objects tracked so far, predict their boxes S_t.
+ *   - preprocessing: each frame is reduced by a Gaussian pyramid
+ *     (ot_pyramid_build);
+ *   - feature calculation: the motion between the frames, here sparse
+ *     coarse-to-fine iterative Lucas-Kanade on points inside the boxes
+ *     (ot_lk_track) in place of the paper's dense TV-L1 field (Sec. IV);
+ *   - prediction: every box moves by the (median) motion of its points
+ *     (ot_box_update; the paper averages the motion vectors in the box).
+ * The Lucas-Kanade steps follow Bouguet (2000), "Pyramidal implementation
+ * of the Lucas-Kanade feature tracker"; gradients are 3x3 Scharr (2000);
+ * the point gate is the Shi-Tomasi (1994) minimum eigenvalue.
+ *
+ * Conventions shared by every call
+ *   - Pointers are DEVICE pointers unless marked (host).
+ *   - Images are uint8, row-major, with a row pitch in bytes >= width.
+ *   - Coordinates are level-0 pixels with pixel centres at integers; pixel i
+ *     of level l sits at level-0 position 2^l * i.  Level sizes are
+ *     w_l = ceil(w_{l-1} / 2), h_l = ceil(h_{l-1} / 2).
+ *   - Every call validates its arguments on the host before it enqueues
+ *     anything.  On an error nothing is enqueued and no output is written.
+ *     Otherwise the call only enqueues kernels on `stream` (a hipStream_t
+ *     passed as void*, NULL = the default stream) and returns without
+ *     synchronising; device faults surface at the caller's next
+ *     synchronisation.  No C++ exception crosses the ABI.
+ *   - The library allocates no device memory, keeps no pointer after a call
+ *     returns and has no global stream, handle or mutable state: calls are
+ *     thread-safe and may run concurrently on different streams (each
+ *     caller thread owns its own stream, the lesson of Sec. III-B).
+ *   - The caller owns every buffer and keeps it (and any frame a pyramid
+ *     aliases as its level 0) alive until the enqueued work has finished.
+ */
+#ifndef OMNITRACK_H
+#define OMNITRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define OT_API __attribute__((visibility("default")))
+#else
+#define OT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ot_err;
+enum {
+    OT_OK = 0,
+    OT_E_INVAL = -1,       /* a pointer, count or parameter is invalid */
+    OT_E_SHAPE = -2,       /* image or pyramid shapes do not agree */
+    OT_E_WORKSPACE = -3,   /* a caller buffer is too small */
+    OT_E_LAUNCH = -4,      /* the HIP runtime refused a launch or copy */
+    OT_E_UNSUPPORTED = -5  /* valid request this build does not implement */
+};
+
+#define OT_MAX_LEVELS 8
+#define OT_MAX_WIN 63
+#define OT_MAX_DIM 16384
+
+/* Gate default: lambda_min(G) / win^2 below this (gray levels per pixel,
+ * squared; 1e-4 on a [0,1] intensity scale) marks a point lost. */
+#define OT_DEFAULT_MIN_EIG 6.5025f
+
+/* (host) Descriptor of a device-resident pyramid.  level[0] may alias the
+ * caller's frame; levels 1.. live in a workspace. */
+typedef struct {
+    const uint8_t* level[OT_MAX_LEVELS];
+    int32_t w[OT_MAX_LEVELS];
+    int32_t h[OT_MAX_LEVELS];
+    int32_t pitch[OT_MAX_LEVELS];
+    int32_t levels; /* number of levels including level 0 */
+    int32_t flags;  /* reserved, 0 */
+} ot_pyr;
+
+/* Bytes of device workspace ot_pyramid_build needs for levels 1..levels-1
+ * of a W x H frame (0 when levels == 1).  Returns 0 for invalid sizes.
+ * Each level starts 256-byte aligned with a pitch rounded up to 64 bytes. */
+OT_API size_t ot_pyramid_bytes(int32_t W, int32_t H, int32_t levels, int32_t flags);
+
+/* (host) Fill *out with the layout ot_pyramid_build would produce, without
+ * enqueuing anything (used to re-describe a resident pyramid). */
+OT_API ot_err ot_pyramid_layout(const uint8_t* frame, int32_t W, int32_t H, int32_t pitch,
+                         int32_t levels, void* workspace, size_t ws_bytes, int32_t flags,
+                         ot_pyr* out);
+
+/* Gaussian pyramid (Sec. V-A preprocessing; binomial reduce of Burt &
+ * Adelson 1983): level l from level l-1 as
+ *   P_l(x,y) = (S + 128) >> 8,  S = sum_{i,j=-2..2} k_i k_j P_{l-1}(cx(2x+i), cy(2y+j))
+ * with k = (1,4,6,4,1) and cx, cy clamping to the level's edge -- exact
+ * integer arithmetic, rounding half up.
+ * frame: W x H, row pitch `pitch`; levels in [1, OT_MAX_LEVELS];
+ * workspace: >= ot_pyramid_bytes(W, H, levels, flags) bytes, 256-aligned.
+ * *out (host) receives the descriptor, level[0] = frame.
+ * Errors: OT_E_INVAL (null pointers, W/H out of [1, OT_MAX_DIM], pitch < W,
+ * levels out of range, flags != 0), OT_E_WORKSPACE (ws_bytes too small or
+ * misaligned), OT_E_LAUNCH. */
+OT_API ot_err ot_pyramid_build(const uint8_t* frame, int32_t W, int32_t H, int32_t pitch,
+                        int32_t levels, void* workspace, size_t ws_bytes, int32_t flags,
+                        ot_pyr* out, void* stream);
+
+/* Optional controls of ot_lk_track_ex (host struct). */
+typedef struct {
+    float min_eig;      /* gate threshold on lambda_min/win^2 (OT_DEFAULT_MIN_EIG) */
+    uint8_t* iters_out; /* device n x levels, iterations run per level, or NULL */
+    float* lam_out;     /* device n x levels, lambda_min/win^2 per level, or NULL */
+    int32_t margin;     /* LDS search margin in pixels, 0 = default (4), max 16 */
+} ot_lk_opts;
+
+/* Pyramidal iterative Lucas-Kanade (Bouguet 2000) from prev_pyr to next_pyr.
+ * For each point u (pts, n x 2 float32 interleaved x,y):
+ *   g = 0; for l = levels-1 .. 0, with c = u / 2^l:
+ *     A(o) = I_l(c+o), X(o), Y(o) = bilinear Scharr/32 gradients of I_l at c+o,
+ *       o over the win x win integer offsets around c;
+ *     G = sum [X^2 XY; XY Y^2]; the point is lost if lambda_min(G)/win^2 < min_eig;
+ *     nu = 0; up to `iters` times: B(o) = J_l(c+g+nu+o), d = A - B,
+ *       b = sum d [X, Y], eta = G^{-1} b, nu += eta, stop once |eta|^2 < eps^2;
+ *     g = 2 (g + nu) for l > 0, else the flow is g + nu.
+ *   next = u + flow.  Bilinear taps clamp to the level's edge.
+ * Outputs: next_pts n x 2 float32; status n (1 tracked, 0 lost: non-finite or
+ * out-of-frame input, failed gate, or final position non-finite or outside
+ * [0,W-1] x [0,H-1]); err n float32 (mean |I-J| over the level-0 window on the
+ * 0..255 scale, -1 when lost) or NULL.  next_pts of a lost point holds its last
+ * estimate.  Arithmetic is FP32.
+ * Arguments: win odd in [3, OT_MAX_WIN]; 1 <= levels <= both pyramids' levels;
+ * iters >= 1; eps >= 0 and finite (0 runs exactly `iters` iterations per level);
+ * level-0 shapes of both pyramids equal; n >= 0 (n == 0 is a no-op).
+ * Errors: OT_E_INVAL, OT_E_SHAPE, OT_E_LAUNCH. */
+OT_API ot_err ot_lk_track(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* pts, int32_t n,
+                   int32_t win, int32_t levels, int32_t iters, float eps, float* next_pts,
+                   uint8_t* status, float* err, void* stream);
+
+/* ot_lk_track with optional controls; opts may be NULL (defaults). */
+OT_API ot_err ot_lk_track_ex(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* pts,
+                      int32_t n, int32_t win, int32_t levels, int32_t iters, float eps,
+                      float* next_pts, uint8_t* status, float* err, const ot_lk_opts* opts,
+                      void* stream);
+
+/* Box prediction (Sec. V-A prediction phase): for box b in [0, m),
+ * (mx, my) = component-wise median of next_pts - pts over the points with
+ * box_id == b and status == 1 (the mean of the two middle values for an even
+ * count); out_boxes[b] = boxes[b] + (mx, my, mx, my), out_count[b] = that count.
+ * A box without such points is copied unchanged with count 0 (lost).
+ * boxes, out_boxes m x 4 float32 (x0, y0, x1, y1); box_id n int32 (ids outside
+ * [0, m) belong to no box); pts, next_pts n x 2; status n.
+ * Errors: OT_E_INVAL (negative counts, null pointers with m > 0), OT_E_LAUNCH. */
+OT_API ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id, const float* pts,
+                     const float* next_pts, const uint8_t* status, int32_t n, float* out_boxes,
+                     int32_t* out_count, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched tick: many independent streams (frame pairs) in one launch per
+ * stage.  Stage 1 builds every job's next pyramid (all jobs, one launch per
+ * level), stage 2 tracks every job's points in one launch, stage 3 updates
+ * every job's boxes in one launch.  Results equal the per-job calls.
+ * The caller packs a descriptor table on the host (ot_batch_pack into a
+ * pinned buffer of ot_batch_table_bytes), and ot_batch_run copies it to a
+ * device buffer of the same size and launches the stages on `stream`.  The
+ * work sizes are read from the device table, so a HIP graph captured around
+ * ot_batch_run replays any later table of the same capacities.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    ot_pyr prev;                /* resident pyramid of I_{t-1} */
+    const uint8_t* next_frame;  /* level 0 of I_t */
+    int32_t next_pitch;
+    void* next_ws;              /* workspace for levels 1.. of I_t's pyramid */
+    size_t next_ws_bytes;
+    int32_t levels;             /* levels built and tracked (<= prev.levels) */
+    const float* pts;           /* n x 2 */
+    int32_t n;
+    float* next_pts;            /* n x 2 */
+    uint8_t* status;            /* n */
+    float* err;                 /* n or NULL */
+    const float* boxes;         /* m x 4 */
+    int32_t m;
+    const int32_t* box_id;      /* n */
+    float* out_boxes;           /* m x 4 */
+    int32_t* out_count;         /* m */
+} ot_job;
+
+typedef struct {
+    int32_t win, iters;
+    float eps, min_eig;
+    int32_t margin;        /* as ot_lk_opts.margin */
+    int32_t lk_waves;      /* persistent LK grid in waves; 0 = one wave per point */
+    int32_t chunk;         /* points a persistent wave claims at a time (>= 1) */
+    int32_t max_jobs;      /* table capacity in jobs */
+    int32_t max_points;    /* capacity in points, sizes the non-persistent LK grid */
+    int32_t max_boxes;     /* capacity in boxes */
+    int32_t max_tiles;     /* capacity in pyramid tiles per level */
+    int32_t max_levels;    /* levels launched for the pyramid stage */
+} ot_batch_cfg;
+
+/* Bytes of the descriptor table for cfg's capacities (0 if invalid). */
+OT_API size_t ot_batch_table_bytes(const ot_batch_cfg* cfg);
+
+/* (host) Validate the jobs against cfg and write the table into table_host.
+ * next_out (host, njobs entries, may be NULL) receives each job's next
+ * pyramid descriptor.  Errors: OT_E_INVAL, OT_E_SHAPE, OT_E_WORKSPACE
+ * (capacity exceeded or a job's workspace too small). */
+OT_API ot_err ot_batch_pack(const ot_job* jobs, int32_t njobs, const ot_batch_cfg* cfg,
+                     void* table_host, size_t table_bytes, ot_pyr* next_out);
+
+/* Copy the packed table to table_dev and launch the three stages on stream.
+ * table_host should be pinned memory for the copy to be asynchronous; it
+ * must stay unchanged until the copy has executed.  The table holds the
+ * persistent stage's work counter, which the stage returns to zero itself.
+ * Errors: OT_E_INVAL, OT_E_WORKSPACE, OT_E_LAUNCH. */
+OT_API ot_err ot_batch_run(const void* table_host, void* table_dev, size_t table_bytes,
+                    const ot_batch_cfg* cfg, void* stream);
+
+/* Static text for an error code. */
+OT_API const char* ot_strerror(ot_err e);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+OT_API int32_t ot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OMNITRACK_H */

@@ -1,0 +1,123 @@
+// ot_common.hpp -- layouts shared by the host layer and the gfx950 kernels of
+// the pyramidal Lucas-Kanade tracker (device descriptors, batched table).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include "omnitrack.h"
+
+#if defined(__HIPCC__)
+#define OT_HD __host__ __device__
+#else
+#define OT_HD
+#endif
+
+namespace ot {
+
+// Pyramid reduce tile: one 256-thread workgroup writes PYR_TW x PYR_TH pixels
+// of level l and reads the (2*PYR_TH+3) x (2*PYR_TW+3) region of level l-1.
+constexpr int PYR_TW = 64;
+constexpr int PYR_TH = 16;
+constexpr int PYR_THREADS = 256;
+
+// Box median: one 256-thread workgroup per box; up to BOX_CAP point
+// displacements are gathered in LDS, larger boxes are re-scanned from memory.
+constexpr int BOX_THREADS = 256;
+constexpr int BOX_CAP = 4096;
+
+constexpr int LK_DEFAULT_MARGIN = 4;
+constexpr int LK_MAX_MARGIN = 16;
+constexpr size_t LK_MAX_LDS = 64 * 1024;
+
+// Device view of a pyramid (copied by value into kernel arguments or into
+// the batched table).
+struct DevPyr {
+    const uint8_t* lvl[OT_MAX_LEVELS];
+    int32_t w[OT_MAX_LEVELS];
+    int32_t h[OT_MAX_LEVELS];
+    int32_t pitch[OT_MAX_LEVELS];
+};
+
+struct LkParams {
+    int32_t win;
+    int32_t levels;  // single-call launches; batched jobs carry their own
+    int32_t iters;
+    float eps2;
+    float min_eig;
+    int32_t margin;
+};
+
+// One stream's frame pair in the batched table.
+struct DevJob {
+    DevPyr prev;
+    DevPyr next;
+    const float* pts;
+    float* next_pts;
+    uint8_t* status;
+    float* err;
+    const float* boxes;
+    const int32_t* box_id;
+    float* out_boxes;
+    int32_t* out_count;
+    int32_t n, m, levels, pad0;
+};
+
+// Batched table header.  The whole table is rewritten by each host->device
+// copy, which also returns the persistent stage's work counter to zero.
+struct TableHdr {
+    int32_t njobs;
+    int32_t total_pts;
+    int32_t total_boxes;
+    int32_t max_level;                  // highest pyramid level built
+    int32_t total_tiles[OT_MAX_LEVELS]; // per level (index 0 unused)
+    LkParams lk;
+    int32_t chunk;
+    uint32_t counter;                   // persistent LK work counter
+    uint32_t pad[4];
+};
+
+// Table layout for capacities (njobs_cap): header | jobs | pt_prefix |
+// box_prefix | tile_prefix[levels][njobs_cap + 1] | tile_cols[levels][njobs_cap].
+struct TableLayout {
+    size_t jobs, pt_prefix, box_prefix, tile_prefix, tile_cols, bytes;
+    OT_HD static TableLayout make(int32_t cap) {
+        TableLayout t;
+        size_t off = (sizeof(TableHdr) + 255) & ~size_t(255);
+        t.jobs = off;
+        off += sizeof(DevJob) * (size_t)cap;
+        t.pt_prefix = off;
+        off += sizeof(int32_t) * (size_t)(cap + 1);
+        t.box_prefix = off;
+        off += sizeof(int32_t) * (size_t)(cap + 1);
+        t.tile_prefix = off;
+        off += sizeof(int32_t) * (size_t)(cap + 1) * OT_MAX_LEVELS;
+        t.tile_cols = off;
+        off += sizeof(int32_t) * (size_t)cap * OT_MAX_LEVELS;
+        t.bytes = (off + 255) & ~size_t(255);
+        return t;
+    }
+};
+
+// Rows per lane strip for a window: the wave's 64 lanes cover the window as
+// win columns x nseg row segments of `rows` rows.
+OT_HD inline int lk_nseg(int win) {
+    int s = 64 / win;
+    return s < 1 ? 1 : (s > win ? win : s);
+}
+OT_HD inline int lk_rows_needed(int win) {
+    int s = lk_nseg(win);
+    return (win + s - 1) / s;
+}
+
+// LDS bytes one tracking wave needs: the larger of the set-up stage (uint8
+// template patch + float2 gradient tap grid) and the iteration stage (float2
+// target region with a margin on every side).
+OT_HD inline size_t lk_lds_bytes(int win, int R, int margin) {
+    const int nseg = lk_nseg(win);
+    const int RR = nseg * R + 1, TW = win + 1, PW = (TW + 2 + 3) & ~3;
+    const size_t setup = (size_t)(((RR + 2) * PW + 15) & ~15) + (size_t)RR * TW * 8;
+    const size_t iter = (size_t)(RR + 2 * margin) * (TW + 2 * margin) * 8;
+    return setup > iter ? setup : iter;
+}
+
+}  // namespace ot

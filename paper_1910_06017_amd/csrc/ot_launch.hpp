@@ -1,0 +1,32 @@
+// ot_launch.hpp -- internal host launchers (one per kernel family).  Each
+// enqueues on `stream` and returns hipGetLastError() of its launches.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ot_common.hpp"
+
+namespace ot {
+
+// Level l of a pyramid from level l-1.
+hipError_t launch_pyr_level(const uint8_t* src, int sw, int sh, int sp, uint8_t* dst, int dw,
+                            int dh, int dp, hipStream_t stream);
+
+// Template row count the tracker uses for a window (0 = unsupported).
+int lk_template_rows(int win);
+
+hipError_t launch_lk(const DevPyr& prev, const DevPyr& next, const float* pts, int n,
+                     const LkParams& prm, float* next_pts, uint8_t* status, float* err,
+                     uint8_t* iters_out, float* lam_out, hipStream_t stream);
+
+hipError_t launch_box(const float* boxes, int m, const int32_t* box_id, const float* pts,
+                      const float* next_pts, const uint8_t* status, int n, float* out_boxes,
+                      int32_t* out_count, hipStream_t stream);
+
+// Batched stages over a device table (layout TableLayout::make(cap)).
+hipError_t launch_batch_pyr(const uint8_t* table, int cap, int level, int grid,
+                            hipStream_t stream);
+hipError_t launch_batch_lk(const uint8_t* table, int cap, int win, int margin, int grid,
+                           bool persistent, hipStream_t stream);
+hipError_t launch_batch_box(const uint8_t* table, int cap, int grid, hipStream_t stream);
+
+}  // namespace ot

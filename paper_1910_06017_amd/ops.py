@@ -1,0 +1,236 @@
+"""Thin ctypes binding of the C ABI in include/omnitrack.h.
+
+Argument marshalling only: every step of the tracking path runs in the HIP
+kernels of libomnitrack.so.  torch is used for device memory and streams.
+There is no fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libomnitrack.so")
+
+OT_MAX_LEVELS = 8
+OT_MAX_WIN = 63
+OT_DEFAULT_MIN_EIG = 6.5025
+ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
+          -4: "OT_E_LAUNCH", -5: "OT_E_UNSUPPORTED"}
+
+# Every symbol the header declares.
+EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
+           "ot_lk_track_ex", "ot_box_update", "ot_batch_table_bytes", "ot_batch_pack",
+           "ot_batch_run", "ot_strerror", "ot_version"]
+
+
+class OtError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {ERRORS.get(code, code)} ({code})")
+        self.code = code
+
+
+class OtPyr(C.Structure):
+    _fields_ = [("level", C.c_void_p * OT_MAX_LEVELS), ("w", C.c_int32 * OT_MAX_LEVELS),
+                ("h", C.c_int32 * OT_MAX_LEVELS), ("pitch", C.c_int32 * OT_MAX_LEVELS),
+                ("levels", C.c_int32), ("flags", C.c_int32)]
+
+
+class OtLkOpts(C.Structure):
+    _fields_ = [("min_eig", C.c_float), ("iters_out", C.c_void_p), ("lam_out", C.c_void_p),
+                ("margin", C.c_int32)]
+
+
+class OtJob(C.Structure):
+    _fields_ = [("prev", OtPyr), ("next_frame", C.c_void_p), ("next_pitch", C.c_int32),
+                ("next_ws", C.c_void_p), ("next_ws_bytes", C.c_size_t), ("levels", C.c_int32),
+                ("pts", C.c_void_p), ("n", C.c_int32), ("next_pts", C.c_void_p),
+                ("status", C.c_void_p), ("err", C.c_void_p), ("boxes", C.c_void_p),
+                ("m", C.c_int32), ("box_id", C.c_void_p), ("out_boxes", C.c_void_p),
+                ("out_count", C.c_void_p)]
+
+
+class OtBatchCfg(C.Structure):
+    _fields_ = [("win", C.c_int32), ("iters", C.c_int32), ("eps", C.c_float),
+                ("min_eig", C.c_float), ("margin", C.c_int32), ("lk_waves", C.c_int32),
+                ("chunk", C.c_int32), ("max_jobs", C.c_int32), ("max_points", C.c_int32),
+                ("max_boxes", C.c_int32), ("max_tiles", C.c_int32), ("max_levels", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libomnitrack.so (built by paper_1910_06017_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1910_06017_amd/build.py "
+                               "(there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        P, i32, sz, f32 = C.c_void_p, C.c_int32, C.c_size_t, C.c_float
+        PP = C.POINTER(OtPyr)
+        L.ot_pyramid_bytes.argtypes = [i32, i32, i32, i32]
+        L.ot_pyramid_bytes.restype = sz
+        L.ot_pyramid_layout.argtypes = [P, i32, i32, i32, i32, P, sz, i32, PP]
+        L.ot_pyramid_layout.restype = i32
+        L.ot_pyramid_build.argtypes = [P, i32, i32, i32, i32, P, sz, i32, PP, P]
+        L.ot_pyramid_build.restype = i32
+        L.ot_lk_track.argtypes = [PP, PP, P, i32, i32, i32, i32, f32, P, P, P, P]
+        L.ot_lk_track.restype = i32
+        L.ot_lk_track_ex.argtypes = [PP, PP, P, i32, i32, i32, i32, f32, P, P, P,
+                                     C.POINTER(OtLkOpts), P]
+        L.ot_lk_track_ex.restype = i32
+        L.ot_box_update.argtypes = [P, i32, P, P, P, P, i32, P, P, P]
+        L.ot_box_update.restype = i32
+        L.ot_batch_table_bytes.argtypes = [C.POINTER(OtBatchCfg)]
+        L.ot_batch_table_bytes.restype = sz
+        L.ot_batch_pack.argtypes = [C.POINTER(OtJob), i32, C.POINTER(OtBatchCfg), P, sz, PP]
+        L.ot_batch_pack.restype = i32
+        L.ot_batch_run.argtypes = [P, P, sz, C.POINTER(OtBatchCfg), P]
+        L.ot_batch_run.restype = i32
+        L.ot_strerror.argtypes = [i32]
+        L.ot_strerror.restype = C.c_char_p
+        L.ot_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def check(code: int, what: str) -> None:
+    if code != 0:
+        raise OtError(code, what)
+
+
+# --------------------------------------------------------------------- torch side
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _need(t, dtype, shape_last=None, what="tensor"):
+    torch = _torch()
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous CUDA {dtype} tensor")
+    if shape_last is not None and (t.dim() < 1 or t.shape[-1] != shape_last):
+        raise ValueError(f"{what} must have last dimension {shape_last}")
+    del torch
+
+
+def pyramid_bytes(W: int, H: int, levels: int) -> int:
+    return int(lib().ot_pyramid_bytes(W, H, levels, 0))
+
+
+class Pyramid:
+    """A device-resident pyramid: level 0 aliases `frame`, levels 1.. live in `ws`."""
+
+    def __init__(self, frame, ws, desc: OtPyr):
+        self.frame, self.ws, self.desc = frame, ws, desc
+
+    @property
+    def levels(self) -> int:
+        return self.desc.levels
+
+    def level(self, l: int):
+        """Level l as an (h, w) uint8 tensor view (copies out of the pitched buffer)."""
+        torch = _torch()
+        if l == 0:
+            return self.frame
+        d = self.desc
+        off = d.level[l] - self.ws.data_ptr()
+        rows = self.ws[off:off + d.pitch[l] * d.h[l]].view(d.h[l], d.pitch[l])
+        return rows[:, :d.w[l]]
+
+
+def alloc_workspace(W: int, H: int, levels: int, device="cuda"):
+    torch = _torch()
+    nb = pyramid_bytes(W, H, levels)
+    # torch's caching allocator hands out 512-byte aligned blocks
+    return torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+
+
+def pyramid_build(frame, levels: int, ws=None, stream=None) -> Pyramid:
+    """Build levels 1..levels-1 of `frame` ((H, W) uint8 CUDA tensor)."""
+    torch = _torch()
+    _need(frame, torch.uint8, what="frame")
+    H, W = frame.shape
+    if ws is None:
+        ws = alloc_workspace(W, H, levels, frame.device)
+    desc = OtPyr()
+    check(lib().ot_pyramid_build(_ptr(frame), W, H, frame.stride(0), levels, _ptr(ws), ws.numel(),
+                                 0, C.byref(desc), _stream_handle(stream)), "ot_pyramid_build")
+    return Pyramid(frame, ws, desc)
+
+
+def pyramid_layout(frame, levels: int, ws) -> Pyramid:
+    H, W = frame.shape
+    desc = OtPyr()
+    check(lib().ot_pyramid_layout(_ptr(frame), W, H, frame.stride(0), levels, _ptr(ws),
+                                  ws.numel(), 0, C.byref(desc)), "ot_pyramid_layout")
+    return Pyramid(frame, ws, desc)
+
+
+def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None = None,
+             iters: int = 30, eps: float = 0.01, min_eig: float = OT_DEFAULT_MIN_EIG,
+             margin: int = 0, want_err: bool = True, want_diag: bool = False, out=None,
+             stream=None):
+    """Track (n, 2) float32 points.  Returns (next_pts, status, err[, iters, lam])."""
+    torch = _torch()
+    _need(pts, torch.float32, 2, "pts")
+    n = pts.shape[0]
+    L = prev.levels if levels is None else levels
+    dev = pts.device
+    if out is None:
+        next_pts = torch.empty((n, 2), dtype=torch.float32, device=dev)
+        status = torch.empty(n, dtype=torch.uint8, device=dev)
+        err = torch.empty(n, dtype=torch.float32, device=dev) if want_err else None
+    else:
+        next_pts, status, err = out
+    opts = OtLkOpts(min_eig, None, None, margin)
+    it = lam = None
+    if want_diag:
+        it = torch.zeros((n, L), dtype=torch.uint8, device=dev)
+        lam = torch.zeros((n, L), dtype=torch.float32, device=dev)
+        opts.iters_out, opts.lam_out = _ptr(it), _ptr(lam)
+    check(lib().ot_lk_track_ex(C.byref(prev.desc), C.byref(nxt.desc), _ptr(pts), n, win, L,
+                               iters, eps, _ptr(next_pts), _ptr(status), _ptr(err),
+                               C.byref(opts), _stream_handle(stream)), "ot_lk_track")
+    if want_diag:
+        return next_pts, status, err, it, lam
+    return next_pts, status, err
+
+
+def box_update(boxes, box_id, pts, next_pts, status, out=None, stream=None):
+    """Per-box median displacement.  Returns (out_boxes (m,4), out_count (m,))."""
+    torch = _torch()
+    _need(boxes, torch.float32, 4, "boxes")
+    m = boxes.shape[0]
+    n = pts.shape[0]
+    if out is None:
+        ob = torch.empty((m, 4), dtype=torch.float32, device=boxes.device)
+        oc = torch.empty(m, dtype=torch.int32, device=boxes.device)
+    else:
+        ob, oc = out
+    check(lib().ot_box_update(_ptr(boxes), m, _ptr(box_id), _ptr(pts), _ptr(next_pts),
+                              _ptr(status), n, _ptr(ob), _ptr(oc), _stream_handle(stream)),
+          "ot_box_update")
+    return ob, oc
+
+
+def strerror(code: int) -> str:
+    return lib().ot_strerror(code).decode()
+
+
+def version() -> int:
+    return int(lib().ot_version())

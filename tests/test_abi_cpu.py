@@ -1,0 +1,188 @@
+"""The C ABI library on the CPU: it loads, exports every symbol the header
+declares, and its host-side validation and table packing behave as the
+header states.  No kernel is launched (fake device addresses are never
+dereferenced because every case here fails validation or only packs a host
+table)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_06017_amd import ops
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "omnitrack.h")
+
+FAKE = 0x7F0000000000  # 256-aligned, never dereferenced
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ops.LIB_PATH):
+        pytest.skip("libomnitrack.so not built")
+    return ops.lib()
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"OT_API\s+[\w\s\*]*?\b(ot_\w+)\s*\(", txt)))
+
+
+def test_header_symbols_exported(L):
+    syms = declared_symbols()
+    assert len(syms) == 11
+    assert syms == sorted(ops.EXPORTS)
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_pyramid_bytes(L):
+    # levels 1..3 of 720x576: pitches 384/192/128 (64-byte rounding), 256-aligned sizes
+    want = 384 * 288 + 192 * 144 + 128 * 72
+    assert ops.pyramid_bytes(720, 576, 4) == want
+    assert ops.pyramid_bytes(720, 576, 1) == 0
+    for bad in [(0, 5, 2), (5, 0, 2), (5, 5, 0), (5, 5, 9), (20000, 5, 2)]:
+        assert ops.pyramid_bytes(*bad) == 0
+    assert L.ot_pyramid_bytes(64, 64, 2, 1) == 0  # flags must be 0
+
+
+def layout(L, W=720, H=576, pitch=720, levels=4, ws=FAKE + 4096, wsb=10**7, flags=0):
+    d = ops.OtPyr()
+    rc = L.ot_pyramid_layout(FAKE, W, H, pitch, levels, ws, wsb, flags, C.byref(d))
+    return rc, d
+
+
+def test_pyramid_layout(L):
+    rc, d = layout(L)
+    assert rc == 0 and d.levels == 4
+    assert list(d.w)[:4] == [720, 360, 180, 90] and list(d.h)[:4] == [576, 288, 144, 72]
+    assert d.level[0] == FAKE and d.level[1] == FAKE + 4096
+    assert d.level[2] == FAKE + 4096 + 384 * 288
+    assert all(d.level[l] % 256 == 0 for l in range(1, 4))
+    assert layout(L, pitch=719)[0] == ops_err("OT_E_INVAL")
+    assert layout(L, ws=FAKE + 4096 + 8)[0] == ops_err("OT_E_WORKSPACE")
+    assert layout(L, wsb=1000)[0] == ops_err("OT_E_WORKSPACE")
+    assert layout(L, levels=1, ws=0, wsb=0)[0] == 0
+    assert layout(L, flags=2)[0] == ops_err("OT_E_INVAL")
+
+
+def ops_err(name):
+    return {v: k for k, v in ops.ERRORS.items()}[name]
+
+
+def lk_call(L, P, Q, n=10, win=21, levels=4, iters=30, eps=0.01, pts=FAKE, out=FAKE, st=FAKE):
+    return L.ot_lk_track(C.byref(P), C.byref(Q), pts, n, win, levels, iters, eps, out, st, None,
+                         None)
+
+
+def test_lk_validation(L):
+    _, P = layout(L)
+    _, Q = layout(L)
+    E, S, U = ops_err("OT_E_INVAL"), ops_err("OT_E_SHAPE"), ops_err("OT_E_UNSUPPORTED")
+    assert lk_call(L, P, Q, win=20) == E          # even window
+    assert lk_call(L, P, Q, win=1) == E
+    assert lk_call(L, P, Q, win=65) == E
+    assert lk_call(L, P, Q, levels=5) == E        # more levels than the pyramids hold
+    assert lk_call(L, P, Q, levels=0) == E
+    assert lk_call(L, P, Q, iters=0) == E
+    assert lk_call(L, P, Q, eps=-1.0) == E
+    assert lk_call(L, P, Q, eps=float("nan")) == E
+    assert lk_call(L, P, Q, eps=float("inf")) == E
+    assert lk_call(L, P, Q, n=-1) == E
+    assert lk_call(L, P, Q, pts=None) == E        # null pointer with n > 0
+    assert lk_call(L, P, Q, out=None) == E
+    assert lk_call(L, P, Q, n=0, pts=None, out=None, st=None) == 0  # no-op
+    _, Q2 = layout(L, W=640)
+    assert lk_call(L, P, Q2) == S
+    bad = ops.OtPyr()
+    C.memmove(C.byref(bad), C.byref(P), C.sizeof(P))
+    bad.w[1] = 361                                # inconsistent descriptor
+    assert lk_call(L, bad, Q) == E
+    opts = ops.OtLkOpts(6.5, None, None, 17)      # margin above the maximum
+    assert L.ot_lk_track_ex(C.byref(P), C.byref(Q), FAKE, 10, 21, 4, 30, 0.01, FAKE, FAKE,
+                            None, C.byref(opts), None) == E
+    opts = ops.OtLkOpts(6.5, None, None, 16)      # win 63 at margin 16 exceeds 64 KiB of LDS
+    assert L.ot_lk_track_ex(C.byref(P), C.byref(Q), FAKE, 10, 63, 4, 30, 0.01, FAKE, FAKE,
+                            None, C.byref(opts), None) == U
+
+
+def test_box_validation(L):
+    E = ops_err("OT_E_INVAL")
+    assert L.ot_box_update(FAKE, -1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None) == E
+    assert L.ot_box_update(FAKE, 3, FAKE, FAKE, FAKE, FAKE, -5, FAKE, FAKE, None) == E
+    assert L.ot_box_update(None, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None) == E
+    assert L.ot_box_update(FAKE, 3, None, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None) == E
+    assert L.ot_box_update(None, 0, None, None, None, None, 5, None, None, None) == 0
+
+
+def make_cfg(**kw):
+    c = ops.OtBatchCfg(win=21, iters=30, eps=0.01, min_eig=6.5025, margin=0, lk_waves=0,
+                       chunk=1, max_jobs=4, max_points=5000, max_boxes=64, max_tiles=4096,
+                       max_levels=5)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def make_job(L, W, H, levels, n, m, base):
+    _, prev = layout(L, W=W, H=H, pitch=W, levels=levels)
+    j = ops.OtJob()
+    j.prev = prev
+    j.next_frame = base
+    j.next_pitch = W
+    j.next_ws = base + (1 << 24)
+    j.next_ws_bytes = ops.pyramid_bytes(W, H, levels)
+    j.levels = levels
+    j.pts, j.n, j.next_pts, j.status, j.err = base + 256, n, base + 512, base + 768, 0
+    j.boxes, j.m, j.box_id = base + 1024, m, base + 1280
+    j.out_boxes, j.out_count = base + 1536, base + 1792
+    return j
+
+
+def test_batch_pack_table(L):
+    cfg = make_cfg()
+    nb = L.ot_batch_table_bytes(C.byref(cfg))
+    assert nb > 0 and nb % 256 == 0
+    jobs = (ops.OtJob * 3)(make_job(L, 720, 576, 4, 100, 3, FAKE),
+                           make_job(L, 1920, 1080, 5, 0, 0, FAKE + (1 << 28)),
+                           make_job(L, 1280, 720, 4, 2500, 7, FAKE + (2 << 28)))
+    buf = np.zeros(nb, np.uint8)
+    nxt = (ops.OtPyr * 3)()
+    rc = L.ot_batch_pack(jobs, 3, C.byref(cfg), buf.ctypes.data, nb, nxt)
+    assert rc == 0
+    hdr = buf[:64].view(np.int32)
+    assert hdr[0] == 3 and hdr[1] == 2600 and hdr[2] == 10 and hdr[3] == 4
+    # tiles of level 1: ceil(360/64)*ceil(288/16) + ceil(960/64)*ceil(540/16) + ceil(640/64)*ceil(360/16)
+    assert hdr[4 + 1] == 6 * 18 + 15 * 34 + 10 * 23
+    assert nxt[1].levels == 5 and nxt[1].level[0] == FAKE + (1 << 28)
+    assert nxt[2].w[3] == 160
+    # capacity and validation errors leave nothing half-written
+    buf2 = np.full(nb, 7, np.uint8)
+    small = make_cfg(max_points=1000)
+    assert L.ot_batch_pack(jobs, 3, C.byref(small), buf2.ctypes.data, nb, None) == ops_err("OT_E_WORKSPACE")
+    assert np.all(buf2 == 7)
+    assert L.ot_batch_pack(jobs, 5, C.byref(make_cfg()), buf2.ctypes.data, nb, None) == ops_err("OT_E_WORKSPACE")
+    jobs[0].next_ws_bytes = 10
+    assert L.ot_batch_pack(jobs, 3, C.byref(cfg), buf2.ctypes.data, nb, None) == ops_err("OT_E_WORKSPACE")
+    assert np.all(buf2 == 7)
+    persistent = make_cfg(max_points=0, lk_waves=1024, chunk=4)
+    jobs[0].next_ws_bytes = ops.pyramid_bytes(720, 576, 4)
+    assert L.ot_batch_pack(jobs, 3, C.byref(persistent), buf.ctypes.data, nb, None) == 0
+
+
+def test_batch_run_validation(L):
+    cfg = make_cfg()
+    nb = L.ot_batch_table_bytes(C.byref(cfg))
+    buf = np.zeros(nb, np.uint8)
+    assert L.ot_batch_run(buf.ctypes.data, FAKE + 16, nb, C.byref(cfg), None) == ops_err("OT_E_WORKSPACE")
+    assert L.ot_batch_run(buf.ctypes.data, FAKE, nb - 256, C.byref(cfg), None) == ops_err("OT_E_WORKSPACE")
+    assert L.ot_batch_run(None, FAKE, nb, C.byref(cfg), None) == ops_err("OT_E_INVAL")
+    assert L.ot_batch_table_bytes(C.byref(make_cfg(max_jobs=0))) == 0
+
+
+def test_strerror(L):
+    for code in ops.ERRORS:
+        assert ops.strerror(code)
+    assert ops.version() >= 100
