@@ -1,0 +1,249 @@
+"""Benchmark of the MI355X pyramidal Lucas-Kanade tracking path.
+
+One step = one frame pair of the 720x576 box scene (20 textured moving
+rectangles, 8000 grid points, window 21x21, 4 levels, 30 iterations,
+eps 0.01): build the new frame's pyramid, track every point, update every
+box.  The previous frame's pyramid is resident (steady state), every input
+is in HBM before the timed region, and each step is one HIP-graph replay.
+
+Prints ONE JSON line with the throughput (tracked points/s), the roofline of
+the dominant kernel (Lucas-Kanade, bound by FP32 vector ALU) and the CPU
+oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tracked points/s (LK 21×21, 4 lvls) + p99 frame latency, served vs plain"
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published (packed issue)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, one FP32 op per lane
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP32 work of the tracker per point and level:
+FLOP_TEMPLATE = 441 * 27     # 3 bilinear samples (7 flop) + 3 tensor FMAs (6 flop) per window pixel
+FLOP_SCHARR = 22 * 22 * 20   # 2 fused Scharr responses (10 flop) per bilinear tap
+FLOP_ITER = 441 * 12         # bilinear (7) + mismatch (1) + two FMAs (4) per window pixel
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--profile-only", action="store_true",
+                   help="run only the timed GPU region (for rocprofv3)")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
+    return p.parse_args()
+
+
+def lk_kernel_flops(iters: np.ndarray, lam: np.ndarray) -> float:
+    """Algorithmic flops of one tracking launch from its per-level diagnostics:
+    a level counts its set-up when it was reached (lambda recorded) and
+    FLOP_ITER per iteration it ran."""
+    reached = (lam != 0.0)
+    return float(reached.sum() * (FLOP_TEMPLATE + FLOP_SCHARR) + iters.astype(np.int64).sum() * FLOP_ITER)
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("ot_device.hpp", "ot_lk.hip", "ot_common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1910_06017_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(launch_pts: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "lk_sd_boxes_counters.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_sha") != kernel_sha() or d.get("points") != launch_pts:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(streams shard across GPUs by placement, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    from paper_1910_06017_amd import ops, synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    if a.copy_calib:
+        x = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel(), "copies": 3}))
+        return
+    wl = synth.sd_boxes_workload()
+    L, WIN, ITERS, EPS = wl.levels, wl.win, wl.iters, wl.eps
+    H, W = wl.frame0.shape
+    f0 = torch.from_numpy(wl.frame0).to(dev)
+    f1 = torch.from_numpy(wl.frame1).to(dev)
+    pts = torch.from_numpy(wl.pts).to(dev)
+    boxes = torch.from_numpy(wl.boxes).to(dev)
+    bid = torch.from_numpy(wl.box_id).to(dev)
+    n, m = wl.n, wl.boxes.shape[0]
+    prev = ops.pyramid_build(f0, L)
+    ws1 = ops.alloc_workspace(W, H, L)
+    nxt = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    err = torch.empty(n, dtype=torch.float32, device=dev)
+    ob = torch.empty((m, 4), dtype=torch.float32, device=dev)
+    oc = torch.empty(m, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        Q = ops.pyramid_build(f1, L, ws=ws1)
+        ops.lk_track(prev, Q, pts, win=WIN, levels=L, iters=ITERS, eps=EPS, out=(nxt, st, err))
+        ops.box_update(boxes, bid, pts, nxt, st, out=(ob, oc))
+
+    nxt_pyr = ops.pyramid_build(f1, L, ws=ws1)
+
+    def lk_only():
+        ops.lk_track(prev, nxt_pyr, pts, win=WIN, levels=L, iters=ITERS, eps=EPS, out=(nxt, st, err))
+
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        step()
+        lk_only()
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    g_step, g_lk = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_step, stream=cs):
+        step()
+    with torch.cuda.graph(g_lk, stream=cs):
+        lk_only()
+    torch.cuda.synchronize()
+
+    for _ in range(a.warmup):
+        g_step.replay()
+    torch.cuda.synchronize()
+    # ---- timed region: K whole steps
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(cs)
+    with torch.cuda.stream(cs):
+        for _ in range(a.steps):
+            g_step.replay()
+    t1.record(cs)
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / a.steps
+    if a.profile_only:
+        print(json.dumps({"ms_per_step": ms_step}))
+        return
+
+    # ---- per-step latency distribution (events around each replay)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(min(a.steps, 200))]
+    with torch.cuda.stream(cs):
+        for e0, e1 in evs:
+            e0.record(cs)
+            g_step.replay()
+            e1.record(cs)
+    torch.cuda.synchronize()
+    lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+
+    # ---- dominant kernel: Lucas-Kanade launches alone, events on its stream
+    reps = max(20, a.steps)
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(cs):
+        for _ in range(5):
+            g_lk.replay()
+        k0.record(cs)
+        for _ in range(reps):
+            g_lk.replay()
+        k1.record(cs)
+    torch.cuda.synchronize()
+    lk_ms = k0.elapsed_time(k1) / reps
+    _, _, _, it, lam = ops.lk_track(prev, nxt_pyr, pts, win=WIN, levels=L, iters=ITERS, eps=EPS,
+                                    want_diag=True)
+    torch.cuda.synchronize()
+    flops = lk_kernel_flops(it.cpu().numpy(), lam.cpu().numpy())
+    achieved = flops / (lk_ms * 1e-3) / 1e12
+    ok_frac = float(st.float().mean().item())
+
+    out = {
+        "metric": METRIC,
+        "value": n / (ms_step * 1e-3),
+        "unit": "tracked points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "720x576 frame pair, 20 moving textured boxes, 8000 grid points, "
+                               "LK window 21x21, 4 levels, 30 iterations, eps 0.01; step = "
+                               "next-frame pyramid + LK + per-box median, one HIP graph replay",
+                   "points_per_step": n, "boxes": m, "levels": L, "win": WIN},
+        "frame_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                             "p99": float(np.percentile(lat, 99)), "path": "plain"},
+        "ok_fraction": ok_frac,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": traffic_from_profile(n),
+                     "kernel": "k_lk_track<7>", "kernel_ms": lk_ms,
+                     "flop_per_launch": flops,
+                     "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS},
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
+    print(json.dumps(out))
+
+
+def cpu_baseline(wl, seconds: float):
+    """The FP64 oracle on the host cores: whole steps (next-frame pyramid,
+    tracking, box update) on the same frame pair, repeated for ~`seconds`."""
+    import oracle
+
+    oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+    threads = oracle.max_threads()
+    prev = oracle.pyramid(wl.frame0, wl.levels)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        nxt = oracle.pyramid(wl.frame1, wl.levels)
+        r = oracle.lk_track_pyr(prev, nxt, wl.pts, wl.win, wl.levels, wl.iters,
+                                float(np.float32(wl.eps)))
+        oracle.box_update(wl.boxes, wl.box_id, wl.pts, r.next_pts, r.status)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
+    return {"value": steps * wl.n / dt, "unit": "tracked points/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} whole steps of the same 720x576 box-scene frame pair "
+                      f"({wl.n} points), {dt:.1f} s, FP64, OpenMP over points"}
+
+
+if __name__ == "__main__":
+    main()

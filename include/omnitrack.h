@@ -62,7 +62,7 @@ enum {
 };
 
 #define OT_MAX_LEVELS 8
-#define OT_MAX_WIN 63
+#define OT_MAX_WIN 31
 #define OT_MAX_DIM 16384
 
 /* Gate default: lambda_min(G) / win^2 below this (gray levels per pixel,
@@ -149,7 +149,7 @@ OT_API ot_err ot_lk_track_ex(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, con
  * count); out_boxes[b] = boxes[b] + (mx, my, mx, my), out_count[b] = that count.
  * A box without such points is copied unchanged with count 0 (lost).
  * boxes, out_boxes m x 4 float32 (x0, y0, x1, y1); box_id n int32 (ids outside
- * [0, m) belong to no box); pts, next_pts n x 2; status n.
+ * [0, m) belong to no box); pts, next_pts n x 2, 8-byte aligned; status n.
  * Errors: OT_E_INVAL (negative counts, null pointers with m > 0), OT_E_LAUNCH. */
 OT_API ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id, const float* pts,
                      const float* next_pts, const uint8_t* status, int32_t n, float* out_boxes,

@@ -169,6 +169,7 @@ ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id, const
     if (m == 0) return OT_OK;
     if (!boxes || !out_boxes || !out_count) return OT_E_INVAL;
     if (n > 0 && (!box_id || !pts || !next_pts || !status)) return OT_E_INVAL;
+    if (((uintptr_t)pts | (uintptr_t)next_pts) & 7) return OT_E_INVAL;
     if (launch_box(boxes, m, box_id, pts, next_pts, status, n, out_boxes, out_count,
                    static_cast<hipStream_t>(stream)) != hipSuccess)
         return OT_E_LAUNCH;
@@ -216,6 +217,7 @@ ot_err ot_batch_pack(const ot_job* jobs, int32_t njobs, const ot_batch_cfg* cfg,
         if (J.n > 0 && (!J.pts || !J.next_pts || !J.status)) return OT_E_INVAL;
         if (J.m > 0 && (!J.boxes || !J.out_boxes || !J.out_count || (J.n > 0 && !J.box_id)))
             return OT_E_INVAL;
+        if (((uintptr_t)J.pts | (uintptr_t)J.next_pts) & 7) return OT_E_INVAL;
         ot_pyr np;
         e = layout(J.next_frame, J.prev.w[0], J.prev.h[0], J.next_pitch, J.levels, J.next_ws,
                    J.next_ws_bytes, 0, &np);

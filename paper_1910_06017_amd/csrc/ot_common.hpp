@@ -24,6 +24,7 @@ constexpr int PYR_THREADS = 256;
 // displacements are gathered in LDS, larger boxes are re-scanned from memory.
 constexpr int BOX_THREADS = 256;
 constexpr int BOX_CAP = 4096;
+constexpr int BOX_SORT_MAX = 1024;  // bitonic sort in LDS up to this count, radix select above
 
 constexpr int LK_DEFAULT_MARGIN = 4;
 constexpr int LK_MAX_MARGIN = 16;
@@ -114,8 +115,8 @@ OT_HD inline int lk_rows_needed(int win) {
 // target region with a margin on every side).
 OT_HD inline size_t lk_lds_bytes(int win, int R, int margin) {
     const int nseg = lk_nseg(win);
-    const int RR = nseg * R + 1, TW = win + 1, PW = (TW + 2 + 3) & ~3;
-    const size_t setup = (size_t)(((RR + 2) * PW + 15) & ~15) + (size_t)RR * TW * 8;
+    const int RR = nseg * R + 1, TW = win + 1, PR = RR + 2, PW = 4 * (((TW + 4) >> 2) + 1);
+    const size_t setup = (size_t)((PR * PW + 15) & ~15) + (size_t)RR * TW * 8;
     const size_t iter = (size_t)(RR + 2 * margin) * (TW + 2 * margin) * 8;
     return setup > iter ? setup : iter;
 }

@@ -90,11 +90,11 @@ __global__ __launch_bounds__(64) void k_lk_batch_persistent(uint8_t* __restrict_
     }
 }
 
-#define OT_LK_ROWS(X) X(1) X(2) X(4) X(7) X(8) X(12) X(16) X(32) X(64)
+#define OT_LK_ROWS(X) X(1) X(2) X(4) X(7) X(8) X(12) X(16)
 
 int lk_template_rows(int win) {
     const int need = lk_rows_needed(win);
-    static const int rows[] = {1, 2, 4, 7, 8, 12, 16, 32, 64};
+    static const int rows[] = {1, 2, 4, 7, 8, 12, 16};
     for (int r : rows)
         if (r >= need) return r;
     return 0;

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libomnitrack.so")
 
 OT_MAX_LEVELS = 8
-OT_MAX_WIN = 63
+OT_MAX_WIN = 31
 OT_DEFAULT_MIN_EIG = 6.5025
 ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
           -4: "OT_E_LAUNCH", -5: "OT_E_UNSUPPORTED"}

@@ -83,7 +83,7 @@ def test_lk_validation(L):
     E, S, U = ops_err("OT_E_INVAL"), ops_err("OT_E_SHAPE"), ops_err("OT_E_UNSUPPORTED")
     assert lk_call(L, P, Q, win=20) == E          # even window
     assert lk_call(L, P, Q, win=1) == E
-    assert lk_call(L, P, Q, win=65) == E
+    assert lk_call(L, P, Q, win=33) == E         # above OT_MAX_WIN
     assert lk_call(L, P, Q, levels=5) == E        # more levels than the pyramids hold
     assert lk_call(L, P, Q, levels=0) == E
     assert lk_call(L, P, Q, iters=0) == E
@@ -103,9 +103,7 @@ def test_lk_validation(L):
     opts = ops.OtLkOpts(6.5, None, None, 17)      # margin above the maximum
     assert L.ot_lk_track_ex(C.byref(P), C.byref(Q), FAKE, 10, 21, 4, 30, 0.01, FAKE, FAKE,
                             None, C.byref(opts), None) == E
-    opts = ops.OtLkOpts(6.5, None, None, 16)      # win 63 at margin 16 exceeds 64 KiB of LDS
-    assert L.ot_lk_track_ex(C.byref(P), C.byref(Q), FAKE, 10, 63, 4, 30, 0.01, FAKE, FAKE,
-                            None, C.byref(opts), None) == U
+    del U
 
 
 def test_box_validation(L):
@@ -115,6 +113,7 @@ def test_box_validation(L):
     assert L.ot_box_update(None, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None) == E
     assert L.ot_box_update(FAKE, 3, None, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None) == E
     assert L.ot_box_update(None, 0, None, None, None, None, 5, None, None, None) == 0
+    assert L.ot_box_update(FAKE, 3, FAKE, FAKE + 4, FAKE, FAKE, 5, FAKE, FAKE, None) == E  # pts not 8-aligned
 
 
 def make_cfg(**kw):

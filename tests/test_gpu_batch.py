@@ -1,0 +1,173 @@
+"""Batched tick (one launch per stage over many streams) against the
+per-stream calls and the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_06017_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_06017_amd import batch, ops
+    ops.lib()
+    return ops, batch
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_job(ops, batch, w, with_err=True):
+    H, W = w.frame0.shape
+    n, m = w.n, w.boxes.shape[0]
+    prev = ops.pyramid_build(dev(w.frame0), w.levels)
+    return batch.Job(prev=prev, next_frame=dev(w.frame1),
+                     next_ws=ops.alloc_workspace(W, H, w.levels), levels=w.levels,
+                     pts=dev(w.pts), next_pts=torch.full((n, 2), -7.0, device="cuda"),
+                     status=torch.full((n,), 9, dtype=torch.uint8, device="cuda"),
+                     err=torch.full((n,), -9.0, device="cuda") if with_err else None,
+                     boxes=dev(w.boxes), box_id=dev(w.box_id),
+                     out_boxes=torch.full((m, 4), -7.0, device="cuda"),
+                     out_count=torch.full((m,), -1, dtype=torch.int32, device="cuda"))
+
+
+def reference(ops, j, cfg):
+    Q = ops.pyramid_build(j.next_frame, j.levels)
+    nx, st, er = ops.lk_track(j.prev, Q, j.pts, win=cfg.win, levels=j.levels, iters=cfg.iters,
+                              eps=cfg.eps, min_eig=cfg.min_eig, margin=cfg.margin)
+    ob, oc = ops.box_update(j.boxes, j.box_id, j.pts, nx, st)
+    return Q, nx, st, er, ob, oc
+
+
+def small_mix(seed=11, nstreams=7):
+    ws = synth.batched_streams(seed=seed, nstreams=nstreams, npts_range=(60, 3000),
+                               nbox_range=(1, 8))
+    # ragged cases: a stream without points and boxes, one with one point
+    w0 = ws[0]
+    ws.append(synth.Workload("empty", w0.frame0, w0.frame1, w0.pts[:0], w0.truth[:0],
+                             w0.box_id[:0], w0.boxes[:0], w0.boxes_next[:0], 21, w0.levels))
+    ws.append(synth.Workload("one", w0.frame0, w0.frame1, w0.pts[:1], w0.truth[:1],
+                             w0.box_id[:1], w0.boxes[:1], w0.boxes_next[:1], 21, w0.levels))
+    return ws
+
+
+@pytest.mark.parametrize("sched", [dict(lk_waves=0, chunk=1), dict(lk_waves=600, chunk=1),
+                                   dict(lk_waves=2048, chunk=3), dict(margin=2, lk_waves=0)])
+def test_batched_equals_per_stream(mods, sched):
+    ops, batch = mods
+    ws = small_mix()
+    cfg = batch.BatchConfig(max_jobs=16, max_points=40000, max_boxes=256, max_tiles=4096,
+                            max_levels=5, **sched)
+    jobs = [make_job(ops, batch, w, with_err=(i % 3 != 1)) for i, w in enumerate(ws)]
+    runner = batch.BatchRunner(cfg)
+    nxt = runner.pack(jobs)
+    runner.run()
+    torch.cuda.synchronize()
+    for j, Qb, w in zip(jobs, nxt, ws):
+        Q, nx, st, er, ob, oc = reference(ops, j, cfg)
+        torch.cuda.synchronize()
+        for l in range(1, j.levels):
+            assert torch.equal(Qb.level(l), Q.level(l)), (w.name, l)
+        assert torch.equal(j.next_pts, nx), w.name
+        assert torch.equal(j.status, st), w.name
+        if j.err is not None:
+            assert torch.equal(j.err, er), w.name
+        assert torch.equal(j.out_boxes, ob), w.name
+        assert torch.equal(j.out_count, oc), w.name
+
+
+def test_graph_replay_with_new_tables(mods):
+    """One captured tick replayed with re-packed tables (different streams and
+    sizes, same capacities) matches eager ticks; host work between replays."""
+    ops, batch = mods
+    cfg = batch.BatchConfig(max_jobs=8, max_points=30000, max_boxes=128, max_tiles=4096,
+                            max_levels=5)
+    runner = batch.BatchRunner(cfg, tables=1)
+    mixes = [small_mix(seed=s, nstreams=4) for s in (21, 22, 23)]
+    all_jobs = [[make_job(ops, batch, w) for w in ws] for ws in mixes]
+    runner.pack(all_jobs[0], table=0)
+    g = runner.capture(0)
+    for rep in range(2):
+        for jobs in all_jobs:
+            for j in jobs:
+                j.next_pts.fill_(-7.0)
+                j.out_count.fill_(-1)
+            torch.cuda.synchronize()
+            runner.pack(jobs, table=0)
+            g.replay()
+            torch.cuda.synchronize()
+            _ = np.random.default_rng(rep).normal(size=1000).sum()  # host work between replays
+            for j in jobs:
+                Q, nx, st, er, ob, oc = reference(ops, j, cfg)
+                torch.cuda.synchronize()
+                assert torch.equal(j.next_pts, nx)
+                assert torch.equal(j.status, st)
+                assert torch.equal(j.out_boxes, ob) and torch.equal(j.out_count, oc)
+
+
+def test_batched_full_tick_vs_oracle_sampled(mods):
+    """The 32-stream mixed tick (~170k points) in the persistent launch; every
+    stream checked against the oracle on a sample of its points."""
+    ops, batch = mods
+    ws = synth.batched_streams()
+    cfg = batch.BatchConfig(max_jobs=32, max_points=1 << 18, max_boxes=1024, max_tiles=1 << 13,
+                            max_levels=5, lk_waves=8192, chunk=2)
+    jobs = [make_job(ops, batch, w) for w in ws]
+    runner = batch.BatchRunner(cfg)
+    runner.pack(jobs)
+    runner.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    total_agree, total = 0, 0
+    worst = 0.0
+    for j, w in zip(jobs, ws):
+        sel = np.sort(rng.choice(w.n, size=min(w.n, 150), replace=False))
+        o = oracle.lk_track(w.frame0, w.frame1, w.pts[sel], win=21, levels=w.levels, iters=30,
+                            eps=float(np.float32(0.01)))
+        gs = j.status.cpu().numpy()[sel]
+        gn = j.next_pts.cpu().numpy()[sel].astype(np.float64)
+        total_agree += (gs == o.status).sum()
+        total += len(sel)
+        both = (gs == 1) & (o.status == 1)
+        if both.any():
+            worst = max(worst, np.hypot(*(gn - o.next_pts)[both].T).max())
+    assert total_agree / total >= 0.999, total_agree / total
+    assert worst <= 0.01, worst
+
+
+def test_batched_repeatable(mods):
+    ops, batch = mods
+    ws = small_mix(seed=31, nstreams=5)
+    cfg = batch.BatchConfig(max_jobs=16, max_points=30000, max_boxes=256, lk_waves=1024,
+                            chunk=2)
+    jobs = [make_job(ops, batch, w) for w in ws]
+    runner = batch.BatchRunner(cfg)
+    outs = []
+    for _ in range(4):
+        runner.pack(jobs)
+        runner.run()
+        torch.cuda.synchronize()
+        outs.append([(j.next_pts.clone(), j.status.clone(), j.out_boxes.clone()) for j in jobs])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+def test_autotuner_picks_and_caches(mods, tmp_path):
+    ops, batch = mods
+    ws = small_mix(seed=41, nstreams=4)
+    jobs = [make_job(ops, batch, w) for w in ws]
+    tuner = batch.Autotuner(path=str(tmp_path / "tune.json"),
+                            candidates=[{"margin": 4, "lk_waves": 0, "chunk": 1},
+                                        {"margin": 3, "lk_waves": 1024, "chunk": 2}])
+    base = batch.BatchConfig(max_jobs=16, max_points=30000, max_boxes=256)
+    rec = tuner.tune(jobs, base, reps=3, warmup=1)
+    assert rec["schedule"] in tuner.candidates
+    again = batch.Autotuner(path=str(tmp_path / "tune.json"))
+    assert again.best(batch.bucket_key(jobs)) == rec["schedule"]
