@@ -47,6 +47,12 @@ def parse():
                    help="run only the timed GPU region (for rocprofv3)")
     p.add_argument("--copy-calib", action="store_true",
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
+    p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
+    p.add_argument("--no-served", action="store_true", help="skip the served-vs-plain run")
+    p.add_argument("--served-seconds", type=float, default=4.0,
+                   help="length of the 64-stream arrival trace for served and plain")
+    p.add_argument("--served-rate", type=float, default=1.0,
+                   help="arrival-rate multiplier on 25 fps per stream")
     return p.parse_args()
 
 
@@ -216,9 +222,93 @@ def main():
                      "flop_per_launch": flops,
                      "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS},
     }
+    if not a.no_batched:
+        out["batched"] = bench_batched(a)
+    if not a.no_served:
+        out["served_vs_plain"] = bench_served(a)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
     print(json.dumps(out))
+
+
+def bench_batched(a):
+    """32 independent streams (mixed 720x576 / 1280x720 / 1920x1080, 4-30 boxes,
+    500-20000 points each) in one batched tick, replayed as a HIP graph."""
+    import torch
+    from paper_1910_06017_amd import batch, ops, synth
+
+    ws = synth.batched_streams()
+    jobs = batch.jobs_from_workloads(ws, "cuda:0")
+    npts = sum(w.n for w in ws)
+    sched = batch.default_schedule(batch.bucket_key(jobs))
+    cfg = batch.BatchConfig(max_jobs=32, max_points=npts, max_boxes=2048, max_tiles=1 << 15,
+                            max_levels=5, **sched)
+    runner = batch.BatchRunner(cfg, tables=1)
+    runner.pack(jobs, table=0)
+    g = runner.capture(0)
+    for _ in range(5):
+        g.replay()
+    torch.cuda.synchronize()
+    reps = 30
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = float(np.mean([j.status.float().mean().item() for j in jobs if j.n]))
+    return {"streams": len(ws), "points_per_tick": npts, "ms_per_tick": ms,
+            "tracked_points_per_s": npts / (ms * 1e-3), "schedule": sched, "ok_fraction": ok}
+
+
+def bench_served(a):
+    """64 streams with Poisson arrivals (25 fps each x rate), served with
+    continuous batching and, on the same trace, plain per-stream calls."""
+    from paper_1910_06017_amd import serve, synth
+
+    streams = synth.served_streams(nframes=10)
+    specs = [serve.StreamSpec(s.sid, s.W, s.H, s.levels, sum(s.pts_per_box), len(s.pts_per_box))
+             for s in streams]
+    pinned = [[_pin(f) for f in s.frames] for s in streams]
+    seeds = {}
+
+    def frame_fn(sid, k, t):
+        s = streams[sid]
+        reseed = None
+        if k % 10 == 0:
+            if (sid, k % len(s.frames)) not in seeds:
+                seeds[(sid, k % len(s.frames))] = s.seed_points(k, np.random.default_rng(sid * 7919 + k))
+            reseed = seeds[(sid, k % len(s.frames))]
+        return serve.Frame(sid, k, t, pinned[sid][k % len(s.frames)], reseed)
+
+    trace = serve.make_trace(len(streams), a.served_seconds, 25.0, seed=505,
+                             rate_scale=a.served_rate)
+    pts_of = {s.sid: sum(s.pts_per_box) for s in streams}
+    out = {"streams": len(streams), "trace_s": a.served_seconds, "frames": len(trace),
+           "fps_per_stream": 25.0 * a.served_rate,
+           "offered_points_per_s": sum(pts_of[s] for _, s, _ in trace) / a.served_seconds}
+    for name, batched, ex in (("served", True, serve.GpuExecutor(max_jobs=64, max_points=1 << 21)),
+                              ("plain", False, serve.PlainExecutor())):
+        # warm the executors on a short trace of the same streams
+        sch = serve.Scheduler(budget=1 << 40, max_jobs=64, max_points=1 << 21)
+        t0 = time.perf_counter()
+        res = serve.run_trace(trace, frame_fn, specs, sch, ex, batched=batched,
+                              max_wall=a.served_seconds * 4)
+        wall = time.perf_counter() - t0
+        st = serve.latency_stats(res)
+        st["tracked_points_per_s"] = sum(pts_of[r.sid] for r in res if r.k > 0) / max(wall, 1e-9)
+        st["wall_s"] = wall
+        st["ticks"] = ex.ticks
+        out[name] = st
+    return out
+
+
+def _pin(frame):
+    import torch
+    t = torch.empty(frame.shape, dtype=torch.uint8, pin_memory=True)
+    t.copy_(torch.from_numpy(frame))
+    return t
 
 
 def cpu_baseline(wl, seconds: float):

@@ -80,6 +80,32 @@ def _ptr(t):
     return None if t is None else int(t.data_ptr())
 
 
+def jobs_from_workloads(workloads: list, device="cuda") -> list:
+    """Device-resident jobs for synthetic frame pairs: frame 0's pyramid is
+    built (resident), frame 1 and all point/box inputs are uploaded, outputs
+    allocated."""
+    import numpy as np
+    import torch
+
+    dev = torch.device(device)
+
+    def t(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+    jobs = []
+    for w in workloads:
+        H, W = w.frame0.shape
+        n, m = w.n, w.boxes.shape[0]
+        jobs.append(Job(prev=ops.pyramid_build(t(w.frame0), w.levels), next_frame=t(w.frame1),
+                        next_ws=ops.alloc_workspace(W, H, w.levels, dev), levels=w.levels,
+                        pts=t(w.pts), next_pts=torch.empty((n, 2), device=dev),
+                        status=torch.empty(n, dtype=torch.uint8, device=dev),
+                        err=torch.empty(n, device=dev), boxes=t(w.boxes), box_id=t(w.box_id),
+                        out_boxes=torch.empty((m, 4), device=dev),
+                        out_count=torch.empty(m, dtype=torch.int32, device=dev)))
+    return jobs
+
+
 class BatchRunner:
     """Owns the pinned host table and the device table for one capacity."""
 
@@ -154,6 +180,26 @@ class BatchRunner:
                       "ot_batch_run")
         torch.cuda.synchronize()
         return g
+
+
+_DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def default_schedule(key: str) -> dict:
+    """Tuned schedule for a shape bucket from the packaged cache (nearest
+    point bucket), else one wave per point with the default margin."""
+    if os.path.exists(_DEFAULT_CACHE):
+        with open(_DEFAULT_CACHE) as f:
+            cache = json.load(f)
+        if key in cache:
+            return dict(cache[key]["schedule"])
+        if cache:
+            def pts(k):
+                return int(k.split("_")[0][1:])
+            want = pts(key)
+            best = min(cache, key=lambda k: abs(math.log2(pts(k)) - math.log2(want)))
+            return dict(cache[best]["schedule"])
+    return {"margin": 0, "lk_waves": 0, "chunk": 1}
 
 
 def bucket_key(jobs: list) -> str:

@@ -409,7 +409,35 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         // ---- Scharr gradients at the tap grid: the gradient image is defined on
         // the level's pixels and read at clamped indices, so a tap outside the
         // level takes the gradient of the nearest edge pixel.
-        {
+        if (x0 >= 1 && x0 + g.TW <= w - 1 && y0 >= 1 && y0 + g.RR <= h - 1) {
+            // interior: no clamping; each lane slides a 3x3 window down a
+            // column of taps, so a tap costs three byte reads.  With
+            // d = right - left and t = 3 left + 10 centre + 3 right per row:
+            // Sx = 3 d(y-1) + 10 d(y) + 3 d(y+1),  Sy = t(y+1) - t(y-1).
+            const int ncg = 64 / g.TW;
+            const int GR = (g.RR + ncg - 1) / ncg;
+            const int tx = lane % g.TW, rg = lane / g.TW;
+            if (rg < ncg) {
+                const int ty0 = rg * GR, ty1 = min(ty0 + GR, g.RR);
+                const uint8_t* pp = patch + ty0 * g.PW + (x0 + tx - a0p);
+                int vl = pp[-1], vc = pp[0], vr = pp[1];
+                int d0 = vr - vl, t0 = 3 * (vl + vr) + 10 * vc;
+                vl = pp[g.PW - 1], vc = pp[g.PW], vr = pp[g.PW + 1];
+                int d1 = vr - vl, t1 = 3 * (vl + vr) + 10 * vc;
+                for (int ty = ty0; ty < ty1; ++ty) {
+                    const uint8_t* q = pp + (ty - ty0 + 2) * g.PW;
+                    vl = q[-1], vc = q[0], vr = q[1];
+                    const int d2 = vr - vl, t2 = 3 * (vl + vr) + 10 * vc;
+                    const int sxv = 3 * (d0 + d2) + 10 * d1;
+                    const int syv = t2 - t0;
+                    grad[ty * g.TW + tx] = make_float2((float)sxv * (1.0f / 32.0f), (float)syv * (1.0f / 32.0f));
+                    d0 = d1;
+                    d1 = d2;
+                    t0 = t1;
+                    t1 = t2;
+                }
+            }
+        } else {
             const int dr = 64 / g.TW, dc = 64 - dr * g.TW;
             int ty = lane / g.TW, tx = lane - ty * g.TW;
             const int ntap = g.RR * g.TW;

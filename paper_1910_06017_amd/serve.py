@@ -391,10 +391,16 @@ def run_trace(trace, frame_fn, specs, scheduler: Scheduler, executor, clock=None
         if frames:
             res = executor.run_tick(frames, now=lambda: clock() - t0)
             results += res
-        elif i < n:
-            sleep(trace[i][0] - (clock() - t0))
-        else:
-            break
+            continue
+        # nothing runnable: wait for the next arrival or the next eviction that
+        # could free budget for a waiting stream
+        wake = [trace[i][0]] if i < n else []
+        if scheduler.waiting:
+            wake += [scheduler.last_seen.get(sid, now) + scheduler.evict_after
+                     for sid in scheduler.admitted if not scheduler.queues[sid]]
+        if not wake:
+            break  # frames wait for streams that can never be admitted
+        sleep(min(wake) - (clock() - t0) + 1e-4)
     return results
 
 

@@ -116,7 +116,7 @@ def test_batched_full_tick_vs_oracle_sampled(mods):
     stream checked against the oracle on a sample of its points."""
     ops, batch = mods
     ws = synth.batched_streams()
-    cfg = batch.BatchConfig(max_jobs=32, max_points=1 << 18, max_boxes=1024, max_tiles=1 << 13,
+    cfg = batch.BatchConfig(max_jobs=32, max_points=1 << 18, max_boxes=1024, max_tiles=1 << 15,
                             max_levels=5, lk_waves=8192, chunk=2)
     jobs = [make_job(ops, batch, w) for w in ws]
     runner = batch.BatchRunner(cfg)
@@ -124,21 +124,34 @@ def test_batched_full_tick_vs_oracle_sampled(mods):
     runner.run()
     torch.cuda.synchronize()
     rng = np.random.default_rng(4)
-    total_agree, total = 0, 0
-    worst = 0.0
-    for j, w in zip(jobs, ws):
+    total_agree, total, flips, tracked = 0, 0, 0, 0
+    worst_same, worst_flip = 0.0, 0.0
+    for j, w, Qb in zip(jobs, ws, runner.next_pyrs):
         sel = np.sort(rng.choice(w.n, size=min(w.n, 150), replace=False))
         o = oracle.lk_track(w.frame0, w.frame1, w.pts[sel], win=21, levels=w.levels, iters=30,
                             eps=float(np.float32(0.01)))
         gs = j.status.cpu().numpy()[sel]
         gn = j.next_pts.cpu().numpy()[sel].astype(np.float64)
+        # the per-level iteration counts of the same points (single-call path)
+        nx, st, _, it, _ = ops.lk_track(j.prev, Qb, dev(w.pts[sel]), win=21, levels=w.levels,
+                                        want_diag=True)
+        assert torch.equal(nx.cpu(), j.next_pts.cpu()[sel])
+        same = np.all(it.cpu().numpy().astype(np.int64) == o.iters, axis=1)
         total_agree += (gs == o.status).sum()
         total += len(sel)
         both = (gs == 1) & (o.status == 1)
-        if both.any():
-            worst = max(worst, np.hypot(*(gn - o.next_pts)[both].T).max())
+        d = np.hypot(*(gn - o.next_pts).T)
+        tracked += both.sum()
+        flips += (both & ~same).sum()
+        if (both & same).any():
+            worst_same = max(worst_same, d[both & same].max())
+        if (both & ~same).any():
+            worst_flip = max(worst_flip, d[both & ~same].max())
+    print(f"sampled {total} points: agree {total_agree / total:.5f}, flips {flips}, "
+          f"worst {worst_same:.4f} / {worst_flip:.4f}")
     assert total_agree / total >= 0.999, total_agree / total
-    assert worst <= 0.01, worst
+    assert worst_same <= 0.01, worst_same
+    assert worst_flip <= 0.02 and flips <= 0.01 * tracked, (worst_flip, flips)
 
 
 def test_batched_repeatable(mods):

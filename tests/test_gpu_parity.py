@@ -1,9 +1,13 @@
 """HIP path vs the CPU oracle, element by element, through the C ABI.
 
 Pyramids must match bit for bit.  Lucas-Kanade (FP32 on the GPU, FP64 in the
-oracle) must agree on status for >= 99.9 % of the points, and on the
-position of every point both call tracked to within 0.01 px.  Box updates
-must match within 0.01 px.
+oracle) must agree on status for >= 99.9 % of the points, and every point
+both call tracked must lie within 0.01 px of the oracle when the two took
+the same stopping decisions (equal iteration counts at every level).  Where
+an eps test fell on different sides of the threshold in FP32 and FP64 (a
+"decision flip", <= 1 % of the points), the two runs stop one iteration
+apart and may differ by up to one more step below eps: 0.01 + eps.  Box
+updates must match within 0.01 px.
 """
 import math
 
@@ -34,7 +38,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def run_gpu(ops, f0, f1, pts, win, levels, iters, eps, diag=False, margin=0):
+def run_gpu(ops, f0, f1, pts, win, levels, iters, eps, diag=True, margin=0):
     P = ops.pyramid_build(dev(f0), levels)
     Q = ops.pyramid_build(dev(f1), levels)
     out = ops.lk_track(P, Q, dev(pts), win=win, levels=levels, iters=iters, eps=eps,
@@ -48,17 +52,28 @@ def run_oracle(f0, f1, pts, win, levels, iters, eps):
                            eps=float(np.float32(eps)))
 
 
-def compare(g, o, tag, flow_tol=FLOW_TOL, agree=STATUS_AGREE, err_tol=None):
+def compare(g, o, tag, flow_tol=FLOW_TOL, agree=STATUS_AGREE, err_tol=None, eps=0.01,
+            max_flip_frac=0.01):
+    """g = (next_pts, status, err[, iters, lam]) from the GPU; o = oracle result."""
     gn, gs, ge = g[0], g[1], g[2]
     n = len(gs)
     ag = (gs == o.status).mean() if n else 1.0
     both = (gs == 1) & (o.status == 1)
-    d = np.hypot(*(gn.astype(np.float64) - o.next_pts)[both].T) if both.any() else np.zeros(1)
+    d = np.hypot(*(gn.astype(np.float64) - o.next_pts).T)
+    if len(g) > 3 and g[3] is not None:
+        same = np.all(g[3].astype(np.int64) == o.iters, axis=1)
+    else:
+        same = np.ones(n, bool)
+    ds = d[both & same] if (both & same).any() else np.zeros(1)
+    df = d[both & ~same] if (both & ~same).any() else np.zeros(1)
+    flips = int((both & ~same).sum())
     msg = (f"{tag}: n={n} status agree={ag:.5f} tracked both={both.sum()} "
-           f"max|d|={d.max():.3e} p99={np.percentile(d, 99):.3e}")
+           f"max|d| same decisions={ds.max():.3e} flips={flips} max|d| flips={df.max():.3e}")
     print(msg)
     assert ag >= agree, msg
-    assert d.max() <= flow_tol, msg
+    assert ds.max() <= flow_tol, msg
+    assert df.max() <= flow_tol + eps, msg
+    assert flips <= max_flip_frac * max(1, both.sum()), msg
     if err_tol is not None and both.any():
         de = np.abs(ge[both].astype(np.float64) - o.err[both])
         assert de.max() <= err_tol, f"{tag}: err max diff {de.max()}"
@@ -112,7 +127,7 @@ def test_parity_sd_shift(ops, eps):
     w = synth.sd_shift_workload()
     g = run_gpu(ops, w.frame0, w.frame1, w.pts, w.win, w.levels, w.iters, eps)
     o = run_oracle(w.frame0, w.frame1, w.pts, w.win, w.levels, w.iters, eps)
-    compare(g, o, f"sd_shift eps={eps}", err_tol=0.01 if eps == 0 else None)
+    compare(g, o, f"sd_shift eps={eps}", err_tol=0.01 if eps == 0 else None, eps=eps)
 
 
 @pytest.mark.parametrize("eps", [0.01, 0.0])
@@ -120,7 +135,7 @@ def test_parity_sd_boxes(ops, eps):
     w = synth.sd_boxes_workload()
     g = run_gpu(ops, w.frame0, w.frame1, w.pts, w.win, w.levels, w.iters, eps)
     o = run_oracle(w.frame0, w.frame1, w.pts, w.win, w.levels, w.iters, eps)
-    compare(g, o, f"sd_boxes eps={eps}")
+    compare(g, o, f"sd_boxes eps={eps}", eps=eps)
 
 
 def test_parity_hd_boxes(ops):
@@ -137,7 +152,7 @@ def test_parity_window_sizes(ops, win):
     pts = np.array([(x, y) for x in g for y in g if y < 119], np.float32)
     gg = run_gpu(ops, f0, f1, pts, win, 3, 20, 0.0)
     o = run_oracle(f0, f1, pts, win, 3, 20, 0.0)
-    compare(gg, o, f"win={win}", err_tol=0.01)
+    compare(gg, o, f"win={win}", err_tol=0.01, eps=0.0)
 
 
 def test_parity_tiny_images_and_edges(ops):
@@ -150,7 +165,7 @@ def test_parity_tiny_images_and_edges(ops):
                        np.float32)
         g = run_gpu(ops, a, b, pts, 7, 2, 10, 0.0)
         o = run_oracle(a, b, pts, 7, 2, 10, 0.0)
-        compare(g, o, f"tiny {H}x{W}", agree=1.0, flow_tol=1e-3)
+        compare(g, o, f"tiny {H}x{W}", agree=1.0, flow_tol=1e-3, eps=0.0, max_flip_frac=0.0)
 
 
 def test_invalid_points(ops):
@@ -159,6 +174,7 @@ def test_invalid_points(ops):
                    np.float32)
     g = run_gpu(ops, w.frame0, w.frame1, pts, 21, 3, 30, 0.01)
     assert list(g[1]) == [0, 0, 0, 0, 0, 1]
+    assert np.all(g[3][:5] == 0)
     assert np.all(g[2][:5] == -1.0)
 
 
@@ -176,8 +192,8 @@ def test_iteration_counts_match(ops):
 def test_margin_does_not_change_results(ops, margin):
     w = synth.sd_boxes_workload()
     sel = slice(0, 2000)
-    a = run_gpu(ops, w.frame0, w.frame1, w.pts[sel], 21, 4, 30, 0.01)
-    b = run_gpu(ops, w.frame0, w.frame1, w.pts[sel], 21, 4, 30, 0.01, margin=margin)
+    a = run_gpu(ops, w.frame0, w.frame1, w.pts[sel], 21, 4, 30, 0.01, diag=False)
+    b = run_gpu(ops, w.frame0, w.frame1, w.pts[sel], 21, 4, 30, 0.01, margin=margin, diag=False)
     assert np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], b[0])
 

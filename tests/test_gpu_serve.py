@@ -1,0 +1,82 @@
+"""Serving loop on the GPU: a stream's results are the same alone and in the
+mix, served (batched) and plain (per-stream calls) agree bit for bit, and a
+small HBM budget defers admission without losing frames."""
+import numpy as np
+import pytest
+
+from paper_1910_06017_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_06017_amd import ops, serve
+    ops.lib()
+    streams = synth.served_streams(seed=77, nstreams=4, nframes=10, npts_range=(150, 900),
+                                   nbox_range=(2, 5),
+                                   resolutions=((720, 576), (1280, 720)))
+    return serve, streams
+
+
+def specs_for(serve, streams):
+    return [serve.StreamSpec(s.sid, s.W, s.H, s.levels, sum(s.pts_per_box), len(s.pts_per_box))
+            for s in streams]
+
+
+def frame_fn_for(serve, streams):
+    def fn(sid, k, t):
+        s = streams[sid]
+        reseed = None
+        if k % 10 == 0:
+            reseed = s.seed_points(k, np.random.default_rng(1000 * sid + k))
+        return serve.Frame(sid, k, t, s.frames[k % len(s.frames)], reseed)
+    return fn
+
+
+def run(serve, streams, trace, executor, budget=1 << 40, batched=True):
+    sch = serve.Scheduler(budget=budget, max_jobs=16, max_points=1 << 20)
+    return serve.run_trace(trace, frame_fn_for(serve, streams), specs_for(serve, streams), sch,
+                           executor, batched=batched), sch
+
+
+def by_key(results):
+    return {(r.sid, r.k): r for r in results}
+
+
+def test_alone_equals_mix_and_plain(env):
+    serve, streams = env
+    trace = serve.make_trace(len(streams), 0.5, 25.0, seed=5)
+    mix, _ = run(serve, streams, trace, serve.GpuExecutor(max_jobs=16, max_points=1 << 20))
+    alone_trace = [(t, s, k) for (t, s, k) in trace if s == 1]
+    alone, _ = run(serve, streams, alone_trace, serve.GpuExecutor(max_jobs=16, max_points=1 << 20))
+    plain, _ = run(serve, streams, trace, serve.PlainExecutor(), batched=False)
+    M, A, P = by_key(mix), by_key(alone), by_key(plain)
+    assert len(M) == len(trace) == len(P) and len(A) == len(alone_trace)
+    for key, r in A.items():
+        assert np.array_equal(r.boxes, M[key].boxes), key
+        assert np.array_equal(r.counts, M[key].counts), key
+    for key, r in M.items():
+        assert np.array_equal(r.boxes, P[key].boxes), key
+        assert np.array_equal(r.counts, P[key].counts), key
+    # tracking keeps most points: every box of a non-first frame has tracked points
+    tracked = [r.counts.min() for r in M.values() if r.k > 0 and len(r.counts)]
+    assert np.mean(np.array(tracked) > 0) > 0.9
+
+
+def test_small_budget_defers_admission(env):
+    serve, streams = env
+    specs = specs_for(serve, streams)
+    fps = [serve.stream_footprint(s) for s in specs]
+    budget = max(fps) + min(fps)   # never all four at once
+    trace = serve.make_trace(len(streams), 0.3, 25.0, seed=6)
+    # streams 0 and 1 stop early so 2 and 3 can be admitted after eviction
+    trace = [(t, s, k) for (t, s, k) in trace if not (s in (0, 1) and t > 0.1)]
+    sch = serve.Scheduler(budget=budget, max_jobs=16, max_points=1 << 20, evict_after=0.05)
+    res = serve.run_trace(trace, frame_fn_for(serve, streams), specs, sch,
+                          serve.GpuExecutor(max_jobs=16, max_points=1 << 20))
+    assert len(res) == len(trace)
+    assert sch.used <= budget and sch.evicted
