@@ -7,6 +7,12 @@
 
 #include "ot_common.hpp"
 
+// Clamped-byte staging near level edges keeps this many loads per lane in
+// flight (registers vs latency).
+#ifndef OT_STAGE_BATCH
+#define OT_STAGE_BATCH 4
+#endif
+
 namespace ot {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
@@ -257,11 +263,11 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
         const int dr = 64 / SC, dc = 64 - dr * SC;
         int r = lane / SC, c = lane - r * SC;
         const int nk = (SR * SC + 63) >> 6;
-        for (int kb = 0; kb < nk; kb += 8) {
-            int idx[8];
-            uint32_t p0[8], p1[8];
+        for (int kb = 0; kb < nk; kb += OT_STAGE_BATCH) {
+            int idx[OT_STAGE_BATCH];
+            uint32_t p0[OT_STAGE_BATCH], p1[OT_STAGE_BATCH];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
+            for (int s = 0; s < OT_STAGE_BATCH; ++s) {
                 idx[s] = -1;
                 p0[s] = p1[s] = 0;
                 if (kb + s < nk && r < SR) {
@@ -278,7 +284,7 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
                 }
             }
 #pragma unroll
-            for (int s = 0; s < 8; ++s)
+            for (int s = 0; s < OT_STAGE_BATCH; ++s)
                 if (idx[s] >= 0) {
                     const float f0 = (float)p0[s], f1 = (float)p1[s];
                     jr[idx[s]] = make_float2(f0, f1 - f0);

@@ -3,10 +3,20 @@
 #include "ot_device.hpp"
 #include "ot_launch.hpp"
 
+// Optional occupancy target (waves per SIMD) for the tracking kernels.
+#ifndef OT_LK_MIN_WAVES
+#define OT_LK_MIN_WAVES 0
+#endif
+#if OT_LK_MIN_WAVES > 0
+#define OT_LK_BOUNDS __launch_bounds__(64, OT_LK_MIN_WAVES)
+#else
+#define OT_LK_BOUNDS __launch_bounds__(64)
+#endif
+
 namespace ot {
 
 template <int R>
-__global__ __launch_bounds__(64) void k_lk_track(DevPyr P, DevPyr Q, const float* __restrict__ pts,
+__global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restrict__ pts,
                                                  int n, LkParams prm, float* __restrict__ next_pts,
                                                  uint8_t* __restrict__ status,
                                                  float* __restrict__ err,
@@ -62,7 +72,7 @@ __device__ __forceinline__ void lk_batch_item(const uint8_t* __restrict__ table,
 
 // One wave per point over the flattened points of every job.
 template <int R>
-__global__ __launch_bounds__(64) void k_lk_batch(const uint8_t* __restrict__ table, int cap) {
+__global__ OT_LK_BOUNDS void k_lk_batch(const uint8_t* __restrict__ table, int cap) {
     extern __shared__ __align__(16) unsigned char lk_smem[];
     const TableLayout T = TableLayout::make(cap);
     const TableHdr& hd = *reinterpret_cast<const TableHdr*>(table);
@@ -74,7 +84,7 @@ __global__ __launch_bounds__(64) void k_lk_batch(const uint8_t* __restrict__ tab
 // Persistent form: a fixed grid of waves claims chunks of points from the
 // table's work counter until the points run out.
 template <int R>
-__global__ __launch_bounds__(64) void k_lk_batch_persistent(uint8_t* __restrict__ table, int cap) {
+__global__ OT_LK_BOUNDS void k_lk_batch_persistent(uint8_t* __restrict__ table, int cap) {
     extern __shared__ __align__(16) unsigned char lk_smem[];
     const TableLayout T = TableLayout::make(cap);
     TableHdr& hd = *reinterpret_cast<TableHdr*>(table);
