@@ -49,10 +49,10 @@ def parse():
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
     p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
     p.add_argument("--no-served", action="store_true", help="skip the served-vs-plain run")
-    p.add_argument("--served-seconds", type=float, default=4.0,
+    p.add_argument("--served-seconds", type=float, default=3.0,
                    help="length of the 64-stream arrival trace for served and plain")
-    p.add_argument("--served-rate", type=float, default=1.0,
-                   help="arrival-rate multiplier on 25 fps per stream")
+    p.add_argument("--served-rates", default="1,2,4",
+                   help="arrival-rate multipliers on 25 fps per stream (comma list)")
     return p.parse_args()
 
 
@@ -116,6 +116,9 @@ def main():
     n, m = wl.n, wl.boxes.shape[0]
     prev = ops.pyramid_build(f0, L)
     ws1 = ops.alloc_workspace(W, H, L)
+    from paper_1910_06017_amd import batch
+    MARGIN = batch.default_schedule("single_" + batch.bucket_key(
+        [type("J", (), {"n": n, "levels": L})()])).get("margin", 0)
     nxt = torch.empty((n, 2), dtype=torch.float32, device=dev)
     st = torch.empty(n, dtype=torch.uint8, device=dev)
     err = torch.empty(n, dtype=torch.float32, device=dev)
@@ -125,13 +128,15 @@ def main():
 
     def step():
         Q = ops.pyramid_build(f1, L, ws=ws1)
-        ops.lk_track(prev, Q, pts, win=WIN, levels=L, iters=ITERS, eps=EPS, out=(nxt, st, err))
+        ops.lk_track(prev, Q, pts, win=WIN, levels=L, iters=ITERS, eps=EPS, margin=MARGIN,
+                     out=(nxt, st, err))
         ops.box_update(boxes, bid, pts, nxt, st, out=(ob, oc))
 
     nxt_pyr = ops.pyramid_build(f1, L, ws=ws1)
 
     def lk_only():
-        ops.lk_track(prev, nxt_pyr, pts, win=WIN, levels=L, iters=ITERS, eps=EPS, out=(nxt, st, err))
+        ops.lk_track(prev, nxt_pyr, pts, win=WIN, levels=L, iters=ITERS, eps=EPS, margin=MARGIN,
+                     out=(nxt, st, err))
 
     cs = torch.cuda.Stream()
     cs.wait_stream(torch.cuda.current_stream())
@@ -211,7 +216,8 @@ def main():
         "config": {"workload": "720x576 frame pair, 20 moving textured boxes, 8000 grid points, "
                                "LK window 21x21, 4 levels, 30 iterations, eps 0.01; step = "
                                "next-frame pyramid + LK + per-box median, one HIP graph replay",
-                   "points_per_step": n, "boxes": m, "levels": L, "win": WIN},
+                   "points_per_step": n, "boxes": m, "levels": L, "win": WIN,
+                   "lds_margin": MARGIN},
         "frame_latency_ms": {"p50": float(np.percentile(lat, 50)),
                              "p99": float(np.percentile(lat, 99)), "path": "plain"},
         "ok_fraction": ok_frac,
@@ -264,7 +270,8 @@ def bench_batched(a):
 
 def bench_served(a):
     """64 streams with Poisson arrivals (25 fps each x rate), served with
-    continuous batching and, on the same trace, plain per-stream calls."""
+    continuous batching and, on the same trace, plain per-stream calls, for
+    each arrival-rate multiplier."""
     from paper_1910_06017_amd import serve, synth
 
     streams = synth.served_streams(nframes=10)
@@ -277,31 +284,43 @@ def bench_served(a):
         s = streams[sid]
         reseed = None
         if k % 10 == 0:
-            if (sid, k % len(s.frames)) not in seeds:
-                seeds[(sid, k % len(s.frames))] = s.seed_points(k, np.random.default_rng(sid * 7919 + k))
-            reseed = seeds[(sid, k % len(s.frames))]
+            key = (sid, k % len(s.frames))
+            if key not in seeds:
+                seeds[key] = s.seed_points(k, np.random.default_rng(sid * 7919 + k))
+            reseed = seeds[key]
         return serve.Frame(sid, k, t, pinned[sid][k % len(s.frames)], reseed)
 
-    trace = serve.make_trace(len(streams), a.served_seconds, 25.0, seed=505,
-                             rate_scale=a.served_rate)
     pts_of = {s.sid: sum(s.pts_per_box) for s in streams}
-    out = {"streams": len(streams), "trace_s": a.served_seconds, "frames": len(trace),
-           "fps_per_stream": 25.0 * a.served_rate,
-           "offered_points_per_s": sum(pts_of[s] for _, s, _ in trace) / a.served_seconds}
-    for name, batched, ex in (("served", True, serve.GpuExecutor(max_jobs=64, max_points=1 << 21)),
-                              ("plain", False, serve.PlainExecutor())):
-        # warm the executors on a short trace of the same streams
-        sch = serve.Scheduler(budget=1 << 40, max_jobs=64, max_points=1 << 21)
-        t0 = time.perf_counter()
-        res = serve.run_trace(trace, frame_fn, specs, sch, ex, batched=batched,
-                              max_wall=a.served_seconds * 4)
-        wall = time.perf_counter() - t0
-        st = serve.latency_stats(res)
-        st["tracked_points_per_s"] = sum(pts_of[r.sid] for r in res if r.k > 0) / max(wall, 1e-9)
-        st["wall_s"] = wall
-        st["ticks"] = ex.ticks
-        out[name] = st
-    return out
+    executors = {"served": (True, serve.GpuExecutor(max_jobs=64, max_points=1 << 21)),
+                 "plain": (False, serve.PlainExecutor())}
+    # warm both paths (allocation, graph capture) on a short trace
+    warm = serve.make_trace(len(streams), 0.2, 25.0, seed=1)
+    for name, (batched, ex) in executors.items():
+        serve.run_trace(warm, frame_fn, specs, serve.Scheduler(1 << 40, 64, 1 << 21), ex,
+                        batched=batched)
+        for sid in list(ex.slots):
+            ex.evict(sid)
+    runs = []
+    for rate in [float(r) for r in a.served_rates.split(",")]:
+        trace = serve.make_trace(len(streams), a.served_seconds, 25.0, seed=505, rate_scale=rate)
+        rec = {"rate": rate, "fps_per_stream": 25.0 * rate, "frames": len(trace),
+               "offered_points_per_s": sum(pts_of[s] for _, s, _ in trace) / a.served_seconds}
+        for name, (batched, ex) in executors.items():
+            sch = serve.Scheduler(budget=1 << 40, max_jobs=64, max_points=1 << 21)
+            t0 = time.perf_counter()
+            res = serve.run_trace(trace, frame_fn, specs, sch, ex, batched=batched,
+                                  max_wall=a.served_seconds * 3)
+            wall = time.perf_counter() - t0
+            st = serve.latency_stats(res)
+            st["completed"] = len(res)
+            st["tracked_points_per_s"] = sum(pts_of[r.sid] for r in res if r.k > 0) / max(wall, 1e-9)
+            st["ticks"] = ex.ticks
+            rec[name] = st
+            for sid in list(ex.slots):
+                ex.evict(sid)
+            ex.ticks = 0
+        runs.append(rec)
+    return {"streams": len(streams), "trace_s": a.served_seconds, "runs": runs}
 
 
 def _pin(frame):

@@ -193,13 +193,15 @@ def default_schedule(key: str) -> dict:
             cache = json.load(f)
         if key in cache:
             return dict(cache[key]["schedule"])
-        if cache:
+        single = key.startswith("single_")
+        cands = [k for k in cache if k.startswith("single_") == single]
+        if cands:
             def pts(k):
-                return int(k.split("_")[0][1:])
+                return int(k.split("_")[-2][1:])
             want = pts(key)
-            best = min(cache, key=lambda k: abs(math.log2(pts(k)) - math.log2(want)))
+            best = min(cands, key=lambda k: abs(math.log2(pts(k)) - math.log2(want)))
             return dict(cache[best]["schedule"])
-    return {"margin": 0, "lk_waves": 0, "chunk": 1}
+    return {"margin": 0} if key.startswith("single_") else {"margin": 0, "lk_waves": 0, "chunk": 1}
 
 
 def bucket_key(jobs: list) -> str:

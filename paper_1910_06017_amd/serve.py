@@ -152,37 +152,158 @@ class Scheduler:
 
 
 # ----------------------------------------------------------------------------- GPU side
-class _Slot:
-    """Resident device state of one stream."""
+_HIP = None
 
-    def __init__(self, spec: StreamSpec, device):
+
+def _hip():
+    """hipMemcpyAsync from the HIP runtime (host<->device copies without the
+    torch dispatcher on the per-frame path)."""
+    global _HIP
+    if _HIP is None:
+        import ctypes as C
+
+        h = C.CDLL("libamdhip64.so")
+        h.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        h.hipMemcpyAsync.restype = C.c_int
+        _HIP = h
+    return _HIP
+
+
+_H2D, _D2H = 1, 2
+
+
+def _copy(dst: int, src: int, nbytes: int, kind: int, stream: int):
+    if nbytes:
+        rc = _hip().hipMemcpyAsync(dst, src, nbytes, kind, stream)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+
+class _Arena:
+    """Per-executor result arenas: boxes (two parities) and counts per slot,
+    device and pinned host, so one copy brings back every stream's result."""
+
+    def __init__(self, torch, device, slots: int, m_chunk: int):
+        self.m_chunk = m_chunk
+        self.dev_boxes = [torch.zeros((slots * m_chunk, 4), dtype=torch.float32, device=device)
+                          for _ in range(2)]
+        self.dev_count = torch.zeros(slots * m_chunk, dtype=torch.int32, device=device)
+        self.host_boxes = [torch.zeros((slots * m_chunk, 4), dtype=torch.float32, pin_memory=True)
+                           for _ in range(2)]
+        self.host_count = torch.zeros(slots * m_chunk, dtype=torch.int32, pin_memory=True)
+        self.free = list(range(slots - 1, -1, -1))
+
+    def take(self) -> int:
+        if not self.free:
+            raise RuntimeError("no result slot left (raise max_slots)")
+        return self.free.pop()
+
+    def give(self, k: int):
+        self.free.append(k)
+
+
+class _Slot:
+    """Resident device state of one stream: two frames, two pyramid
+    workspaces, two point buffers and two box chunks (one per frame parity),
+    plus the C job descriptors of both parities, built once."""
+
+    def __init__(self, spec: StreamSpec, device, arena: _Arena):
+        import ctypes as C
+
         import torch
 
         from . import ops
 
+        if spec.m_max > arena.m_chunk:
+            raise ValueError(f"stream {spec.sid}: {spec.m_max} boxes > {arena.m_chunk} per stream")
         self.spec = spec
         H, W, L = spec.H, spec.W, spec.levels
         self.frames = [torch.empty((H, W), dtype=torch.uint8, device=device) for _ in range(2)]
         self.ws = [ops.alloc_workspace(W, H, L, device) for _ in range(2)]
-        n, m = spec.n_max, spec.m_max
+        n = max(1, spec.n_max)
         self.pts = [torch.zeros((n, 2), dtype=torch.float32, device=device) for _ in range(2)]
         self.status = torch.zeros(n, dtype=torch.uint8, device=device)
         self.err = torch.zeros(n, dtype=torch.float32, device=device)
         self.box_id = torch.full((n,), -1, dtype=torch.int32, device=device)
-        self.boxes = [torch.zeros((m, 4), dtype=torch.float32, device=device) for _ in range(2)]
-        self.count = torch.zeros(m, dtype=torch.int32, device=device)
-        self.cur = 0            # index of the frame / pyramid / points / boxes of the last frame
-        self.pyr = None         # ops.Pyramid of the last frame
+        self.arena = arena
+        self.chunk = arena.take()
+        c0 = self.chunk * arena.m_chunk
+        self.c0 = c0
+        self.boxes = [arena.dev_boxes[p][c0:c0 + arena.m_chunk] for p in range(2)]
+        self.count = arena.dev_count[c0:c0 + arena.m_chunk]
+        self.pyr = [ops.pyramid_layout(self.frames[p], L, self.ws[p]) for p in range(2)]
+        # job[p]: the frame just uploaded is in parity p, the previous one in 1-p
+        self.job = []
+        for p in range(2):
+            j = ops.OtJob()
+            q = 1 - p
+            j.prev = self.pyr[q].desc
+            j.next_frame = self.frames[p].data_ptr()
+            j.next_pitch = W
+            j.next_ws = self.ws[p].data_ptr()
+            j.next_ws_bytes = self.ws[p].numel()
+            j.levels = L
+            j.pts, j.next_pts = self.pts[q].data_ptr(), self.pts[p].data_ptr()
+            j.status, j.err = self.status.data_ptr(), self.err.data_ptr()
+            j.boxes, j.out_boxes = self.boxes[q].data_ptr(), self.boxes[p].data_ptr()
+            j.box_id, j.out_count = self.box_id.data_ptr(), self.count.data_ptr()
+            self.job.append(j)
+        self.cur = 0        # parity of the last frame
+        self.started = False
         self.n = 0
         self.m = 0
         self.frames_done = 0
+        self._c = C
+
+    def release(self):
+        self.arena.give(self.chunk)
+
+    def upload(self, fr: Frame, p: int, stream: int):
+        px = fr.pixels
+        if hasattr(px, "data_ptr"):
+            _copy(self.frames[p].data_ptr(), px.data_ptr(), px.numel(), _H2D, stream)
+        else:
+            a = np.ascontiguousarray(px, np.uint8)
+            _copy(self.frames[p].data_ptr(), a.ctypes.data, a.nbytes, _H2D, stream)
+
+    def reseed(self, fr: Frame, p: int, stream: int):
+        """Detections at this frame replace the points and boxes tracked from
+        it, after the frame's own pair has been processed."""
+        if fr.reseed is None:
+            return
+        pts, bid, bx = (np.ascontiguousarray(a) for a in fr.reseed)
+        n, m = len(pts), len(bx)
+        if n > self.spec.n_max or m > self.spec.m_max:
+            raise ValueError("detections exceed the stream's capacity")
+        pts = pts.astype(np.float32, copy=False)
+        bid = bid.astype(np.int32, copy=False)
+        bx = bx.astype(np.float32, copy=False)
+        # pageable sources: the runtime stages them before the call returns
+        _copy(self.pts[p].data_ptr(), pts.ctypes.data, pts.nbytes, _H2D, stream)
+        _copy(self.box_id.data_ptr(), bid.ctypes.data, bid.nbytes, _H2D, stream)
+        _copy(self.boxes[p].data_ptr(), bx.ctypes.data, bx.nbytes, _H2D, stream)
+        self.n, self.m = n, m
+
+    def job_for(self, p: int):
+        """C job for the frame in parity p (no points or boxes on the first frame)."""
+        j = self.job[p]
+        if not self.started:
+            j.prev = self.pyr[p].desc   # any valid descriptor: nothing is tracked
+            j.n = j.m = 0
+        else:
+            j.prev = self.pyr[1 - p].desc
+            j.n, j.m = self.n, self.m
+        return j
 
 
 class GpuExecutor:
-    """Runs a tick of frames (at most one per stream) as one batched launch."""
+    """Runs a tick of frames (at most one per stream) as one batched launch:
+    frame uploads, one captured HIP graph (table copy, pyramid, tracking, box
+    stages), one copy back of every result, all on one stream."""
 
     def __init__(self, win=21, iters=30, eps=0.01, max_jobs=64, max_points=1 << 21,
-                 max_boxes=4096, max_levels=5, schedule=None, device="cuda"):
+                 max_boxes=4096, max_levels=5, schedule=None, device="cuda", max_slots=128,
+                 m_chunk=64):
         import torch
 
         from . import batch
@@ -193,147 +314,146 @@ class GpuExecutor:
         self.cfg = batch.BatchConfig(win=win, iters=iters, eps=eps, max_jobs=max_jobs,
                                      max_points=max_points, max_boxes=max_boxes,
                                      max_tiles=1 << 15, max_levels=max_levels, **sched)
-        self.runner = batch.BatchRunner(self.cfg, device=self.device, tables=2)
+        self.runner = batch.BatchRunner(self.cfg, device=self.device, tables=1)
+        self.arena = _Arena(torch, self.device, max_slots, m_chunk)
         self.slots: dict = {}
-        self.stream = torch.cuda.Stream()
-        self.host_boxes = torch.empty((max_boxes, 4), dtype=torch.float32, pin_memory=True)
-        self.host_count = torch.empty(max_boxes, dtype=torch.int32, pin_memory=True)
-        self.dev_boxes = torch.empty((max_boxes, 4), dtype=torch.float32, device=self.device)
-        self.dev_count = torch.empty(max_boxes, dtype=torch.int32, device=self.device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.sh = int(self.stream.cuda_stream)
+        self.graph = None
         self.ticks = 0
 
     def admit(self, spec: StreamSpec):
-        self.slots[spec.sid] = _Slot(spec, self.device)
+        self.slots[spec.sid] = _Slot(spec, self.device, self.arena)
 
     def evict(self, sid: int):
-        self.slots.pop(sid, None)
+        s = self.slots.pop(sid, None)
+        if s is not None:
+            self.torch.cuda.synchronize(self.device)
+            s.release()
 
-    @staticmethod
-    def _upload(torch, slot, fr: Frame, nxt: int):
-        src = fr.pixels if isinstance(fr.pixels, torch.Tensor) else torch.from_numpy(fr.pixels)
-        slot.frames[nxt].copy_(src, non_blocking=True)
+    def _launch(self, jobs):
+        import ctypes as C
 
-    @staticmethod
-    def _reseed(torch, slot, fr: Frame, dst: int):
-        """Detections at this frame replace the points and boxes tracked from it
-        (after the frame's own pair has been processed)."""
-        if fr.reseed is None:
-            return
-        p, bid, bx = fr.reseed
-        n, m = len(p), len(bx)
-        if n > slot.spec.n_max or m > slot.spec.m_max:
-            raise ValueError("detections exceed the stream's capacity")
-        slot.pts[dst][:n].copy_(torch.from_numpy(np.ascontiguousarray(p)), non_blocking=True)
-        slot.box_id[:n].copy_(torch.from_numpy(np.ascontiguousarray(bid)), non_blocking=True)
-        slot.boxes[dst][:m].copy_(torch.from_numpy(np.ascontiguousarray(bx)), non_blocking=True)
-        slot.n, slot.m = n, m
+        from . import ops
+
+        arr = (ops.OtJob * max(1, len(jobs)))()
+        for i, j in enumerate(jobs):
+            C.memmove(C.byref(arr, i * C.sizeof(ops.OtJob)), C.byref(j), C.sizeof(ops.OtJob))
+        ops.check(ops.lib().ot_batch_pack(arr, len(jobs), C.byref(self.runner.ccfg),
+                                          int(self.runner.host[0].data_ptr()),
+                                          self.runner.table_bytes, None), "ot_batch_pack")
+        if self.graph is None:
+            self.graph = self.runner.capture(0)
+        with self.torch.cuda.stream(self.stream):
+            self.graph.replay()
 
     def run_tick(self, frames: list, now=time.perf_counter) -> list:
         torch = self.torch
-        from . import batch, ops
-
-        jobs, metas = [], []
-        with torch.cuda.stream(self.stream):
-            for fr in frames:
-                slot = self.slots[fr.sid]
-                nxt = 1 - slot.cur
-                self._upload(torch, slot, fr, nxt)
-                first = slot.pyr is None
-                n = 0 if first else slot.n
-                m = 0 if first else slot.m
-                prev = slot.pyr if not first else ops.pyramid_layout(
-                    slot.frames[nxt], slot.spec.levels, slot.ws[nxt])
-                jobs.append(batch.Job(
-                    prev=prev, next_frame=slot.frames[nxt], next_ws=slot.ws[nxt],
-                    levels=slot.spec.levels, pts=slot.pts[slot.cur][:n],
-                    next_pts=slot.pts[nxt][:n], status=slot.status[:n], err=slot.err[:n],
-                    boxes=slot.boxes[slot.cur][:m], box_id=slot.box_id[:n],
-                    out_boxes=slot.boxes[nxt][:m], out_count=slot.count[:m]))
-                metas.append((fr, slot, nxt, m))
-            pyrs = self.runner.pack(jobs)
-            self.runner.run(self.stream)
-            # gather every stream's outputs into one buffer for a single copy back
-            off = 0
-            for (fr, slot, nxt, m), _ in zip(metas, jobs):
-                if m:
-                    self.dev_boxes[off:off + m].copy_(slot.boxes[nxt][:m])
-                    self.dev_count[off:off + m].copy_(slot.count[:m])
-                off += m
-            tot = off
-            for fr, slot, nxt, m in metas:
-                self._reseed(torch, slot, fr, nxt)
-            if tot:
-                self.host_boxes[:tot].copy_(self.dev_boxes[:tot], non_blocking=True)
-                self.host_count[:tot].copy_(self.dev_count[:tot], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(self.stream)
+        metas, jobs = [], []
+        for fr in frames:
+            slot = self.slots[fr.sid]
+            p = 1 - slot.cur
+            slot.upload(fr, p, self.sh)
+            jobs.append(slot.job_for(p))
+            metas.append((fr, slot, p, slot.m if slot.started else 0))
+        self._launch(jobs)
+        a = self.arena
+        for par in (0, 1):
+            if any(p == par for _, _, p, m in metas if m):
+                _copy(a.host_boxes[par].data_ptr(), a.dev_boxes[par].data_ptr(),
+                      a.dev_boxes[par].numel() * 4, _D2H, self.sh)
+        _copy(a.host_count.data_ptr(), a.dev_count.data_ptr(), a.dev_count.numel() * 4, _D2H,
+              self.sh)
+        for fr, slot, p, m in metas:
+            slot.reseed(fr, p, self.sh)
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
         ev.synchronize()
         t = now()
-        out, off = [], 0
-        for (fr, slot, nxt, m), pyr in zip(metas, pyrs):
-            slot.pyr = pyr
-            slot.cur = nxt
+        out = []
+        hb = [b.numpy() for b in a.host_boxes]
+        hc = a.host_count.numpy()
+        for fr, slot, p, m in metas:
+            out.append(Result(fr.sid, fr.k, fr.t_arrival, t, hb[p][slot.c0:slot.c0 + m].copy(),
+                              hc[slot.c0:slot.c0 + m].copy(), self.ticks))
+            slot.cur = p
+            slot.started = True
             slot.frames_done += 1
-            out.append(Result(fr.sid, fr.k, fr.t_arrival, t,
-                              self.host_boxes[off:off + m].numpy().copy(),
-                              self.host_count[off:off + m].numpy().copy(), self.ticks))
-            off += m
         self.ticks += 1
         return out
 
 
 class PlainExecutor:
-    """The comparison path: each frame on its own, with the per-stream calls
-    (ot_pyramid_build, ot_lk_track, ot_box_update), in arrival order."""
+    """The comparison path: each frame on its own with the per-stream calls
+    (ot_pyramid_build, ot_lk_track, ot_box_update), in arrival order, with the
+    same resident state and the same copies as the served path."""
 
-    def __init__(self, win=21, iters=30, eps=0.01, device="cuda"):
+    def __init__(self, win=21, iters=30, eps=0.01, device="cuda", max_slots=128, m_chunk=64):
         import torch
+
+        from . import ops
 
         self.torch = torch
         self.device = torch.device(device)
         self.win, self.iters, self.eps = win, iters, eps
+        self.arena = _Arena(torch, self.device, max_slots, m_chunk)
         self.slots: dict = {}
-        self.stream = torch.cuda.Stream()
+        self.stream = torch.cuda.Stream(self.device)
+        self.sh = int(self.stream.cuda_stream)
+        self.opts = ops.OtLkOpts(ops.OT_DEFAULT_MIN_EIG, None, None, 0)
         self.ticks = 0
 
     def admit(self, spec: StreamSpec):
-        self.slots[spec.sid] = _Slot(spec, self.device)
+        self.slots[spec.sid] = _Slot(spec, self.device, self.arena)
 
     def evict(self, sid: int):
-        self.slots.pop(sid, None)
+        s = self.slots.pop(sid, None)
+        if s is not None:
+            self.torch.cuda.synchronize(self.device)
+            s.release()
 
     def run_tick(self, frames: list, now=time.perf_counter) -> list:
-        torch = self.torch
+        import ctypes as C
+
         from . import ops
 
+        torch, L = self.torch, ops.lib()
         out = []
+        a = self.arena
         for fr in frames:
             slot = self.slots[fr.sid]
-            nxt = 1 - slot.cur
-            with torch.cuda.stream(self.stream):
-                GpuExecutor._upload(torch, slot, fr, nxt)
-                Q = ops.pyramid_build(slot.frames[nxt], slot.spec.levels, ws=slot.ws[nxt],
-                                      stream=self.stream)
-                m = 0
-                if slot.pyr is not None:
-                    n, m = slot.n, slot.m
-                    ops.lk_track(slot.pyr, Q, slot.pts[slot.cur][:n], win=self.win,
-                                 levels=slot.spec.levels, iters=self.iters, eps=self.eps,
-                                 out=(slot.pts[nxt][:n], slot.status[:n], slot.err[:n]),
-                                 stream=self.stream)
-                    ops.box_update(slot.boxes[slot.cur][:m], slot.box_id[:n],
-                                   slot.pts[slot.cur][:n], slot.pts[nxt][:n], slot.status[:n],
-                                   out=(slot.boxes[nxt][:m], slot.count[:m]), stream=self.stream)
-                hb = slot.boxes[nxt][:m].to("cpu", non_blocking=True)
-                hc = slot.count[:m].to("cpu", non_blocking=True)
-                GpuExecutor._reseed(torch, slot, fr, nxt)
-                ev = torch.cuda.Event()
-                ev.record(self.stream)
+            p, q = 1 - slot.cur, slot.cur
+            sp = slot.spec
+            slot.upload(fr, p, self.sh)
+            d = ops.OtPyr()
+            ops.check(L.ot_pyramid_build(slot.frames[p].data_ptr(), sp.W, sp.H, sp.W, sp.levels,
+                                         slot.ws[p].data_ptr(), slot.ws[p].numel(), 0,
+                                         C.byref(d), self.sh), "ot_pyramid_build")
+            m = 0
+            if slot.started:
+                n, m = slot.n, slot.m
+                ops.check(L.ot_lk_track_ex(C.byref(slot.pyr[q].desc), C.byref(slot.pyr[p].desc),
+                                           slot.pts[q].data_ptr(), n, self.win, sp.levels,
+                                           self.iters, self.eps, slot.pts[p].data_ptr(),
+                                           slot.status.data_ptr(), slot.err.data_ptr(),
+                                           C.byref(self.opts), self.sh), "ot_lk_track")
+                ops.check(L.ot_box_update(slot.boxes[q].data_ptr(), m, slot.box_id.data_ptr(),
+                                          slot.pts[q].data_ptr(), slot.pts[p].data_ptr(),
+                                          slot.status.data_ptr(), n, slot.boxes[p].data_ptr(),
+                                          slot.count.data_ptr(), self.sh), "ot_box_update")
+                _copy(a.host_boxes[p][slot.c0:].data_ptr(), slot.boxes[p].data_ptr(), m * 16,
+                      _D2H, self.sh)
+                _copy(a.host_count[slot.c0:].data_ptr(), slot.count.data_ptr(), m * 4, _D2H,
+                      self.sh)
+            slot.reseed(fr, p, self.sh)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
             ev.synchronize()
-            slot.pyr = Q
-            slot.cur = nxt
-            out.append(Result(fr.sid, fr.k, fr.t_arrival, now(), hb.numpy().copy(),
-                              hc.numpy().copy(), self.ticks))
+            out.append(Result(fr.sid, fr.k, fr.t_arrival, now(),
+                              a.host_boxes[p].numpy()[slot.c0:slot.c0 + m].copy(),
+                              a.host_count.numpy()[slot.c0:slot.c0 + m].copy(), self.ticks))
+            slot.cur = p
+            slot.started = True
             self.ticks += 1
         return out
 
