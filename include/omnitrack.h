@@ -196,6 +196,9 @@ typedef struct {
     int32_t max_boxes;     /* capacity in boxes */
     int32_t max_tiles;     /* capacity in pyramid tiles per level */
     int32_t max_levels;    /* levels launched for the pyramid stage */
+    int32_t exact_grids;   /* nonzero: size every launch from the packed table's totals
+                              (read from table_host) instead of the capacities -- for
+                              eager ticks; a captured graph needs capacity-sized grids */
 } ot_batch_cfg;
 
 /* Bytes of the descriptor table for cfg's capacities (0 if invalid). */

@@ -66,11 +66,13 @@ class BatchConfig:
     max_boxes: int = 4096
     max_tiles: int = 1 << 14
     max_levels: int = 5
+    exact_grids: bool = False  # eager ticks: launch exactly the packed work
 
     def to_c(self) -> "ops.OtBatchCfg":
         return ops.OtBatchCfg(self.win, self.iters, self.eps, self.min_eig, self.margin,
                               self.lk_waves, self.chunk, self.max_jobs, self.max_points,
-                              self.max_boxes, self.max_tiles, self.max_levels)
+                              self.max_boxes, self.max_tiles, self.max_levels,
+                              int(self.exact_grids))
 
     def schedule(self) -> dict:
         return {"margin": self.margin, "lk_waves": self.lk_waves, "chunk": self.chunk}
@@ -170,6 +172,8 @@ class BatchRunner:
         """A HIP graph of one tick reading host table `table` (replay after
         re-packing that table with the same capacities)."""
         torch = self.torch
+        if self.cfg.exact_grids:
+            raise ValueError("a captured tick needs capacity-sized grids (exact_grids=False)")
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())

@@ -301,16 +301,23 @@ ot_err ot_batch_run(const void* table_host, void* table_dev, size_t table_bytes,
     if (hipMemcpyAsync(table_dev, table_host, T.bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         return OT_E_LAUNCH;
     const uint8_t* tdev = static_cast<const uint8_t*>(table_dev);
-    for (int l = 1; l < cfg->max_levels; ++l)
-        if (cfg->max_tiles > 0 &&
-            launch_batch_pyr(tdev, cfg->max_jobs, l, cfg->max_tiles, s) != hipSuccess)
+    // grid sizes: the capacities (graph-capturable), or the packed totals
+    TableHdr hd;
+    memcpy(&hd, table_host, sizeof(hd));
+    const bool exact = cfg->exact_grids != 0;
+    for (int l = 1; l < cfg->max_levels; ++l) {
+        const int grid = exact ? hd.total_tiles[l] : cfg->max_tiles;
+        if (grid > 0 && launch_batch_pyr(tdev, cfg->max_jobs, l, grid, s) != hipSuccess)
             return OT_E_LAUNCH;
+    }
     const bool persistent = cfg->lk_waves > 0;
-    const int grid = persistent ? cfg->lk_waves : cfg->max_points;
+    int grid = persistent ? cfg->lk_waves : (exact ? hd.total_pts : cfg->max_points);
+    if (persistent && exact && hd.total_pts == 0) grid = 0;
     if (grid > 0 &&
         launch_batch_lk(tdev, cfg->max_jobs, prm.win, prm.margin, grid, persistent, s) != hipSuccess)
         return OT_E_LAUNCH;
-    if (cfg->max_boxes > 0 && launch_batch_box(tdev, cfg->max_jobs, cfg->max_boxes, s) != hipSuccess)
+    grid = exact ? hd.total_boxes : cfg->max_boxes;
+    if (grid > 0 && launch_batch_box(tdev, cfg->max_jobs, grid, s) != hipSuccess)
         return OT_E_LAUNCH;
     return OT_OK;
 }

@@ -56,7 +56,8 @@ class OtBatchCfg(C.Structure):
     _fields_ = [("win", C.c_int32), ("iters", C.c_int32), ("eps", C.c_float),
                 ("min_eig", C.c_float), ("margin", C.c_int32), ("lk_waves", C.c_int32),
                 ("chunk", C.c_int32), ("max_jobs", C.c_int32), ("max_points", C.c_int32),
-                ("max_boxes", C.c_int32), ("max_tiles", C.c_int32), ("max_levels", C.c_int32)]
+                ("max_boxes", C.c_int32), ("max_tiles", C.c_int32), ("max_levels", C.c_int32),
+                ("exact_grids", C.c_int32)]
 
 
 _lib = None

@@ -298,8 +298,9 @@ class _Slot:
 
 class GpuExecutor:
     """Runs a tick of frames (at most one per stream) as one batched launch:
-    frame uploads, one captured HIP graph (table copy, pyramid, tracking, box
-    stages), one copy back of every result, all on one stream."""
+    frame uploads, the table copy and the pyramid, tracking and box stages
+    (grids sized to the packed work), one copy back of every result, all on
+    one stream."""
 
     def __init__(self, win=21, iters=30, eps=0.01, max_jobs=64, max_points=1 << 21,
                  max_boxes=4096, max_levels=5, schedule=None, device="cuda", max_slots=128,
@@ -313,13 +314,13 @@ class GpuExecutor:
         sched = schedule or {}
         self.cfg = batch.BatchConfig(win=win, iters=iters, eps=eps, max_jobs=max_jobs,
                                      max_points=max_points, max_boxes=max_boxes,
-                                     max_tiles=1 << 15, max_levels=max_levels, **sched)
+                                     max_tiles=1 << 15, max_levels=max_levels, exact_grids=True,
+                                     **sched)
         self.runner = batch.BatchRunner(self.cfg, device=self.device, tables=1)
         self.arena = _Arena(torch, self.device, max_slots, m_chunk)
         self.slots: dict = {}
         self.stream = torch.cuda.Stream(self.device)
         self.sh = int(self.stream.cuda_stream)
-        self.graph = None
         self.ticks = 0
 
     def admit(self, spec: StreamSpec):
@@ -342,10 +343,10 @@ class GpuExecutor:
         ops.check(ops.lib().ot_batch_pack(arr, len(jobs), C.byref(self.runner.ccfg),
                                           int(self.runner.host[0].data_ptr()),
                                           self.runner.table_bytes, None), "ot_batch_pack")
-        if self.graph is None:
-            self.graph = self.runner.capture(0)
-        with self.torch.cuda.stream(self.stream):
-            self.graph.replay()
+        # launches sized from the packed totals (a graph would need capacity grids)
+        ops.check(ops.lib().ot_batch_run(int(self.runner.host[0].data_ptr()),
+                                         int(self.runner.dev.data_ptr()), self.runner.table_bytes,
+                                         C.byref(self.runner.ccfg), self.sh), "ot_batch_run")
 
     def run_tick(self, frames: list, now=time.perf_counter) -> list:
         torch = self.torch

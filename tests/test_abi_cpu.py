@@ -119,7 +119,7 @@ def test_box_validation(L):
 def make_cfg(**kw):
     c = ops.OtBatchCfg(win=21, iters=30, eps=0.01, min_eig=6.5025, margin=0, lk_waves=0,
                        chunk=1, max_jobs=4, max_points=5000, max_boxes=64, max_tiles=4096,
-                       max_levels=5)
+                       max_levels=5, exact_grids=0)
     for k, v in kw.items():
         setattr(c, k, v)
     return c

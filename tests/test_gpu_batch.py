@@ -57,7 +57,8 @@ def small_mix(seed=11, nstreams=7):
     return ws
 
 
-@pytest.mark.parametrize("sched", [dict(lk_waves=0, chunk=1), dict(lk_waves=600, chunk=1),
+@pytest.mark.parametrize("sched", [dict(lk_waves=0, chunk=1), dict(lk_waves=0, exact_grids=True),
+                                   dict(lk_waves=600, chunk=1), dict(lk_waves=600, exact_grids=True),
                                    dict(lk_waves=2048, chunk=3), dict(margin=2, lk_waves=0)])
 def test_batched_equals_per_stream(mods, sched):
     ops, batch = mods
