@@ -66,7 +66,7 @@ def lk_kernel_flops(iters: np.ndarray, lam: np.ndarray) -> float:
 
 def kernel_sha() -> str:
     h = hashlib.sha256()
-    for f in ("ot_device.hpp", "ot_lk.hip", "ot_common.hpp"):
+    for f in ("ot_device.hpp", "ot_lk_dev.hpp", "ot_lk.hip", "ot_common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1910_06017_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -194,7 +194,8 @@ typedef struct {
     int32_t max_jobs;      /* table capacity in jobs */
     int32_t max_points;    /* capacity in points, sizes the non-persistent LK grid */
     int32_t max_boxes;     /* capacity in boxes */
-    int32_t max_tiles;     /* capacity in pyramid tiles per level */
+    int32_t max_tiles;     /* capacity in pyramid tiles per fused launch (16x8 tiles of
+                              the top level of each run of up to 3 levels) */
     int32_t max_levels;    /* levels launched for the pyramid stage */
     int32_t exact_grids;   /* nonzero: size every launch from the packed table's totals
                               (read from table_host) instead of the capacities -- for

@@ -124,12 +124,10 @@ ot_err ot_pyramid_build(const uint8_t* frame, int32_t W, int32_t H, int32_t pitc
     const ot_err e = layout(frame, W, H, pitch, levels, workspace, ws_bytes, flags, &p);
     if (e != OT_OK) return e;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int l = 1; l < levels; ++l) {
-        if (launch_pyr_level(p.level[l - 1], p.w[l - 1], p.h[l - 1], p.pitch[l - 1],
-                             const_cast<uint8_t*>(p.level[l]), p.w[l], p.h[l], p.pitch[l],
-                             s) != hipSuccess)
+    const DevPyr d = to_dev(p);
+    for (int l0 = 0; l0 < levels - 1; l0 += PYR_FUSE)
+        if (launch_pyr_stage(d, l0, pyr_stage_steps(levels, l0), s) != hipSuccess)
             return OT_E_LAUNCH;
-    }
     *out = p;
     return OT_OK;
 }
@@ -224,8 +222,11 @@ ot_err ot_batch_pack(const ot_job* jobs, int32_t njobs, const ot_batch_cfg* cfg,
         if (e != OT_OK) return e;
         pts_total += J.n;
         boxes_total += J.m;
-        for (int l = 1; l < J.levels; ++l)
-            tiles[l] += (int64_t)((np.w[l] + PYR_TW - 1) / PYR_TW) * ((np.h[l] + PYR_TH - 1) / PYR_TH);
+        for (int l0 = 0; l0 < J.levels - 1; l0 += PYR_FUSE) {
+            const int top = l0 + pyr_stage_steps(J.levels, l0);
+            tiles[l0 + 1] += (int64_t)((np.w[top] + PYR_FTW - 1) / PYR_FTW) *
+                             ((np.h[top] + PYR_FTH - 1) / PYR_FTH);
+        }
         if (J.levels - 1 > max_level) max_level = J.levels - 1;
     }
     if (pts_total > cfg->max_points && cfg->lk_waves == 0) return OT_E_WORKSPACE;
@@ -263,12 +264,16 @@ ot_err ot_batch_pack(const ot_job* jobs, int32_t njobs, const ot_batch_cfg* cfg,
         bxp[j] = bacc;
         pacc += J.n;
         bacc += J.m;
+        // fused pyramid stages start at levels 0, PYR_FUSE, ...; stage l0's
+        // tile list lives at per-level index l0 + 1
         for (int l = 1; l < OT_MAX_LEVELS; ++l) {
             tlp[(size_t)l * (cfg->max_jobs + 1) + j] = tacc[l];
-            if (l < J.levels) {
-                const int cols = (np.w[l] + PYR_TW - 1) / PYR_TW;
+            const int l0 = l - 1;
+            if (l0 % PYR_FUSE == 0 && l0 < J.levels - 1) {
+                const int top = l0 + pyr_stage_steps(J.levels, l0);
+                const int cols = (np.w[top] + PYR_FTW - 1) / PYR_FTW;
                 tlc[(size_t)l * cfg->max_jobs + j] = cols;
-                tacc[l] += cols * ((np.h[l] + PYR_TH - 1) / PYR_TH);
+                tacc[l] += cols * ((np.h[top] + PYR_FTH - 1) / PYR_FTH);
             } else {
                 tlc[(size_t)l * cfg->max_jobs + j] = 1;
             }
@@ -305,9 +310,9 @@ ot_err ot_batch_run(const void* table_host, void* table_dev, size_t table_bytes,
     TableHdr hd;
     memcpy(&hd, table_host, sizeof(hd));
     const bool exact = cfg->exact_grids != 0;
-    for (int l = 1; l < cfg->max_levels; ++l) {
-        const int grid = exact ? hd.total_tiles[l] : cfg->max_tiles;
-        if (grid > 0 && launch_batch_pyr(tdev, cfg->max_jobs, l, grid, s) != hipSuccess)
+    for (int l0 = 0; l0 < cfg->max_levels - 1; l0 += PYR_FUSE) {
+        const int grid = exact ? hd.total_tiles[l0 + 1] : cfg->max_tiles;
+        if (grid > 0 && launch_batch_pyr(tdev, cfg->max_jobs, l0, grid, s) != hipSuccess)
             return OT_E_LAUNCH;
     }
     const bool persistent = cfg->lk_waves > 0;

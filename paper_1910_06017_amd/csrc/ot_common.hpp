@@ -14,17 +14,41 @@
 
 namespace ot {
 
-// Pyramid reduce tile: one 256-thread workgroup writes PYR_TW x PYR_TH pixels
-// of level l and reads the (2*PYR_TH+3) x (2*PYR_TW+3) region of level l-1.
-constexpr int PYR_TW = 64;
-constexpr int PYR_TH = 16;
-constexpr int PYR_THREADS = 256;
+// Pyramid: one launch reduces up to PYR_FUSE levels; a 256-thread workgroup
+// owns a PYR_FTW x PYR_FTH tile of the launch's top level and that tile's
+// footprint at the levels below it.
+#ifndef OT_PYR_FTW
+#define OT_PYR_FTW 16
+#endif
+#ifndef OT_PYR_FTH
+#define OT_PYR_FTH 8
+#endif
+#ifndef OT_PYR_THREADS
+#define OT_PYR_THREADS 256
+#endif
+constexpr int PYR_FUSE = 3;
+constexpr int PYR_FTW = OT_PYR_FTW;
+constexpr int PYR_FTH = OT_PYR_FTH;
+constexpr int PYR_THREADS = OT_PYR_THREADS;
 
-// Box median: one 256-thread workgroup per box; up to BOX_CAP point
+// Steps of the fused launch starting at level l0 for a pyramid of `levels`.
+OT_HD inline int pyr_stage_steps(int levels, int l0) {
+    const int k = levels - 1 - l0;
+    return k < 0 ? 0 : (k > PYR_FUSE ? PYR_FUSE : k);
+}
+
+// Box median: one 1024-thread workgroup per box; up to BOX_CAP point
 // displacements are gathered in LDS, larger boxes are re-scanned from memory.
-constexpr int BOX_THREADS = 256;
+constexpr int BOX_THREADS = 1024;
 constexpr int BOX_CAP = 4096;
-constexpr int BOX_SORT_MAX = 1024;  // bitonic sort in LDS up to this count, radix select above
+#ifndef OT_BOX_WAVE_SORT
+#define OT_BOX_WAVE_SORT 512
+#endif
+#ifndef OT_BOX_SORT_MAX
+#define OT_BOX_SORT_MAX 4096
+#endif
+constexpr int BOX_WAVE_SORT = OT_BOX_WAVE_SORT;  // one wave per axis sorts in registers up to this
+constexpr int BOX_SORT_MAX = OT_BOX_SORT_MAX;    // bitonic sort in LDS up to this, radix select above
 
 constexpr int LK_DEFAULT_MARGIN = 4;
 constexpr int LK_MAX_MARGIN = 16;
@@ -70,7 +94,7 @@ struct TableHdr {
     int32_t total_pts;
     int32_t total_boxes;
     int32_t max_level;                  // highest pyramid level built
-    int32_t total_tiles[OT_MAX_LEVELS]; // per level (index 0 unused)
+    int32_t total_tiles[OT_MAX_LEVELS]; // fused pyramid stage from level l-1 at index l
     LkParams lk;
     int32_t chunk;
     uint32_t counter;                   // persistent LK work counter
@@ -111,13 +135,15 @@ OT_HD inline int lk_rows_needed(int win) {
 }
 
 // LDS bytes one tracking wave needs: the larger of the set-up stage (uint8
-// template patch + float2 gradient tap grid) and the iteration stage (float2
-// target region with a margin on every side).
+// template patch + float2 gradient tap grid) and the iteration stage (packed
+// half-pair target region with a margin on every side, rows padded to whole
+// 16-byte groups from the 4-byte aligned column at or below the region).
 OT_HD inline size_t lk_lds_bytes(int win, int R, int margin) {
     const int nseg = lk_nseg(win);
     const int RR = nseg * R + 1, TW = win + 1, PR = RR + 2, PW = 4 * (((TW + 4) >> 2) + 1);
+    const int SC = TW + 2 * margin, SP = 4 * (((SC + 3) >> 2) + 1);
     const size_t setup = (size_t)((PR * PW + 15) & ~15) + (size_t)RR * TW * 8;
-    const size_t iter = (size_t)(RR + 2 * margin) * (TW + 2 * margin) * 8;
+    const size_t iter = (size_t)(RR + 2 * margin) * SP * 4;
     return setup > iter ? setup : iter;
 }
 

@@ -7,9 +7,8 @@
 
 namespace ot {
 
-// Level l of a pyramid from level l-1.
-hipError_t launch_pyr_level(const uint8_t* src, int sw, int sh, int sp, uint8_t* dst, int dw,
-                            int dh, int dp, hipStream_t stream);
+// Levels l0+1 .. l0+K (K <= PYR_FUSE) of a pyramid from level l0.
+hipError_t launch_pyr_stage(const DevPyr& P, int l0, int K, hipStream_t stream);
 
 // Template row count the tracker uses for a window (0 = unsupported).
 int lk_template_rows(int win);
@@ -23,8 +22,7 @@ hipError_t launch_box(const float* boxes, int m, const int32_t* box_id, const fl
                       int32_t* out_count, hipStream_t stream);
 
 // Batched stages over a device table (layout TableLayout::make(cap)).
-hipError_t launch_batch_pyr(const uint8_t* table, int cap, int level, int grid,
-                            hipStream_t stream);
+hipError_t launch_batch_pyr(const uint8_t* table, int cap, int l0, int grid, hipStream_t stream);
 hipError_t launch_batch_lk(const uint8_t* table, int cap, int win, int margin, int grid,
                            bool persistent, hipStream_t stream);
 hipError_t launch_batch_box(const uint8_t* table, int cap, int grid, hipStream_t stream);

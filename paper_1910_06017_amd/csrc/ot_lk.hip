@@ -1,6 +1,6 @@
 // ot_lk.hip -- Lucas-Kanade tracking kernels for gfx950: one wave64 per point,
 // single-pyramid-pair and batched (flattened multi-stream table) forms.
-#include "ot_device.hpp"
+#include "ot_lk_dev.hpp"
 #include "ot_launch.hpp"
 
 // Optional occupancy target (waves per SIMD) for the tracking kernels.

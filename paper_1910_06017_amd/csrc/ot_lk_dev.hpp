@@ -1,0 +1,509 @@
+// ot_lk_dev.hpp -- gfx950 device code of the per-point pyramidal Lucas-Kanade
+// tracker (one wave64 per point) and its paired wave reductions.
+#pragma once
+#include "ot_device.hpp"
+
+// Clamped-byte staging near level edges keeps this many loads per lane in
+// flight (registers vs latency).
+#ifndef OT_STAGE_BATCH
+#define OT_STAGE_BATCH 4
+#endif
+
+namespace ot {
+
+// ---------------------------------------------------------------------------
+// Paired and quadruple wave sums using the gfx950 lane-swap instructions:
+// v_permlane32_swap folds the upper half-wave of one value onto the lower
+// half of another, v_permlane16_swap does the same for 16-lane rows, so two
+// (or four) sums share one DPP row reduction.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned fbits(float v) { return __builtin_bit_cast(unsigned, v); }
+__device__ __forceinline__ float ubits(unsigned v) { return __builtin_bit_cast(float, v); }
+
+__device__ __forceinline__ float row_sum16(float t) {
+    t += dpp_f<0xB1>(t);   // quad_perm [1,0,3,2]
+    t += dpp_f<0x4E>(t);   // quad_perm [2,3,0,1]
+    t += dpp_f<0x141>(t);  // row_half_mirror
+    t += dpp_f<0x140>(t);  // row_mirror
+    return t;
+}
+
+// (sum of a, sum of b) over the 64 lanes, wave-uniform.
+__device__ __forceinline__ void wave_sum2(float a, float b, float& sa, float& sb) {
+    const auto r = __builtin_amdgcn_permlane32_swap(fbits(a), fbits(b), false, false);
+    const float s = ubits(r[0]) + ubits(r[1]);  // lanes 0-31: a, lanes 32-63: b
+    const auto q = __builtin_amdgcn_permlane16_swap(fbits(s), fbits(s), false, false);
+    const float t = row_sum16(ubits(q[0]) + ubits(q[1]));  // rows 0,1: a; rows 2,3: b
+    sa = ubits(__builtin_amdgcn_readlane(fbits(t), 0));
+    sb = ubits(__builtin_amdgcn_readlane(fbits(t), 32));
+}
+
+// Sums of a, b, c, d over the 64 lanes, wave-uniform.
+__device__ __forceinline__ void wave_sum4(float a, float b, float c, float d, float& sa, float& sb,
+                                          float& sc, float& sd) {
+    const auto r1 = __builtin_amdgcn_permlane32_swap(fbits(a), fbits(b), false, false);
+    const auto r2 = __builtin_amdgcn_permlane32_swap(fbits(c), fbits(d), false, false);
+    const float s1 = ubits(r1[0]) + ubits(r1[1]);  // a | b
+    const float s2 = ubits(r2[0]) + ubits(r2[1]);  // c | d
+    const auto q = __builtin_amdgcn_permlane16_swap(fbits(s1), fbits(s2), false, false);
+    const float t = row_sum16(ubits(q[0]) + ubits(q[1]));  // rows: a, c, b, d
+    sa = ubits(__builtin_amdgcn_readlane(fbits(t), 0));
+    sc = ubits(__builtin_amdgcn_readlane(fbits(t), 16));
+    sb = ubits(__builtin_amdgcn_readlane(fbits(t), 32));
+    sd = ubits(__builtin_amdgcn_readlane(fbits(t), 48));
+}
+
+// ---------------------------------------------------------------------------
+// Lucas-Kanade for one point, one wave64 per point.
+//
+// Lane mapping: the win x win window is split into win columns x nseg row
+// segments; lane = seg * win + col owns the R consecutive window rows
+// seg*R .. seg*R+R-1 of column col (lanes past win*nseg own nothing).  Each
+// lane keeps its template, x- and y-gradient samples in registers, so a
+// Lucas-Kanade iteration reads only the target image.
+//
+// LDS (per wave): during a level's set-up, the raw template patch (uint8,
+// rows starting at a 4-byte aligned column) and the Scharr gradients at the
+// bilinear tap grid; during iterations, the target region with a `margin`
+// border, stored as (J[x], J[x+1]-J[x]) pairs so each bilinear row blend is
+// one FMA.  Regions are restaged only when the estimate leaves the margin.
+// Global reads are issued in batches before their LDS writes, as aligned
+// dwords when the region lies inside the level and as clamped bytes near
+// its edges.
+// ---------------------------------------------------------------------------
+struct LkGeom {
+    int win, r, nseg, RR, TW, PR, PW, M, SC, SR, SP;
+    __device__ LkGeom(int win_, int R, int margin) {
+        win = win_;
+        r = win >> 1;
+        nseg = min(win, max(1, 64 / win));
+        RR = nseg * R + 1;               // tap rows held (>= win + 1)
+        TW = win + 1;                    // tap columns
+        PR = RR + 2;                     // template patch rows
+        PW = 4 * (((TW + 4) >> 2) + 1);  // template patch row bytes
+        M = margin;
+        SC = TW + 2 * M;
+        SR = RR + 2 * M;
+        SP = 4 * (((SC + 3) >> 2) + 1);  // target row entries (16-byte rows)
+    }
+};
+
+// Target region, stored as packed half pairs (J[y][x], J[y][x+1] - J[y][x]):
+// both are integers of magnitude <= 255, exact in binary16, and a bilinear
+// row blend is then one mixed-precision FMA on the pair.  Rows start at the
+// 4-byte aligned column a0 = sx0 & ~3 and hold SP entries; entry
+// (rr, (sx0 & 3) + cc) covers y = clamp(sy0 + rr), x = clamp(sx0 + cc) for
+// rr < SR, cc < SC (SP >= 4 * (((SC + 3) >> 2) + 1)).
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_pair(float j, float dj) {
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(j, dj));
+}
+
+// Horizontal blend J[x] + bx * (J[x+1] - J[x]) of one packed entry.
+__device__ __forceinline__ float blend_pair(uint32_t e, float bx) {
+    const half2_t h = __builtin_bit_cast(half2_t, e);
+    return fmaf(bx, (float)h.y, (float)h.x);
+}
+
+__device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int w, int h, int jp,
+                                             int sx0, int sy0, int SR, int SC, int SP,
+                                             uint32_t* __restrict__ jr, int lane) {
+    const int a0 = sx0 & ~3;
+    const int nd = ((sx0 + SC - a0) >> 2) + 1;  // dwords covering columns a0 .. sx0+SC
+    const bool fast = a0 >= 0 && sy0 >= 0 && a0 + 4 * nd <= w && sy0 + SR <= h &&
+                      ((reinterpret_cast<uintptr_t>(Jl) | (uintptr_t)jp) & 3) == 0;
+    if (fast) {
+        // one dword (4 pixels) per lane and row; the fifth pixel of the last
+        // entry comes from the next lane (junk for the row's last dword, whose
+        // last entry lies past column SC - 1 and is never read)
+        const int rps = 64 / nd;
+        const int lr = lane / nd, kk = lane - lr * nd;
+        const bool lane_ok = lr < rps;
+        const int steps = (SR + rps - 1) / rps;
+        const uint8_t* __restrict__ base = Jl + (size_t)sy0 * jp + a0 + 4 * kk;
+        uint32_t* __restrict__ dst = jr + lr * SP + 4 * kk;
+        for (int s0 = 0; s0 < steps; s0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int rr = lr + (s0 + s) * rps;
+                v[s] = (lane_ok && rr < SR)
+                           ? *reinterpret_cast<const uint32_t*>(base + (size_t)rr * jp)
+                           : 0u;
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const uint32_t nx = __shfl_down(v[s], 1, 64);
+                const int rr = lr + (s0 + s) * rps;
+                if (lane_ok && rr < SR) {
+                    const float b0 = (float)(v[s] & 255u), b1 = (float)((v[s] >> 8) & 255u);
+                    const float b2 = (float)((v[s] >> 16) & 255u), b3 = (float)(v[s] >> 24);
+                    const float b4 = (float)(nx & 255u);
+                    uint4 q;
+                    q.x = pack_pair(b0, b1 - b0);
+                    q.y = pack_pair(b1, b2 - b1);
+                    q.z = pack_pair(b2, b3 - b2);
+                    q.w = pack_pair(b3, b4 - b3);
+                    *reinterpret_cast<uint4*>(dst + (s0 + s) * rps * SP) = q;
+                }
+            }
+        }
+    } else {
+        const int off = sx0 - a0;
+        const int dr = 64 / SC, dc = 64 - dr * SC;
+        int r = lane / SC, c = lane - r * SC;
+        const int nk = (SR * SC + 63) >> 6;
+        for (int kb = 0; kb < nk; kb += OT_STAGE_BATCH) {
+            int idx[OT_STAGE_BATCH];
+            uint32_t p0[OT_STAGE_BATCH], p1[OT_STAGE_BATCH];
+#pragma unroll
+            for (int s = 0; s < OT_STAGE_BATCH; ++s) {
+                idx[s] = -1;
+                p0[s] = p1[s] = 0;
+                if (kb + s < nk && r < SR) {
+                    const uint8_t* row = Jl + (size_t)clampi(sy0 + r, 0, h - 1) * jp;
+                    p0[s] = row[clampi(sx0 + c, 0, w - 1)];
+                    p1[s] = row[clampi(sx0 + c + 1, 0, w - 1)];
+                    idx[s] = r * SP + off + c;
+                }
+                c += dc;
+                r += dr;
+                if (c >= SC) {
+                    c -= SC;
+                    ++r;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < OT_STAGE_BATCH; ++s)
+                if (idx[s] >= 0) {
+                    const float f0 = (float)p0[s], f1 = (float)p1[s];
+                    jr[idx[s]] = pack_pair(f0, f1 - f0);
+                }
+        }
+    }
+}
+
+// Template patch: rows y0-1 .. y0+PR-2, columns x0-1 .. x0+TW of the level
+// (clamped), stored with its row starting at column a0p = (x0-1) & ~3, so
+// patch[pr * PW + (x - a0p)] holds I[clamp(y0-1+pr)][clamp(x)].
+__device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int w, int h, int ip,
+                                            int x0, int y0, const LkGeom& g,
+                                            uint8_t* __restrict__ patch, int lane) {
+    const int xs = x0 - 1, ys = y0 - 1;
+    const int a0 = xs & ~3;
+    const int nd = ((x0 + g.TW - a0) >> 2) + 1;  // dwords covering a0 .. x0+TW
+    const bool fast = a0 >= 0 && ys >= 0 && a0 + 4 * nd <= w && ys + g.PR <= h &&
+                      ((reinterpret_cast<uintptr_t>(Il) | (uintptr_t)ip) & 3) == 0;
+    if (fast) {
+        const int rps = 64 / nd;
+        const int lr = lane / nd, kk = lane - lr * nd;
+        const bool lane_ok = lr < rps;
+        const int steps = (g.PR + rps - 1) / rps;
+        const uint8_t* __restrict__ base = Il + (size_t)ys * ip + a0 + 4 * kk;
+        for (int s0 = 0; s0 < steps; s0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int rr = lr + (s0 + s) * rps;
+                v[s] = (lane_ok && rr < g.PR)
+                           ? *reinterpret_cast<const uint32_t*>(base + (size_t)rr * ip)
+                           : 0u;
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int rr = lr + (s0 + s) * rps;
+                if (lane_ok && rr < g.PR)
+                    *reinterpret_cast<uint32_t*>(patch + rr * g.PW + 4 * kk) = v[s];
+            }
+        }
+    } else {
+        const int cols = g.TW + 2, po = xs - a0;
+        const int dr = 64 / cols, dc = 64 - dr * cols;
+        int r = lane / cols, c = lane - r * cols;
+        const int nk = (g.PR * cols + 63) >> 6;
+        for (int kb = 0; kb < nk; kb += 8) {
+            int idx[8];
+            uint32_t p[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                idx[s] = -1;
+                p[s] = 0;
+                if (kb + s < nk && r < g.PR) {
+                    p[s] = Il[(size_t)clampi(ys + r, 0, h - 1) * ip + clampi(xs + c, 0, w - 1)];
+                    idx[s] = r * g.PW + po + c;
+                }
+                c += dc;
+                r += dr;
+                if (c >= cols) {
+                    c -= cols;
+                    ++r;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                if (idx[s] >= 0) patch[idx[s]] = (uint8_t)p[s];
+        }
+    }
+}
+
+struct LkResult {
+    float nx, ny, err;
+    int status;
+};
+
+template <int R, class PyrRef>
+__device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, float ux, float uy,
+                                             int L, int iters, float eps2, float min_eig,
+                                             const LkGeom& g, unsigned char* __restrict__ smem,
+                                             uint8_t* iters_out, float* lam_out) {
+    const int lane = threadIdx.x & 63;
+    const int used = g.win * g.nseg;
+    const bool lvalid = lane < used;
+    const int col = lvalid ? lane % g.win : 0;
+    const int seg = lvalid ? lane / g.win : 0;
+    const int row0 = seg * R;
+    const int nrows = lvalid ? max(0, min(R, g.win - row0)) : 0;
+    const float N = (float)(g.win * g.win);
+
+    LkResult res;
+    res.nx = ux;
+    res.ny = uy;
+    res.err = -1.0f;
+    res.status = 0;
+    const int W0 = P.w[0], H0 = P.h[0];
+    if (!(ux >= 0.0f && uy >= 0.0f && ux <= (float)(W0 - 1) && uy <= (float)(H0 - 1))) {
+        if (lane == 0)
+            for (int l = 0; l < L; ++l) {
+                if (iters_out) iters_out[l] = 0;
+                if (lam_out) lam_out[l] = 0.0f;
+            }
+        return res;  // also catches NaN
+    }
+
+    float A[R], X[R], Y[R];
+    float gx = 0.0f, gy = 0.0f;
+    float nux = 0.0f, nuy = 0.0f;
+    uint32_t* jr = reinterpret_cast<uint32_t*>(smem);
+    uint8_t* patch = smem;
+    float2* grad = reinterpret_cast<float2*>(smem + ((g.PR * g.PW + 15) & ~15));
+    int sx0 = 0, sy0 = 0;  // origin of the staged target region (level coords)
+    int soff = 0;          // sx0 & 3: column of sx0 in a staged row
+
+    for (int l = L - 1; l >= 0; --l) {
+        const uint8_t* __restrict__ Il = P.lvl[l];
+        const uint8_t* __restrict__ Jl = Q.lvl[l];
+        const int w = P.w[l], h = P.h[l], ip = P.pitch[l], jp = Q.pitch[l];
+        const float sc = __builtin_ldexpf(1.0f, -l);
+        const float cx = ux * sc, cy = uy * sc;
+        const float flx = floorf(cx), fly = floorf(cy);
+        const float ax = cx - flx, ay = cy - fly;
+        const int x0 = (int)flx - g.r, y0 = (int)fly - g.r;  // top-left tap
+        const int a0p = (x0 - 1) & ~3;
+
+        // ---- template patch
+        stage_patch(Il, w, h, ip, x0, y0, g, patch, lane);
+        __syncthreads();
+        // ---- Scharr gradients at the tap grid: the gradient image is defined on
+        // the level's pixels and read at clamped indices, so a tap outside the
+        // level takes the gradient of the nearest edge pixel.
+        if (x0 >= 1 && x0 + g.TW <= w - 1 && y0 >= 1 && y0 + g.RR <= h - 1) {
+            // interior: no clamping; each lane slides a 3x3 window down a
+            // column of taps, so a tap costs three byte reads.  With
+            // d = right - left and t = 3 left + 10 centre + 3 right per row:
+            // Sx = 3 d(y-1) + 10 d(y) + 3 d(y+1),  Sy = t(y+1) - t(y-1).
+            const int ncg = 64 / g.TW;
+            const int GR = (g.RR + ncg - 1) / ncg;
+            const int tx = lane % g.TW, rg = lane / g.TW;
+            if (rg < ncg) {
+                const int ty0 = rg * GR, ty1 = min(ty0 + GR, g.RR);
+                const uint8_t* pp = patch + ty0 * g.PW + (x0 + tx - a0p);
+                int vl = pp[-1], vc = pp[0], vr = pp[1];
+                int d0 = vr - vl, t0 = 3 * (vl + vr) + 10 * vc;
+                vl = pp[g.PW - 1], vc = pp[g.PW], vr = pp[g.PW + 1];
+                int d1 = vr - vl, t1 = 3 * (vl + vr) + 10 * vc;
+                for (int ty = ty0; ty < ty1; ++ty) {
+                    const uint8_t* q = pp + (ty - ty0 + 2) * g.PW;
+                    vl = q[-1], vc = q[0], vr = q[1];
+                    const int d2 = vr - vl, t2 = 3 * (vl + vr) + 10 * vc;
+                    const int sxv = 3 * (d0 + d2) + 10 * d1;
+                    const int syv = t2 - t0;
+                    grad[ty * g.TW + tx] = make_float2((float)sxv * (1.0f / 32.0f), (float)syv * (1.0f / 32.0f));
+                    d0 = d1;
+                    d1 = d2;
+                    t0 = t1;
+                    t1 = t2;
+                }
+            }
+        } else {
+            const int dr = 64 / g.TW, dc = 64 - dr * g.TW;
+            int ty = lane / g.TW, tx = lane - ty * g.TW;
+            const int ntap = g.RR * g.TW;
+            for (int e = lane; e < ntap; e += 64) {
+                const int qx = clampi(x0 + tx, 0, w - 1), qy = clampi(y0 + ty, 0, h - 1);
+                const int xl = max(qx - 1, 0) - a0p, xc = qx - a0p, xr = min(qx + 1, w - 1) - a0p;
+                const int yu = (max(qy - 1, 0) - (y0 - 1)) * g.PW;
+                const int yc = (qy - (y0 - 1)) * g.PW;
+                const int yd = (min(qy + 1, h - 1) - (y0 - 1)) * g.PW;
+                const int pul = patch[yu + xl], puc = patch[yu + xc], pur = patch[yu + xr];
+                const int pcl = patch[yc + xl], pcr = patch[yc + xr];
+                const int pdl = patch[yd + xl], pdc = patch[yd + xc], pdr = patch[yd + xr];
+                const int sxv = 3 * (pur - pul) + 10 * (pcr - pcl) + 3 * (pdr - pdl);
+                const int syv = 3 * (pdl - pul) + 10 * (pdc - puc) + 3 * (pdr - pur);
+                grad[e] = make_float2((float)sxv * (1.0f / 32.0f), (float)syv * (1.0f / 32.0f));
+                tx += dc;
+                ty += dr;
+                if (tx >= g.TW) {
+                    tx -= g.TW;
+                    ++ty;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- bilinear template and gradients of this lane's strip
+        {
+            const int pcol = x0 + col - a0p;  // patch column of tap column `col`
+            float pi = 0.0f, px = 0.0f, py = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= R; ++k) {
+                const int ty = row0 + k;
+                const float i0 = (float)patch[(ty + 1) * g.PW + pcol];
+                const float i1 = (float)patch[(ty + 1) * g.PW + pcol + 1];
+                const float2 g0 = grad[ty * g.TW + col];
+                const float2 g1 = grad[ty * g.TW + col + 1];
+                const float ri = fmaf(ax, i1 - i0, i0);
+                const float rx = fmaf(ax, g1.x - g0.x, g0.x);
+                const float ry = fmaf(ax, g1.y - g0.y, g0.y);
+                if (k > 0) {
+                    const bool v = (k - 1) < nrows;
+                    A[k - 1] = v ? fmaf(ay, ri - pi, pi) : 0.0f;
+                    X[k - 1] = v ? fmaf(ay, rx - px, px) : 0.0f;
+                    Y[k - 1] = v ? fmaf(ay, ry - py, py) : 0.0f;
+                }
+                pi = ri;
+                px = rx;
+                py = ry;
+            }
+        }
+        float gxx = 0.0f, gxy = 0.0f, gyy = 0.0f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            gxx = fmaf(X[k], X[k], gxx);
+            gxy = fmaf(X[k], Y[k], gxy);
+            gyy = fmaf(Y[k], Y[k], gyy);
+        }
+        {
+            float unused;
+            wave_sum4(gxx, gxy, gyy, 0.0f, gxx, gxy, gyy, unused);
+        }
+        const float hm = 0.5f * (gxx + gyy), hd = 0.5f * (gxx - gyy);
+        const float lam = (hm - sqrtf(hd * hd + gxy * gxy)) / N;
+        if (lane == 0 && lam_out) lam_out[l] = lam;
+        if (!(lam >= min_eig)) {
+            if (lane == 0)
+                for (int k = l; k >= 0; --k) {
+                    if (iters_out) iters_out[k] = 0;
+                    if (lam_out && k < l) lam_out[k] = 0.0f;
+                }
+            const float s = __builtin_ldexpf(1.0f, l);
+            res.nx = ux + gx * s;
+            res.ny = uy + gy * s;
+            return res;
+        }
+        const float idet = 1.0f / (gxx * gyy - gxy * gxy);
+        __syncthreads();  // the set-up LDS is reused for the target region
+
+        // Positions are clamped before the integer conversion; past the bounds
+        // every tap already reads the level's edge, so the samples are unchanged.
+        const float lo = -(float)(g.win + 8), hix = (float)(w + g.win + 8), hiy = (float)(h + g.win + 8);
+        nux = 0.0f;
+        nuy = 0.0f;
+        {
+            const float qx = fminf(fmaxf(cx + gx, lo), hix), qy = fminf(fmaxf(cy + gy, lo), hiy);
+            sx0 = (int)floorf(qx) - g.r - g.M;
+            sy0 = (int)floorf(qy) - g.r - g.M;
+            stage_target(Jl, w, h, jp, sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
+            soff = sx0 & 3;
+            __syncthreads();
+        }
+        int it = 0;
+        while (it < iters) {
+            const float qx = fminf(fmaxf(cx + gx + nux, lo), hix);
+            const float qy = fminf(fmaxf(cy + gy + nuy, lo), hiy);
+            const float fqx = floorf(qx), fqy = floorf(qy);
+            const float bxw = qx - fqx, byw = qy - fqy;
+            int ox = (int)fqx - g.r - sx0, oy = (int)fqy - g.r - sy0;
+            if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
+                __syncthreads();
+                sx0 += ox - g.M;
+                sy0 += oy - g.M;
+                stage_target(Jl, w, h, jp, sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
+                soff = sx0 & 3;
+                __syncthreads();
+                ox = g.M;
+                oy = g.M;
+            }
+            const uint32_t* __restrict__ jb = jr + (oy + row0) * g.SP + soff + ox + col;
+            float rp = blend_pair(jb[0], bxw);
+            float bx = 0.0f, by = 0.0f;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const float rn = blend_pair(jb[(k + 1) * g.SP], bxw);
+                const float d = A[k] - fmaf(byw, rn - rp, rp);
+                bx = fmaf(d, X[k], bx);
+                by = fmaf(d, Y[k], by);
+                rp = rn;
+            }
+            wave_sum2(bx, by, bx, by);
+            const float ex = (gyy * bx - gxy * by) * idet;
+            const float ey = (gxx * by - gxy * bx) * idet;
+            nux += ex;
+            nuy += ey;
+            ++it;
+            if (ex * ex + ey * ey < eps2) break;
+        }
+        if (lane == 0 && iters_out) iters_out[l] = (uint8_t)min(it, 255);
+        if (l > 0) {
+            gx = 2.0f * (gx + nux);
+            gy = 2.0f * (gy + nuy);
+        }
+    }
+    // level 0: flow = g + nu
+    const float fx = gx + nux, fy = gy + nuy;
+    const float nx = ux + fx, ny = uy + fy;
+    res.nx = nx;
+    res.ny = ny;
+    if (!(nx >= 0.0f && ny >= 0.0f && nx <= (float)(W0 - 1) && ny <= (float)(H0 - 1))) return res;
+
+    // ---- err: mean |I - J| over the level-0 window at the final position
+    {
+        const float fqx = floorf(nx), fqy = floorf(ny);
+        const float bxw = nx - fqx, byw = ny - fqy;
+        int ox = (int)fqx - g.r - sx0, oy = (int)fqy - g.r - sy0;
+        if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
+            __syncthreads();
+            sx0 += ox - g.M;
+            sy0 += oy - g.M;
+            stage_target(Q.lvl[0], P.w[0], P.h[0], Q.pitch[0], sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
+            soff = sx0 & 3;
+            __syncthreads();
+            ox = g.M;
+            oy = g.M;
+        }
+        const uint32_t* __restrict__ jb = jr + (oy + row0) * g.SP + soff + ox + col;
+        float rp = blend_pair(jb[0], bxw);
+        float e = 0.0f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float rn = blend_pair(jb[(k + 1) * g.SP], bxw);
+            const float d = A[k] - fmaf(byw, rn - rp, rp);
+            e += (k < nrows) ? fabsf(d) : 0.0f;
+            rp = rn;
+        }
+        res.err = wave_sum(e) / N;
+    }
+    res.status = 1;
+    return res;
+}
+
+}  // namespace ot

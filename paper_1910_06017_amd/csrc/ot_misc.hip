@@ -1,22 +1,20 @@
 // ot_misc.hip -- pyramid reduce and box-median kernels for gfx950, single and
 // batched forms.
-#include "ot_device.hpp"
+#include "ot_box.hpp"
+#include "ot_pyr.hpp"
 #include "ot_launch.hpp"
 
 namespace ot {
 
-__global__ __launch_bounds__(PYR_THREADS) void k_pyr_level(const uint8_t* __restrict__ src, int sw,
-                                                           int sh, int sp, uint8_t* __restrict__ dst,
-                                                           int dw, int dh, int dp) {
+__global__ __launch_bounds__(PYR_THREADS) void k_pyr_stage(DevPyr P, int l0, int K) {
     __shared__ PyrSmem sm;
-    pyr_tile(src, sw, sh, sp, dst, dw, dh, dp, blockIdx.x, blockIdx.y, sm);
+    pyr_fused(P, l0, K, blockIdx.x, blockIdx.y, sm);
 }
 
-hipError_t launch_pyr_level(const uint8_t* src, int sw, int sh, int sp, uint8_t* dst, int dw,
-                            int dh, int dp, hipStream_t stream) {
-    const dim3 grid((dw + PYR_TW - 1) / PYR_TW, (dh + PYR_TH - 1) / PYR_TH);
-    hipLaunchKernelGGL(k_pyr_level, grid, dim3(PYR_THREADS), 0, stream, src, sw, sh, sp, dst, dw,
-                       dh, dp);
+hipError_t launch_pyr_stage(const DevPyr& P, int l0, int K, hipStream_t stream) {
+    const int top = l0 + K;
+    const dim3 grid((P.w[top] + PYR_FTW - 1) / PYR_FTW, (P.h[top] + PYR_FTH - 1) / PYR_FTH);
+    hipLaunchKernelGGL(k_pyr_stage, grid, dim3(PYR_THREADS), 0, stream, P, l0, K);
     return hipGetLastError();
 }
 
@@ -29,30 +27,27 @@ __device__ __forceinline__ int find_item(const int32_t* __restrict__ prefix, int
     return lo;
 }
 
-// Level `level` of every job's next pyramid: one workgroup per tile of the
-// flattened tile list.
+// The fused stage starting at level l0 of every job's next pyramid: one
+// workgroup per top-level tile of the flattened tile list (kept at index
+// l0 + 1 of the table's per-level tile arrays).
 __global__ __launch_bounds__(PYR_THREADS) void k_batch_pyr(const uint8_t* __restrict__ table,
-                                                           int cap, int level) {
+                                                           int cap, int l0) {
     __shared__ PyrSmem sm;
     const TableLayout T = TableLayout::make(cap);
     const TableHdr& hd = *reinterpret_cast<const TableHdr*>(table);
     const int t = blockIdx.x;
-    if (t >= hd.total_tiles[level]) return;
-    const int32_t* tp = reinterpret_cast<const int32_t*>(table + T.tile_prefix) + (size_t)level * (cap + 1);
-    const int32_t* tc = reinterpret_cast<const int32_t*>(table + T.tile_cols) + (size_t)level * cap;
+    if (t >= hd.total_tiles[l0 + 1]) return;
+    const int32_t* tp = reinterpret_cast<const int32_t*>(table + T.tile_prefix) + (size_t)(l0 + 1) * (cap + 1);
+    const int32_t* tc = reinterpret_cast<const int32_t*>(table + T.tile_cols) + (size_t)(l0 + 1) * cap;
     const int j = __builtin_amdgcn_readfirstlane(find_item(tp, hd.njobs, t));
     const DevJob& jb = reinterpret_cast<const DevJob*>(table + T.jobs)[j];
     const int lt = t - tp[j];
     const int cols = tc[j];
-    const DevPyr& P = jb.next;
-    pyr_tile(P.lvl[level - 1], P.w[level - 1], P.h[level - 1], P.pitch[level - 1],
-             const_cast<uint8_t*>(P.lvl[level]), P.w[level], P.h[level], P.pitch[level],
-             lt % cols, lt / cols, sm);
+    pyr_fused(jb.next, l0, pyr_stage_steps(jb.levels, l0), lt % cols, lt / cols, sm);
 }
 
-hipError_t launch_batch_pyr(const uint8_t* table, int cap, int level, int grid,
-                            hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch_pyr, dim3(grid), dim3(PYR_THREADS), 0, stream, table, cap, level);
+hipError_t launch_batch_pyr(const uint8_t* table, int cap, int l0, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_pyr, dim3(grid), dim3(PYR_THREADS), 0, stream, table, cap, l0);
     return hipGetLastError();
 }
 

@@ -153,8 +153,12 @@ def test_batch_pack_table(L):
     assert rc == 0
     hdr = buf[:64].view(np.int32)
     assert hdr[0] == 3 and hdr[1] == 2600 and hdr[2] == 10 and hdr[3] == 4
-    # tiles of level 1: ceil(360/64)*ceil(288/16) + ceil(960/64)*ceil(540/16) + ceil(640/64)*ceil(360/16)
-    assert hdr[4 + 1] == 6 * 18 + 15 * 34 + 10 * 23
+    # fused pyramid stage from level 0 (index 1): 16x8 tiles of level 3 of each job,
+    # ceil(90/16)*ceil(72/8) + ceil(240/16)*ceil(135/8) + ceil(160/16)*ceil(90/8);
+    # stage from level 3 (index 4): level 4 of the 5-level job only, ceil(120/16)*ceil(68/8)
+    assert hdr[4 + 1] == 6 * 9 + 15 * 17 + 10 * 12
+    assert hdr[4 + 2] == 0 and hdr[4 + 3] == 0
+    assert hdr[4 + 4] == 8 * 9
     assert nxt[1].levels == 5 and nxt[1].level[0] == FAKE + (1 << 28)
     assert nxt[2].w[3] == 160
     # capacity and validation errors leave nothing half-written
