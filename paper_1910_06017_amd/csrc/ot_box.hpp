@@ -8,9 +8,8 @@ namespace ot {
 // Per-box median of point displacements, one BOX_THREADS workgroup per box.
 // The box's tracked displacements are gathered into LDS; the x and y values
 // at ranks (c-1)/2 and c/2 then come from a one-wave register sort per axis
-// (c <= BOX_WAVE_SORT), a bitonic sort in LDS (c <= BOX_SORT_MAX), or an
-// exact radix selection (four 8-bit passes over order-preserving integer
-// keys, four selections at once) for larger boxes.
+// (c <= BOX_WAVE_SORT) or, for larger boxes, an exact radix selection (four
+// 8-bit passes over order-preserving integer keys, four selections at once).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t f2key(float f) {
     const uint32_t u = __float_as_uint(f);
@@ -107,34 +106,6 @@ __device__ __forceinline__ void box_radix_select(bool in_lds, BoxSmem& sm, int c
     }
 }
 
-// Ascending bitonic sort of dx[0..np2) and dy[0..np2) in LDS (np2 a power of two).
-__device__ __forceinline__ void box_bitonic(BoxSmem& sm, int np2) {
-    const int tid = threadIdx.x;
-    for (int k = 2; k <= np2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = tid; t < (np2 >> 1); t += BOX_THREADS) {
-                const int i = 2 * t - (t & (j - 1)), p = i + j;
-                const bool up = (i & k) == 0;
-                const float a = sm.dx[i], bb = sm.dx[p];
-                if ((a > bb) == up) {
-                    sm.dx[i] = bb;
-                    sm.dx[p] = a;
-                }
-                const float c = sm.dy[i], d = sm.dy[p];
-                if ((c > d) == up) {
-                    sm.dy[i] = d;
-                    sm.dy[p] = c;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// One wave sorts 512 values held as v[r] of lane l = element 8*l + r
-// (ascending bitonic network): partners 8 or more apart are exchanged across
-// lanes with shuffles, closer partners inside a lane's registers; no LDS and
-// no barrier.  x and y are sorted side by side.
 // Ascending bitonic sort of 512 values held 8 per lane (value i in lane i/8,
 // register i%8) by one wave: the compare distances of 8 and more are lane
 // exchanges, the smaller ones stay inside a lane's registers.
@@ -283,17 +254,6 @@ __device__ __forceinline__ void box_median(const float* __restrict__ boxes, int 
         __syncthreads();
         mx = sm.med[0];
         my = sm.med[1];
-    } else if (c > 0 && c <= BOX_SORT_MAX) {
-        int np2 = 64;
-        while (np2 < c) np2 <<= 1;
-        for (int i = c + tid; i < np2; i += BOX_THREADS) {
-            sm.dx[i] = __builtin_inff();
-            sm.dy[i] = __builtin_inff();
-        }
-        __syncthreads();
-        box_bitonic(sm, np2);
-        mx = 0.5f * (sm.dx[(c - 1) / 2] + sm.dx[c / 2]);
-        my = 0.5f * (sm.dy[(c - 1) / 2] + sm.dy[c / 2]);
     } else if (c > 0) {
         box_radix_select(c <= BOX_CAP, sm, c, b, box_id, status, pts, next_pts, n);
         mx = 0.5f * (key2f(sm.prefix[0]) + key2f(sm.prefix[1]));

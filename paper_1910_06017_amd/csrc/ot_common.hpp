@@ -14,7 +14,7 @@
 
 namespace ot {
 
-// Pyramid: one launch reduces up to PYR_FUSE levels; a 256-thread workgroup
+// Pyramid: one launch reduces up to PYR_FUSE levels; a PYR_THREADS workgroup
 // owns a PYR_FTW x PYR_FTH tile of the launch's top level and that tile's
 // footprint at the levels below it.
 #ifndef OT_PYR_FTW
@@ -24,7 +24,7 @@ namespace ot {
 #define OT_PYR_FTH 8
 #endif
 #ifndef OT_PYR_THREADS
-#define OT_PYR_THREADS 256
+#define OT_PYR_THREADS 1024
 #endif
 constexpr int PYR_FUSE = 3;
 constexpr int PYR_FTW = OT_PYR_FTW;
@@ -39,16 +39,13 @@ OT_HD inline int pyr_stage_steps(int levels, int l0) {
 
 // Box median: one 1024-thread workgroup per box; up to BOX_CAP point
 // displacements are gathered in LDS, larger boxes are re-scanned from memory.
-constexpr int BOX_THREADS = 1024;
-constexpr int BOX_CAP = 4096;
 #ifndef OT_BOX_WAVE_SORT
 #define OT_BOX_WAVE_SORT 512
 #endif
-#ifndef OT_BOX_SORT_MAX
-#define OT_BOX_SORT_MAX 4096
-#endif
-constexpr int BOX_WAVE_SORT = OT_BOX_WAVE_SORT;  // one wave per axis sorts in registers up to this
-constexpr int BOX_SORT_MAX = OT_BOX_SORT_MAX;    // bitonic sort in LDS up to this, radix select above
+constexpr int BOX_THREADS = 1024;
+constexpr int BOX_CAP = 6144;
+constexpr int BOX_WAVE_SORT = OT_BOX_WAVE_SORT;  // one wave per axis sorts in registers up to
+                                                 // this count, radix selection above
 
 constexpr int LK_DEFAULT_MARGIN = 4;
 constexpr int LK_MAX_MARGIN = 16;

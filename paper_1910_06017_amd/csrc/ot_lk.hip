@@ -13,7 +13,20 @@
 #define OT_LK_BOUNDS __launch_bounds__(64)
 #endif
 
+// Points map to waves in dispatch order (0), which deals neighbouring points
+// round-robin to the XCDs, or through the XCD-contiguous remap (1).  Points
+// of one box cost alike, so contiguous ranges leave some XCDs with the
+// expensive boxes; a frame pair's pyramids fit in every XCD's L2, so the
+// interleaved order loses no locality and balances the XCDs.
+#ifndef OT_LK_XCD_REMAP
+#define OT_LK_XCD_REMAP 0
+#endif
+
 namespace ot {
+
+__device__ __forceinline__ int lk_item(int b, int G) {
+    return OT_LK_XCD_REMAP ? xcd_remap(b, G) : b;
+}
 
 template <int R>
 __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restrict__ pts,
@@ -23,7 +36,7 @@ __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restr
                                                  uint8_t* __restrict__ iters_out,
                                                  float* __restrict__ lam_out) {
     extern __shared__ __align__(16) unsigned char lk_smem[];
-    const int i = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = lk_item(blockIdx.x, gridDim.x);
     if (i >= n) return;
     const float ux = uniform_f(pts[2 * i]), uy = uniform_f(pts[2 * i + 1]);
     const LkGeom g(prm.win, R, prm.margin);
@@ -76,7 +89,7 @@ __global__ OT_LK_BOUNDS void k_lk_batch(const uint8_t* __restrict__ table, int c
     extern __shared__ __align__(16) unsigned char lk_smem[];
     const TableLayout T = TableLayout::make(cap);
     const TableHdr& hd = *reinterpret_cast<const TableHdr*>(table);
-    const int i = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = lk_item(blockIdx.x, gridDim.x);
     if (i >= hd.total_pts) return;
     lk_batch_item<R>(table, T, hd, i, lk_smem);
 }

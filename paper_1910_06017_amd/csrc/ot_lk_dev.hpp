@@ -117,10 +117,10 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
         // one dword (4 pixels) per lane and row; the fifth pixel of the last
         // entry comes from the next lane (junk for the row's last dword, whose
         // last entry lies past column SC - 1 and is never read)
-        const int rps = 64 / nd;
-        const int lr = lane / nd, kk = lane - lr * nd;
+        const int rps = udiv_small(64, nd);
+        const int lr = udiv_small(lane, nd), kk = lane - lr * nd;
         const bool lane_ok = lr < rps;
-        const int steps = (SR + rps - 1) / rps;
+        const int steps = udiv_small(SR + rps - 1, rps);
         const uint8_t* __restrict__ base = Jl + (size_t)sy0 * jp + a0 + 4 * kk;
         uint32_t* __restrict__ dst = jr + lr * SP + 4 * kk;
         for (int s0 = 0; s0 < steps; s0 += 8) {
@@ -151,8 +151,8 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
         }
     } else {
         const int off = sx0 - a0;
-        const int dr = 64 / SC, dc = 64 - dr * SC;
-        int r = lane / SC, c = lane - r * SC;
+        const int dr = udiv_small(64, SC), dc = 64 - dr * SC;
+        int r = udiv_small(lane, SC), c = lane - r * SC;
         const int nk = (SR * SC + 63) >> 6;
         for (int kb = 0; kb < nk; kb += OT_STAGE_BATCH) {
             int idx[OT_STAGE_BATCH];
@@ -196,10 +196,10 @@ __device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int 
     const bool fast = a0 >= 0 && ys >= 0 && a0 + 4 * nd <= w && ys + g.PR <= h &&
                       ((reinterpret_cast<uintptr_t>(Il) | (uintptr_t)ip) & 3) == 0;
     if (fast) {
-        const int rps = 64 / nd;
-        const int lr = lane / nd, kk = lane - lr * nd;
+        const int rps = udiv_small(64, nd);
+        const int lr = udiv_small(lane, nd), kk = lane - lr * nd;
         const bool lane_ok = lr < rps;
-        const int steps = (g.PR + rps - 1) / rps;
+        const int steps = udiv_small(g.PR + rps - 1, rps);
         const uint8_t* __restrict__ base = Il + (size_t)ys * ip + a0 + 4 * kk;
         for (int s0 = 0; s0 < steps; s0 += 8) {
             uint32_t v[8];
@@ -219,8 +219,8 @@ __device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int 
         }
     } else {
         const int cols = g.TW + 2, po = xs - a0;
-        const int dr = 64 / cols, dc = 64 - dr * cols;
-        int r = lane / cols, c = lane - r * cols;
+        const int dr = udiv_small(64, cols), dc = 64 - dr * cols;
+        int r = udiv_small(lane, cols), c = lane - r * cols;
         const int nk = (g.PR * cols + 63) >> 6;
         for (int kb = 0; kb < nk; kb += 8) {
             int idx[8];
@@ -260,8 +260,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
     const int lane = threadIdx.x & 63;
     const int used = g.win * g.nseg;
     const bool lvalid = lane < used;
-    const int col = lvalid ? lane % g.win : 0;
-    const int seg = lvalid ? lane / g.win : 0;
+    const int seg = lvalid ? udiv_small(lane, g.win) : 0;
+    const int col = lvalid ? lane - seg * g.win : 0;
     const int row0 = seg * R;
     const int nrows = lvalid ? max(0, min(R, g.win - row0)) : 0;
     const float N = (float)(g.win * g.win);
@@ -312,9 +312,9 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             // column of taps, so a tap costs three byte reads.  With
             // d = right - left and t = 3 left + 10 centre + 3 right per row:
             // Sx = 3 d(y-1) + 10 d(y) + 3 d(y+1),  Sy = t(y+1) - t(y-1).
-            const int ncg = 64 / g.TW;
-            const int GR = (g.RR + ncg - 1) / ncg;
-            const int tx = lane % g.TW, rg = lane / g.TW;
+            const int ncg = udiv_small(64, g.TW);
+            const int GR = udiv_small(g.RR + ncg - 1, ncg);
+            const int rg = udiv_small(lane, g.TW), tx = lane - rg * g.TW;
             if (rg < ncg) {
                 const int ty0 = rg * GR, ty1 = min(ty0 + GR, g.RR);
                 const uint8_t* pp = patch + ty0 * g.PW + (x0 + tx - a0p);
@@ -336,8 +336,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                 }
             }
         } else {
-            const int dr = 64 / g.TW, dc = 64 - dr * g.TW;
-            int ty = lane / g.TW, tx = lane - ty * g.TW;
+            const int dr = udiv_small(64, g.TW), dc = 64 - dr * g.TW;
+            int ty = udiv_small(lane, g.TW), tx = lane - ty * g.TW;
             const int ntap = g.RR * g.TW;
             for (int e = lane; e < ntap; e += 64) {
                 const int qx = clampi(x0 + tx, 0, w - 1), qy = clampi(y0 + ty, 0, h - 1);

@@ -236,7 +236,10 @@ def test_deterministic(ops):
 # ------------------------------------------------------------------ box update
 def test_box_update_parity_same_inputs(ops):
     rng = np.random.default_rng(12)
-    for trial, (m, n) in enumerate([(1, 0), (3, 1), (5, 200), (20, 8000), (4, 20000)]):
+    # per-box tracked counts span the one-wave sort (<= 512), radix selection
+    # on the gathered values (<= 6144) and radix selection re-scanning memory
+    for trial, (m, n) in enumerate([(1, 0), (3, 1), (5, 200), (20, 8000), (4, 20000),
+                                    (2, 30000)]):
         boxes = rng.uniform(0, 500, (m, 4)).astype(np.float32)
         box_id = rng.integers(-1, m, n).astype(np.int32)
         pts = rng.uniform(0, 700, (n, 2)).astype(np.float32)
@@ -247,6 +250,28 @@ def test_box_update_parity_same_inputs(ops):
         wb, wc = oracle.box_update(boxes, box_id, pts, nxt, st)
         assert np.array_equal(oc.cpu().numpy(), wc)
         assert np.allclose(ob.cpu().numpy(), wb, atol=1e-4, rtol=0), trial
+
+
+def test_box_update_path_boundaries_and_ties(ops):
+    """Boxes with exactly 511, 512, 513, 6144 and 6145 tracked points (the
+    switch between the register sort, radix selection in LDS and radix
+    selection from memory), with many equal displacements, zeros and signs."""
+    rng = np.random.default_rng(13)
+    counts = [511, 512, 513, 6144, 6145, 2]
+    box_id = np.concatenate([np.full(c, b, np.int32) for b, c in enumerate(counts)])
+    n, m = box_id.size, len(counts)
+    rng.shuffle(box_id)
+    pts = rng.uniform(0, 700, (n, 2)).astype(np.float32)
+    d = rng.integers(-3, 4, (n, 2)).astype(np.float32) * 0.25   # few distinct values
+    d[rng.uniform(size=n) < 0.1] = 0.0
+    nxt = (pts + d).astype(np.float32)
+    st = np.ones(n, np.uint8)
+    boxes = rng.uniform(0, 500, (m, 4)).astype(np.float32)
+    ob, oc = ops.box_update(dev(boxes), dev(box_id), dev(pts), dev(nxt), dev(st))
+    torch.cuda.synchronize()
+    wb, wc = oracle.box_update(boxes, box_id, pts, nxt, st)
+    assert np.array_equal(oc.cpu().numpy(), wc)
+    assert np.allclose(ob.cpu().numpy(), wb, atol=1e-4, rtol=0)
 
 
 def test_box_update_end_to_end(ops):
