@@ -37,15 +37,13 @@ OT_HD inline int pyr_stage_steps(int levels, int l0) {
     return k < 0 ? 0 : (k > PYR_FUSE ? PYR_FUSE : k);
 }
 
-// Box median: one 1024-thread workgroup per box; up to BOX_CAP point
+// Box median: one BOX_THREADS workgroup per box; up to BOX_CAP point
 // displacements are gathered in LDS, larger boxes are re-scanned from memory.
-#ifndef OT_BOX_WAVE_SORT
-#define OT_BOX_WAVE_SORT 512
+#ifndef OT_BOX_THREADS
+#define OT_BOX_THREADS 1024
 #endif
-constexpr int BOX_THREADS = 1024;
+constexpr int BOX_THREADS = OT_BOX_THREADS;
 constexpr int BOX_CAP = 6144;
-constexpr int BOX_WAVE_SORT = OT_BOX_WAVE_SORT;  // one wave per axis sorts in registers up to
-                                                 // this count, radix selection above
 
 constexpr int LK_DEFAULT_MARGIN = 4;
 constexpr int LK_MAX_MARGIN = 16;

@@ -44,6 +44,47 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
+// Integer DPP move: rows masked off (and, with bound_ctrl, lanes whose source
+// is outside the row) return `old`/0 as the GFX9 DPP rules give.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, true);
+}
+
+// Minimum / maximum over the 64 lanes (same DPP pattern as wave_sum; masked
+// rows keep their own value).  All 64 lanes must be active.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    v = min(v, dpp_u<0xB1>(v, v));
+    v = min(v, dpp_u<0x4E>(v, v));
+    v = min(v, dpp_u<0x141>(v, v));
+    v = min(v, dpp_u<0x140>(v, v));
+    v = min(v, dpp_u<0x142, 0xA>(v, v));
+    v = min(v, dpp_u<0x143, 0xC>(v, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, dpp_u<0xB1>(v, v));
+    v = max(v, dpp_u<0x4E>(v, v));
+    v = max(v, dpp_u<0x141>(v, v));
+    v = max(v, dpp_u<0x140>(v, v));
+    v = max(v, dpp_u<0x142, 0xA>(v, v));
+    v = max(v, dpp_u<0x143, 0xC>(v, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Inclusive prefix sum over the 64 lanes: row_shr 1, 2, 4, 8 scan each row of
+// 16, row_bcast:15 and row_bcast:31 carry the row totals forward.  All 64
+// lanes must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    v += dpp_u<0x111>(0u, v);
+    v += dpp_u<0x112>(0u, v);
+    v += dpp_u<0x114>(0u, v);
+    v += dpp_u<0x118>(0u, v);
+    v += dpp_u<0x142, 0xA>(0u, v);
+    v += dpp_u<0x143, 0xC>(0u, v);
+    return v;
+}
+
 // Workgroup b runs on XCD b % 8; hand each XCD one contiguous range of work
 // items so neighbouring points share that XCD's L2.
 __device__ __forceinline__ int xcd_remap(int b, int G) {
