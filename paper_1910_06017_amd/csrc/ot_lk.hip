@@ -28,7 +28,10 @@ __device__ __forceinline__ int lk_item(int b, int G) {
     return OT_LK_XCD_REMAP ? xcd_remap(b, G) : b;
 }
 
-template <int R>
+// WIN / MARGIN > 0 fix the window and LDS margin at compile time (every
+// derived size, pitch and loop count then folds to a constant); 0 takes them
+// from the launch parameters.
+template <int R, int WIN = 0, int MARGIN = 0>
 __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restrict__ pts,
                                                  int n, LkParams prm, float* __restrict__ next_pts,
                                                  uint8_t* __restrict__ status,
@@ -39,7 +42,7 @@ __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restr
     const int i = lk_item(blockIdx.x, gridDim.x);
     if (i >= n) return;
     const float ux = uniform_f(pts[2 * i]), uy = uniform_f(pts[2 * i + 1]);
-    const LkGeom g(prm.win, R, prm.margin);
+    const LkGeom g(WIN > 0 ? WIN : prm.win, R, MARGIN > 0 ? MARGIN : prm.margin);
     const int L = prm.levels;
     const LkResult r = lk_point<R>(P, Q, ux, uy, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
                                    iters_out ? iters_out + (size_t)i * L : nullptr,
@@ -128,6 +131,15 @@ hipError_t launch_lk(const DevPyr& prev, const DevPyr& next, const float* pts, i
                      uint8_t* iters_out, float* lam_out, hipStream_t stream) {
     const int R = lk_template_rows(prm.win);
     const size_t lds = lk_lds_bytes(prm.win, R, prm.margin);
+    if (R == 7 && prm.win == 21 && (prm.margin == 4 || prm.margin == 6)) {
+        if (prm.margin == 4)
+            hipLaunchKernelGGL((k_lk_track<7, 21, 4>), dim3(n), dim3(64), lds, stream, prev, next, pts,
+                               n, prm, next_pts, status, err, iters_out, lam_out);
+        else
+            hipLaunchKernelGGL((k_lk_track<7, 21, 6>), dim3(n), dim3(64), lds, stream, prev, next, pts,
+                               n, prm, next_pts, status, err, iters_out, lam_out);
+        return hipGetLastError();
+    }
     switch (R) {
 #define OT_CASE(RR)                                                                          \
     case RR:                                                                                 \

@@ -123,6 +123,7 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
         const int steps = udiv_small(SR + rps - 1, rps);
         const uint8_t* __restrict__ base = Jl + (size_t)sy0 * jp + a0 + 4 * kk;
         uint32_t* __restrict__ dst = jr + lr * SP + 4 * kk;
+#pragma unroll 1
         for (int s0 = 0; s0 < steps; s0 += 8) {
             uint32_t v[8];
 #pragma unroll
@@ -154,6 +155,7 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
         const int dr = udiv_small(64, SC), dc = 64 - dr * SC;
         int r = udiv_small(lane, SC), c = lane - r * SC;
         const int nk = (SR * SC + 63) >> 6;
+#pragma unroll 1
         for (int kb = 0; kb < nk; kb += OT_STAGE_BATCH) {
             int idx[OT_STAGE_BATCH];
             uint32_t p0[OT_STAGE_BATCH], p1[OT_STAGE_BATCH];
@@ -201,6 +203,7 @@ __device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int 
         const bool lane_ok = lr < rps;
         const int steps = udiv_small(g.PR + rps - 1, rps);
         const uint8_t* __restrict__ base = Il + (size_t)ys * ip + a0 + 4 * kk;
+#pragma unroll 1
         for (int s0 = 0; s0 < steps; s0 += 8) {
             uint32_t v[8];
 #pragma unroll
@@ -222,6 +225,7 @@ __device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int 
         const int dr = udiv_small(64, cols), dc = 64 - dr * cols;
         int r = udiv_small(lane, cols), c = lane - r * cols;
         const int nk = (g.PR * cols + 63) >> 6;
+#pragma unroll 1
         for (int kb = 0; kb < nk; kb += 8) {
             int idx[8];
             uint32_t p[8];
@@ -339,6 +343,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             const int dr = udiv_small(64, g.TW), dc = 64 - dr * g.TW;
             int ty = udiv_small(lane, g.TW), tx = lane - ty * g.TW;
             const int ntap = g.RR * g.TW;
+#pragma unroll 1
             for (int e = lane; e < ntap; e += 64) {
                 const int qx = clampi(x0 + tx, 0, w - 1), qy = clampi(y0 + ty, 0, h - 1);
                 const int xl = max(qx - 1, 0) - a0p, xc = qx - a0p, xr = min(qx + 1, w - 1) - a0p;
