@@ -44,7 +44,7 @@ __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restr
     const float ux = uniform_f(pts[2 * i]), uy = uniform_f(pts[2 * i + 1]);
     const LkGeom g(WIN > 0 ? WIN : prm.win, R, MARGIN > 0 ? MARGIN : prm.margin);
     const int L = prm.levels;
-    const LkResult r = lk_point<R>(P, Q, ux, uy, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
+    const LkResult r = lk_point<R, (WIN > 0)>(P, Q, ux, uy, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
                                    iters_out ? iters_out + (size_t)i * L : nullptr,
                                    lam_out ? lam_out + (size_t)i * L : nullptr);
     if ((threadIdx.x & 63) == 0) {
@@ -65,7 +65,7 @@ __device__ __forceinline__ int find_job(const int32_t* __restrict__ prefix, int 
     return lo;
 }
 
-template <int R>
+template <int R, int WIN = 0, int MARGIN = 0>
 __device__ __forceinline__ void lk_batch_item(const uint8_t* __restrict__ table,
                                               const TableLayout& T, const TableHdr& hd, int i,
                                               unsigned char* smem) {
@@ -75,8 +75,8 @@ __device__ __forceinline__ void lk_batch_item(const uint8_t* __restrict__ table,
     const DevJob& jb = jobs[j];
     const int li = i - pt_prefix[j];
     const float ux = uniform_f(jb.pts[2 * li]), uy = uniform_f(jb.pts[2 * li + 1]);
-    const LkGeom g(hd.lk.win, R, hd.lk.margin);
-    const LkResult r = lk_point<R>(jb.prev, jb.next, ux, uy, jb.levels, hd.lk.iters, hd.lk.eps2,
+    const LkGeom g(WIN > 0 ? WIN : hd.lk.win, R, MARGIN > 0 ? MARGIN : hd.lk.margin);
+    const LkResult r = lk_point<R, (WIN > 0)>(jb.prev, jb.next, ux, uy, jb.levels, hd.lk.iters, hd.lk.eps2,
                                    hd.lk.min_eig, g, smem, nullptr, nullptr);
     if ((threadIdx.x & 63) == 0) {
         jb.next_pts[2 * li] = r.nx;
@@ -87,19 +87,19 @@ __device__ __forceinline__ void lk_batch_item(const uint8_t* __restrict__ table,
 }
 
 // One wave per point over the flattened points of every job.
-template <int R>
+template <int R, int WIN = 0, int MARGIN = 0>
 __global__ OT_LK_BOUNDS void k_lk_batch(const uint8_t* __restrict__ table, int cap) {
     extern __shared__ __align__(16) unsigned char lk_smem[];
     const TableLayout T = TableLayout::make(cap);
     const TableHdr& hd = *reinterpret_cast<const TableHdr*>(table);
     const int i = lk_item(blockIdx.x, gridDim.x);
     if (i >= hd.total_pts) return;
-    lk_batch_item<R>(table, T, hd, i, lk_smem);
+    lk_batch_item<R, WIN, MARGIN>(table, T, hd, i, lk_smem);
 }
 
 // Persistent form: a fixed grid of waves claims chunks of points from the
 // table's work counter until the points run out.
-template <int R>
+template <int R, int WIN = 0, int MARGIN = 0>
 __global__ OT_LK_BOUNDS void k_lk_batch_persistent(uint8_t* __restrict__ table, int cap) {
     extern __shared__ __align__(16) unsigned char lk_smem[];
     const TableLayout T = TableLayout::make(cap);
@@ -112,7 +112,7 @@ __global__ OT_LK_BOUNDS void k_lk_batch_persistent(uint8_t* __restrict__ table, 
         base = __builtin_amdgcn_readfirstlane(base);
         if (base >= total) break;
         const int end = min(base + chunk, total);
-        for (int i = base; i < end; ++i) lk_batch_item<R>(table, T, hd, i, lk_smem);
+        for (int i = base; i < end; ++i) lk_batch_item<R, WIN, MARGIN>(table, T, hd, i, lk_smem);
     }
 }
 
@@ -158,6 +158,21 @@ hipError_t launch_batch_lk(const uint8_t* table, int cap, int win, int margin, i
                            bool persistent, hipStream_t stream) {
     const int R = lk_template_rows(win);
     const size_t lds = lk_lds_bytes(win, R, margin);
+    if (R == 7 && win == 21 && (margin == 4 || margin == 6)) {
+#define OT_SPEC(MM)                                                                              \
+    if (persistent)                                                                              \
+        hipLaunchKernelGGL((k_lk_batch_persistent<7, 21, MM>), dim3(grid), dim3(64), lds, stream, \
+                           const_cast<uint8_t*>(table), cap);                                    \
+    else                                                                                         \
+        hipLaunchKernelGGL((k_lk_batch<7, 21, MM>), dim3(grid), dim3(64), lds, stream, table, cap);
+        if (margin == 4) {
+            OT_SPEC(4)
+        } else {
+            OT_SPEC(6)
+        }
+#undef OT_SPEC
+        return hipGetLastError();
+    }
     switch (R) {
 #define OT_CASE(RR)                                                                           \
     case RR:                                                                                  \

@@ -256,7 +256,9 @@ struct LkResult {
     int status;
 };
 
-template <int R, class PyrRef>
+// FIXED: the geometry g is a compile-time constant (the caller's window and
+// margin are template arguments), so fixed-count loops are unrolled.
+template <int R, bool FIXED, class PyrRef>
 __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, float ux, float uy,
                                              int L, int iters, float eps2, float min_eig,
                                              const LkGeom& g, unsigned char* __restrict__ smem,
@@ -310,33 +312,43 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         __syncthreads();
         // ---- Scharr gradients at the tap grid: the gradient image is defined on
         // the level's pixels and read at clamped indices, so a tap outside the
-        // level takes the gradient of the nearest edge pixel.
+        // level takes the gradient of the nearest edge pixel.  The responses are
+        // kept as the integer sums (32x the gradient); the factor is exact and
+        // is taken out in the tensor, the gate and the solve.
         if (x0 >= 1 && x0 + g.TW <= w - 1 && y0 >= 1 && y0 + g.RR <= h - 1) {
-            // interior: no clamping; each lane slides a 3x3 window down a
-            // column of taps, so a tap costs three byte reads.  With
-            // d = right - left and t = 3 left + 10 centre + 3 right per row:
-            // Sx = 3 d(y-1) + 10 d(y) + 3 d(y+1),  Sy = t(y+1) - t(y-1).
+            // interior: no clamping; ncg groups of TW lanes each slide a 3x3
+            // window down GR consecutive taps of a column, so a tap costs three
+            // byte reads.  With d = right - left and t = 3 left + 10 centre +
+            // 3 right per row: Sx = 3 d(y-1) + 10 d(y) + 3 d(y+1),
+            // Sy = t(y+1) - t(y-1).  Groups run past row RR - 1 when ncg does
+            // not divide RR; those taps land in LDS rows nobody reads.
             const int ncg = udiv_small(64, g.TW);
             const int GR = udiv_small(g.RR + ncg - 1, ncg);
             const int rg = udiv_small(lane, g.TW), tx = lane - rg * g.TW;
             if (rg < ncg) {
-                const int ty0 = rg * GR, ty1 = min(ty0 + GR, g.RR);
+                const int ty0 = rg * GR;
                 const uint8_t* pp = patch + ty0 * g.PW + (x0 + tx - a0p);
+                float2* gp = grad + ty0 * g.TW + tx;
                 int vl = pp[-1], vc = pp[0], vr = pp[1];
                 int d0 = vr - vl, t0 = 3 * (vl + vr) + 10 * vc;
                 vl = pp[g.PW - 1], vc = pp[g.PW], vr = pp[g.PW + 1];
                 int d1 = vr - vl, t1 = 3 * (vl + vr) + 10 * vc;
-                for (int ty = ty0; ty < ty1; ++ty) {
-                    const uint8_t* q = pp + (ty - ty0 + 2) * g.PW;
+                auto tap = [&](int k) {
+                    const uint8_t* q = pp + (k + 2) * g.PW;
                     vl = q[-1], vc = q[0], vr = q[1];
                     const int d2 = vr - vl, t2 = 3 * (vl + vr) + 10 * vc;
-                    const int sxv = 3 * (d0 + d2) + 10 * d1;
-                    const int syv = t2 - t0;
-                    grad[ty * g.TW + tx] = make_float2((float)sxv * (1.0f / 32.0f), (float)syv * (1.0f / 32.0f));
+                    gp[k * g.TW] = make_float2((float)(3 * (d0 + d2) + 10 * d1), (float)(t2 - t0));
                     d0 = d1;
                     d1 = d2;
                     t0 = t1;
                     t1 = t2;
+                };
+                if constexpr (FIXED) {
+#pragma unroll
+                    for (int k = 0; k < GR; ++k) tap(k);
+                } else {
+#pragma unroll 1
+                    for (int k = 0; k < GR; ++k) tap(k);
                 }
             }
         } else {
@@ -355,7 +367,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                 const int pdl = patch[yd + xl], pdc = patch[yd + xc], pdr = patch[yd + xr];
                 const int sxv = 3 * (pur - pul) + 10 * (pcr - pcl) + 3 * (pdr - pdl);
                 const int syv = 3 * (pdl - pul) + 10 * (pdc - puc) + 3 * (pdr - pur);
-                grad[e] = make_float2((float)sxv * (1.0f / 32.0f), (float)syv * (1.0f / 32.0f));
+                grad[e] = make_float2((float)sxv, (float)syv);
                 tx += dc;
                 ty += dr;
                 if (tx >= g.TW) {
@@ -401,8 +413,9 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             float unused;
             wave_sum4(gxx, gxy, gyy, 0.0f, gxx, gxy, gyy, unused);
         }
+        // the sums are 1024x the tensor of the true gradients (exactly)
         const float hm = 0.5f * (gxx + gyy), hd = 0.5f * (gxx - gyy);
-        const float lam = (hm - sqrtf(hd * hd + gxy * gxy)) / N;
+        const float lam = ((hm - sqrtf(hd * hd + gxy * gxy)) / N) * (1.0f / 1024.0f);
         if (lane == 0 && lam_out) lam_out[l] = lam;
         if (!(lam >= min_eig)) {
             if (lane == 0)
@@ -415,7 +428,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             res.ny = uy + gy * s;
             return res;
         }
-        const float idet = 1.0f / (gxx * gyy - gxy * gxy);
+        // b comes out 32x and the tensor 1024x: 32 / det(1024 G) gives eta
+        const float idet = 32.0f / (gxx * gyy - gxy * gxy);
         __syncthreads();  // the set-up LDS is reused for the target region
 
         // Positions are clamped before the integer conversion; past the bounds
