@@ -129,12 +129,13 @@ OT_HD inline int lk_rows_needed(int win) {
     return (win + s - 1) / s;
 }
 
-// LDS bytes one tracking wave needs: the larger of the set-up stage (uint8
-// template patch + float2 gradient tap grid, both with the rows the Scharr
-// groups run past the tap grid) and the iteration stage (packed half-pair
-// target region with a margin on every side, rows padded to whole 16-byte
-// groups from the 4-byte aligned column at or below the region).
-OT_HD inline size_t lk_lds_bytes(int win, int R, int margin) {
+// LDS of one tracking wave: the larger of the set-up stage (uint8 template
+// patch + float2 gradient tap grid, both with the rows the Scharr groups run
+// past the tap grid) and the iteration stage (packed half-pair target region
+// with a margin on every side, rows padded to whole 16-byte groups from the
+// 4-byte aligned column at or below the region), followed by the level-0
+// template samples (R floats per lane, kept for the residual).
+OT_HD inline size_t lk_lds_a_offset(int win, int R, int margin) {
     const int nseg = lk_nseg(win);
     const int RR = nseg * R + 1, TW = win + 1, PW = 4 * (((TW + 4) >> 2) + 1);
     const int ncg = 64 / TW, GR = (RR + ncg - 1) / ncg, GRR = ncg * GR;  // GRR >= RR
@@ -142,7 +143,10 @@ OT_HD inline size_t lk_lds_bytes(int win, int R, int margin) {
     const int SC = TW + 2 * margin, SP = 4 * (((SC + 3) >> 2) + 1);
     const size_t setup = (size_t)((PR * PW + 15) & ~15) + (size_t)GRR * TW * 8;
     const size_t iter = (size_t)(RR + 2 * margin) * SP * 4;
-    return setup > iter ? setup : iter;
+    return ((setup > iter ? setup : iter) + 15) & ~(size_t)15;
+}
+OT_HD inline size_t lk_lds_bytes(int win, int R, int margin) {
+    return lk_lds_a_offset(win, R, margin) + (size_t)64 * R * 4;
 }
 
 }  // namespace ot

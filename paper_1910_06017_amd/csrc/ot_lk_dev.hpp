@@ -72,7 +72,7 @@ __device__ __forceinline__ void wave_sum4(float a, float b, float c, float d, fl
 // its edges.
 // ---------------------------------------------------------------------------
 struct LkGeom {
-    int win, r, nseg, RR, TW, PR, PW, M, SC, SR, SP;
+    int win, r, nseg, RR, TW, PR, PW, M, SC, SR, SP, AO;
     __device__ LkGeom(int win_, int R, int margin) {
         win = win_;
         r = win >> 1;
@@ -85,6 +85,7 @@ struct LkGeom {
         SC = TW + 2 * M;
         SR = RR + 2 * M;
         SP = 4 * (((SC + 3) >> 2) + 1);  // target row entries (16-byte rows)
+        AO = (int)lk_lds_a_offset(win, R, margin);  // level-0 template samples
     }
 };
 
@@ -287,7 +288,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         return res;  // also catches NaN
     }
 
-    float A[R], X[R], Y[R];
+    float X[R], Y[R];
+    float* __restrict__ aA = reinterpret_cast<float*>(smem + g.AO);  // [R][64], level 0 only
     float gx = 0.0f, gy = 0.0f;
     float nux = 0.0f, nuy = 0.0f;
     uint32_t* jr = reinterpret_cast<uint32_t*>(smem);
@@ -393,7 +395,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                 const float ry = fmaf(ax, g1.y - g0.y, g0.y);
                 if (k > 0) {
                     const bool v = (k - 1) < nrows;
-                    A[k - 1] = v ? fmaf(ay, ri - pi, pi) : 0.0f;
+                    if (l == 0) aA[(k - 1) * 64 + lane] = v ? fmaf(ay, ri - pi, pi) : 0.0f;
                     X[k - 1] = v ? fmaf(ay, rx - px, px) : 0.0f;
                     Y[k - 1] = v ? fmaf(ay, ry - py, py) : 0.0f;
                 }
@@ -412,6 +414,36 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         {
             float unused;
             wave_sum4(gxx, gxy, gyy, 0.0f, gxx, gxy, gyy, unused);
+        }
+        // sum(A grad) through the same window sums and blend the iterations use
+        // for the target (below), so identical frames give b == 0 exactly
+        float cax, cay;
+        {
+            const uint8_t* pr = patch + (row0 + 1) * g.PW + x0 + col - a0p;
+            float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+            float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f, q3 = 0.0f;
+            float i0 = (float)pr[0], di0 = (float)pr[1] - i0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const float i1 = (float)pr[(k + 1) * g.PW], di1 = (float)pr[(k + 1) * g.PW + 1] - i1;
+                p0 = fmaf(i0, X[k], p0);
+                p1 = fmaf(di0, X[k], p1);
+                p2 = fmaf(i1, X[k], p2);
+                p3 = fmaf(di1, X[k], p3);
+                q0 = fmaf(i0, Y[k], q0);
+                q1 = fmaf(di0, Y[k], q1);
+                q2 = fmaf(i1, Y[k], q2);
+                q3 = fmaf(di1, Y[k], q3);
+                i0 = i1;
+                di0 = di1;
+            }
+            float tj0x, td0x, tj1x, td1x, tj0y, td0y, tj1y, td1y;
+            wave_sum4(p0, p1, p2, p3, tj0x, td0x, tj1x, td1x);
+            wave_sum4(q0, q1, q2, q3, tj0y, td0y, tj1y, td1y);
+            const float r0x = fmaf(ax, td0x, tj0x), r1x = fmaf(ax, td1x, tj1x);
+            const float r0y = fmaf(ax, td0y, tj0y), r1y = fmaf(ax, td1y, tj1y);
+            cax = fmaf(ay, r1x - r0x, r0x);
+            cay = fmaf(ay, r1y - r0y, r0y);
         }
         // the sums are 1024x the tensor of the true gradients (exactly)
         const float hm = 0.5f * (gxx + gyy), hd = 0.5f * (gxx - gyy);
@@ -445,6 +477,16 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             soff = sx0 & 3;
             __syncthreads();
         }
+        // The bilinear target at position floor + (fx, fy) blends four whole-
+        // pixel samples with weights that depend only on (fx, fy), so
+        //   sum_p J(p + d) grad_p = (1-fy) (S_J0 + fx S_D0) + fy (S_J1 + fx S_D1)
+        // with S_J0 = sum J(row k) grad, S_D0 = sum (J(x+1) - J(x))(row k) grad
+        // and S_J1, S_D1 the same one row down.  These eight window sums are
+        // recomputed only when the floor position changes; an iteration that
+        // stays on the same pixel costs a handful of wave-uniform operations.
+        int sfx = INT32_MIN, sfy = INT32_MIN;  // floor position of the sums
+        float sj0x = 0.0f, sd0x = 0.0f, sj1x = 0.0f, sd1x = 0.0f;
+        float sj0y = 0.0f, sd0y = 0.0f, sj1y = 0.0f, sd1y = 0.0f;
         int it = 0;
         while (it < iters) {
             const float qx = fminf(fmaxf(cx + gx + nux, lo), hix);
@@ -462,18 +504,34 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                 ox = g.M;
                 oy = g.M;
             }
-            const uint32_t* __restrict__ jb = jr + (oy + row0) * g.SP + soff + ox + col;
-            float rp = blend_pair(jb[0], bxw);
-            float bx = 0.0f, by = 0.0f;
+            const int ifx = (int)fqx, ify = (int)fqy;
+            if (ifx != sfx || ify != sfy) {
+                const uint32_t* __restrict__ jb = jr + (oy + row0) * g.SP + soff + ox + col;
+                float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+                float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f, q3 = 0.0f;
+                half2_t e = __builtin_bit_cast(half2_t, jb[0]);
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const float rn = blend_pair(jb[(k + 1) * g.SP], bxw);
-                const float d = A[k] - fmaf(byw, rn - rp, rp);
-                bx = fmaf(d, X[k], bx);
-                by = fmaf(d, Y[k], by);
-                rp = rn;
+                for (int k = 0; k < R; ++k) {
+                    const half2_t en = __builtin_bit_cast(half2_t, jb[(k + 1) * g.SP]);
+                    p0 = fmaf((float)e.x, X[k], p0);
+                    p1 = fmaf((float)e.y, X[k], p1);
+                    p2 = fmaf((float)en.x, X[k], p2);
+                    p3 = fmaf((float)en.y, X[k], p3);
+                    q0 = fmaf((float)e.x, Y[k], q0);
+                    q1 = fmaf((float)e.y, Y[k], q1);
+                    q2 = fmaf((float)en.x, Y[k], q2);
+                    q3 = fmaf((float)en.y, Y[k], q3);
+                    e = en;
+                }
+                wave_sum4(p0, p1, p2, p3, sj0x, sd0x, sj1x, sd1x);
+                wave_sum4(q0, q1, q2, q3, sj0y, sd0y, sj1y, sd1y);
+                sfx = ifx;
+                sfy = ify;
             }
-            wave_sum2(bx, by, bx, by);
+            const float r0x = fmaf(bxw, sd0x, sj0x), r1x = fmaf(bxw, sd1x, sj1x);
+            const float r0y = fmaf(bxw, sd0y, sj0y), r1y = fmaf(bxw, sd1y, sj1y);
+            const float bx = cax - fmaf(byw, r1x - r0x, r0x);
+            const float by = cay - fmaf(byw, r1y - r0y, r0y);
             const float ex = (gyy * bx - gxy * by) * idet;
             const float ey = (gxx * by - gxy * bx) * idet;
             nux += ex;
@@ -515,7 +573,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const float rn = blend_pair(jb[(k + 1) * g.SP], bxw);
-            const float d = A[k] - fmaf(byw, rn - rp, rp);
+            const float d = aA[k * 64 + lane] - fmaf(byw, rn - rp, rp);
             e += (k < nrows) ? fabsf(d) : 0.0f;
             rp = rn;
         }
