@@ -71,6 +71,12 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def lk_kernel_name(win: int, margin: int) -> str:
+    """The tracker instance a single-call launch of this window and margin runs."""
+    m = margin or 4  # the library's default margin
+    return f"k_lk_track<7,{win},{m}>" if win == 21 and m in (4, 6) else "k_lk_track<7>"
+
+
 def traffic_from_profile(launch_pts: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
@@ -224,7 +230,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": traffic_from_profile(n),
-                     "kernel": "k_lk_track<7>", "kernel_ms": lk_ms,
+                     "kernel": lk_kernel_name(WIN, MARGIN), "kernel_ms": lk_ms,
                      "flop_per_launch": flops,
                      "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS},
     }
