@@ -13,24 +13,30 @@
 #define OT_LK_BOUNDS __launch_bounds__(64)
 #endif
 
-// Points map to waves in dispatch order (0), which deals neighbouring points
-// round-robin to the XCDs, or through the XCD-contiguous remap (1).  Points
-// of one box cost alike, so contiguous ranges leave some XCDs with the
-// expensive boxes; a frame pair's pyramids fit in every XCD's L2, so the
-// interleaved order loses no locality and balances the XCDs.
+// Point order.  Workgroup b runs on XCD b % 8.  Points of one box cost
+// alike, so giving each XCD one contiguous range of points (OT_LK_XCD_REMAP
+// 1) leaves some XCDs with the expensive boxes.  The default (0) deals
+// chunks of LK_CHUNK consecutive points to the XCDs round-robin: the XCDs
+// get even shares of every box, while each chunk's outputs fill whole cache
+// lines in one XCD's L2 and its neighbouring windows share that L2.  Each XCD
+// then reads most of both pyramids (a few MB per frame pair), which costs far
+// less than the imbalance it removes.
 #ifndef OT_LK_XCD_REMAP
 #define OT_LK_XCD_REMAP 0
 #endif
 
 namespace ot {
 
+constexpr int LK_CHUNK = 16;
+
 __device__ __forceinline__ int lk_item(int b, int G) {
-    return OT_LK_XCD_REMAP ? xcd_remap(b, G) : b;
+    if (OT_LK_XCD_REMAP) return xcd_remap(b, G);
+    constexpr int X = 8, S = X * LK_CHUNK;
+    if (b >= G - G % S) return b;  // ragged tail in dispatch order
+    const int x = b % X, k = b / X;
+    return ((k / LK_CHUNK) * X + x) * LK_CHUNK + k % LK_CHUNK;
 }
 
-// WIN / MARGIN > 0 fix the window and LDS margin at compile time (every
-// derived size, pitch and loop count then folds to a constant); 0 takes them
-// from the launch parameters.
 template <int R, int WIN = 0, int MARGIN = 0>
 __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restrict__ pts,
                                                  int n, LkParams prm, float* __restrict__ next_pts,
