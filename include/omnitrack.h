@@ -69,6 +69,12 @@ enum {
  * squared; 1e-4 on a [0,1] intensity scale) marks a point lost. */
 #define OT_DEFAULT_MIN_EIG 6.5025f
 
+/* Pyramid flag: also materialize the Scharr responses of every level (0 ..
+ * levels-1) in the workspace.  A tracker that reads such a pyramid as its
+ * template (previous) pyramid takes the gradients from these planes instead
+ * of computing them for every point and level; results are identical. */
+#define OT_PYR_GRADS 1
+
 /* (host) Descriptor of a device-resident pyramid.  level[0] may alias the
  * caller's frame; levels 1.. live in a workspace. */
 typedef struct {
@@ -77,12 +83,21 @@ typedef struct {
     int32_t h[OT_MAX_LEVELS];
     int32_t pitch[OT_MAX_LEVELS];
     int32_t levels; /* number of levels including level 0 */
-    int32_t flags;  /* reserved, 0 */
+    int32_t flags;  /* 0 or OT_PYR_GRADS */
+    /* With OT_PYR_GRADS, per level one int32 per pixel (row pitch gpitch
+     * elements): bits 0-15 the signed Scharr sum Sx, bits 16-31 Sy, with
+     * Sx(x,y) = sum_{j=-1..1} s_j (P(cx(x+1), cy(y+j)) - P(cx(x-1), cy(y+j))),
+     * s = (3,10,3), cx/cy clamping to the level; the gradient is S/32 and
+     * |S| <= 4080.  Sy likewise with x and y exchanged.  NULL / 0 otherwise. */
+    const int32_t* grad[OT_MAX_LEVELS];
+    int32_t gpitch[OT_MAX_LEVELS];
 } ot_pyr;
 
 /* Bytes of device workspace ot_pyramid_build needs for levels 1..levels-1
- * of a W x H frame (0 when levels == 1).  Returns 0 for invalid sizes.
- * Each level starts 256-byte aligned with a pitch rounded up to 64 bytes. */
+ * of a W x H frame (0 when levels == 1 and flags == 0), plus, with
+ * OT_PYR_GRADS, the gradient planes of all levels.  Returns 0 for invalid
+ * sizes or flags.  Each level and plane starts 256-byte aligned; level
+ * pitches are rounded up to 64 bytes, plane pitches to 16 elements. */
 OT_API size_t ot_pyramid_bytes(int32_t W, int32_t H, int32_t levels, int32_t flags);
 
 /* (host) Fill *out with the layout ot_pyramid_build would produce, without
@@ -100,8 +115,10 @@ OT_API ot_err ot_pyramid_layout(const uint8_t* frame, int32_t W, int32_t H, int3
  * workspace: >= ot_pyramid_bytes(W, H, levels, flags) bytes, 256-aligned.
  * *out (host) receives the descriptor, level[0] = frame.
  * Errors: OT_E_INVAL (null pointers, W/H out of [1, OT_MAX_DIM], pitch < W,
- * levels out of range, flags != 0), OT_E_WORKSPACE (ws_bytes too small or
- * misaligned), OT_E_LAUNCH. */
+ * levels out of range, flags not 0 or OT_PYR_GRADS), OT_E_WORKSPACE
+ * (ws_bytes too small or misaligned), OT_E_LAUNCH.  With OT_PYR_GRADS the
+ * gradient planes (see ot_pyr) are written on the same stream after the
+ * levels. */
 OT_API ot_err ot_pyramid_build(const uint8_t* frame, int32_t W, int32_t H, int32_t pitch,
                         int32_t levels, void* workspace, size_t ws_bytes, int32_t flags,
                         ot_pyr* out, void* stream);

@@ -27,20 +27,25 @@ bool level_dims(int32_t W, int32_t H, int32_t levels, int32_t* w, int32_t* h) {
 }
 
 size_t level_pitch(int32_t w) { return align_up((size_t)w, 64); }
+size_t grad_pitch(int32_t w) { return align_up((size_t)w, 16); }  // int32 elements
 
-size_t pyr_bytes(const int32_t* w, const int32_t* h, int32_t levels) {
+size_t pyr_bytes(const int32_t* w, const int32_t* h, int32_t levels, int32_t flags) {
     size_t total = 0;
     for (int l = 1; l < levels; ++l) total += align_up(level_pitch(w[l]) * (size_t)h[l], 256);
+    if (flags & OT_PYR_GRADS)
+        for (int l = 0; l < levels; ++l) total += align_up(grad_pitch(w[l]) * (size_t)h[l] * 4, 256);
     return total;
 }
+
+bool flags_valid(int32_t flags) { return flags == 0 || flags == OT_PYR_GRADS; }
 
 ot_err layout(const uint8_t* frame, int32_t W, int32_t H, int32_t pitch, int32_t levels,
               void* workspace, size_t ws_bytes, int32_t flags, ot_pyr* out) {
     int32_t w[OT_MAX_LEVELS], h[OT_MAX_LEVELS];
-    if (!frame || !out || flags != 0 || pitch < W || !level_dims(W, H, levels, w, h))
+    if (!frame || !out || !flags_valid(flags) || pitch < W || !level_dims(W, H, levels, w, h))
         return OT_E_INVAL;
-    const size_t need = pyr_bytes(w, h, levels);
-    if (levels > 1 && (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255) != 0))
+    const size_t need = pyr_bytes(w, h, levels, flags);
+    if (need > 0 && (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255) != 0))
         return OT_E_WORKSPACE;
     ot_pyr p;
     memset(&p, 0, sizeof(p));
@@ -57,6 +62,13 @@ ot_err layout(const uint8_t* frame, int32_t W, int32_t H, int32_t pitch, int32_t
         p.pitch[l] = (int32_t)level_pitch(w[l]);
         off += align_up((size_t)p.pitch[l] * h[l], 256);
     }
+    p.flags = flags;
+    if (flags & OT_PYR_GRADS)
+        for (int l = 0; l < levels; ++l) {
+            p.grad[l] = reinterpret_cast<const int32_t*>(static_cast<const uint8_t*>(workspace) + off);
+            p.gpitch[l] = (int32_t)grad_pitch(w[l]);
+            off += align_up((size_t)p.gpitch[l] * h[l] * 4, 256);
+        }
     *out = p;
     return OT_OK;
 }
@@ -68,6 +80,10 @@ bool pyr_valid(const ot_pyr* p) {
     if (!level_dims(p->w[0], p->h[0], p->levels, w, h)) return false;
     for (int l = 0; l < p->levels; ++l)
         if (!p->level[l] || p->w[l] != w[l] || p->h[l] != h[l] || p->pitch[l] < w[l]) return false;
+    if (!flags_valid(p->flags)) return false;
+    if (p->flags & OT_PYR_GRADS)
+        for (int l = 0; l < p->levels; ++l)
+            if (!p->grad[l] || p->gpitch[l] < w[l] || ((uintptr_t)p->grad[l] & 3) != 0) return false;
     return true;
 }
 
@@ -79,7 +95,13 @@ DevPyr to_dev(const ot_pyr& p) {
         d.w[l] = p.w[l];
         d.h[l] = p.h[l];
         d.pitch[l] = p.pitch[l];
+        if (p.flags & OT_PYR_GRADS) {
+            d.grad[l] = p.grad[l];
+            d.gpitch[l] = p.gpitch[l];
+        }
     }
+    d.levels = p.levels;
+    d.flags = p.flags;
     return d;
 }
 
@@ -107,8 +129,8 @@ extern "C" {
 
 size_t ot_pyramid_bytes(int32_t W, int32_t H, int32_t levels, int32_t flags) {
     int32_t w[OT_MAX_LEVELS], h[OT_MAX_LEVELS];
-    if (flags != 0 || !level_dims(W, H, levels, w, h)) return 0;
-    return pyr_bytes(w, h, levels);
+    if (!flags_valid(flags) || !level_dims(W, H, levels, w, h)) return 0;
+    return pyr_bytes(w, h, levels, flags);
 }
 
 ot_err ot_pyramid_layout(const uint8_t* frame, int32_t W, int32_t H, int32_t pitch,
@@ -128,6 +150,7 @@ ot_err ot_pyramid_build(const uint8_t* frame, int32_t W, int32_t H, int32_t pitc
     for (int l0 = 0; l0 < levels - 1; l0 += PYR_FUSE)
         if (launch_pyr_stage(d, l0, pyr_stage_steps(levels, l0), s) != hipSuccess)
             return OT_E_LAUNCH;
+    if ((flags & OT_PYR_GRADS) && launch_grad(d, levels, s) != hipSuccess) return OT_E_LAUNCH;
     *out = p;
     return OT_OK;
 }

@@ -53,9 +53,13 @@ constexpr size_t LK_MAX_LDS = 64 * 1024;
 // the batched table).
 struct DevPyr {
     const uint8_t* lvl[OT_MAX_LEVELS];
+    const int32_t* grad[OT_MAX_LEVELS];  // packed Scharr sums (Sx low, Sy high), or null
     int32_t w[OT_MAX_LEVELS];
     int32_t h[OT_MAX_LEVELS];
     int32_t pitch[OT_MAX_LEVELS];
+    int32_t gpitch[OT_MAX_LEVELS];
+    int32_t levels;
+    int32_t flags;
 };
 
 struct LkParams {

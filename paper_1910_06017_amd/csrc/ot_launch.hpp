@@ -10,6 +10,9 @@ namespace ot {
 // Levels l0+1 .. l0+K (K <= PYR_FUSE) of a pyramid from level l0.
 hipError_t launch_pyr_stage(const DevPyr& P, int l0, int K, hipStream_t stream);
 
+// Scharr gradient planes of levels 0..levels-1 (P.grad must be set).
+hipError_t launch_grad(const DevPyr& P, int levels, hipStream_t stream);
+
 // Template row count the tracker uses for a window (0 = unsupported).
 int lk_template_rows(int win);
 

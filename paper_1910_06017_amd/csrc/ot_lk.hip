@@ -37,7 +37,7 @@ __device__ __forceinline__ int lk_item(int b, int G) {
     return ((k / LK_CHUNK) * X + x) * LK_CHUNK + k % LK_CHUNK;
 }
 
-template <int R, int WIN = 0, int MARGIN = 0>
+template <int R, int WIN = 0, int MARGIN = 0, bool GRADS = false>
 __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restrict__ pts,
                                                  int n, LkParams prm, float* __restrict__ next_pts,
                                                  uint8_t* __restrict__ status,
@@ -50,7 +50,7 @@ __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restr
     const float ux = uniform_f(pts[2 * i]), uy = uniform_f(pts[2 * i + 1]);
     const LkGeom g(WIN > 0 ? WIN : prm.win, R, MARGIN > 0 ? MARGIN : prm.margin);
     const int L = prm.levels;
-    const LkResult r = lk_point<R, (WIN > 0)>(P, Q, ux, uy, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
+    const LkResult r = lk_point<R, (WIN > 0), GRADS>(P, Q, ux, uy, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
                                    iters_out ? iters_out + (size_t)i * L : nullptr,
                                    lam_out ? lam_out + (size_t)i * L : nullptr);
     if ((threadIdx.x & 63) == 0) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ void lk_batch_item(const uint8_t* __restrict__ table,
     const int li = i - pt_prefix[j];
     const float ux = uniform_f(jb.pts[2 * li]), uy = uniform_f(jb.pts[2 * li + 1]);
     const LkGeom g(WIN > 0 ? WIN : hd.lk.win, R, MARGIN > 0 ? MARGIN : hd.lk.margin);
-    const LkResult r = lk_point<R, (WIN > 0)>(jb.prev, jb.next, ux, uy, jb.levels, hd.lk.iters, hd.lk.eps2,
+    const LkResult r = lk_point<R, (WIN > 0), false>(jb.prev, jb.next, ux, uy, jb.levels, hd.lk.iters, hd.lk.eps2,
                                    hd.lk.min_eig, g, smem, nullptr, nullptr);
     if ((threadIdx.x & 63) == 0) {
         jb.next_pts[2 * li] = r.nx;
@@ -137,26 +137,29 @@ hipError_t launch_lk(const DevPyr& prev, const DevPyr& next, const float* pts, i
                      uint8_t* iters_out, float* lam_out, hipStream_t stream) {
     const int R = lk_template_rows(prm.win);
     const size_t lds = lk_lds_bytes(prm.win, R, prm.margin);
+    const bool grads = (prev.flags & OT_PYR_GRADS) != 0;
+#define OT_LAUNCH(...)                                                                           \
+    hipLaunchKernelGGL((k_lk_track<__VA_ARGS__>), dim3(n), dim3(64), lds, stream, prev, next, pts, \
+                       n, prm, next_pts, status, err, iters_out, lam_out)
     if (R == 7 && prm.win == 21 && (prm.margin == 4 || prm.margin == 6)) {
-        if (prm.margin == 4)
-            hipLaunchKernelGGL((k_lk_track<7, 21, 4>), dim3(n), dim3(64), lds, stream, prev, next, pts,
-                               n, prm, next_pts, status, err, iters_out, lam_out);
-        else
-            hipLaunchKernelGGL((k_lk_track<7, 21, 6>), dim3(n), dim3(64), lds, stream, prev, next, pts,
-                               n, prm, next_pts, status, err, iters_out, lam_out);
+        if (prm.margin == 4) {
+            if (grads) OT_LAUNCH(7, 21, 4, true); else OT_LAUNCH(7, 21, 4, false);
+        } else {
+            if (grads) OT_LAUNCH(7, 21, 6, true); else OT_LAUNCH(7, 21, 6, false);
+        }
         return hipGetLastError();
     }
     switch (R) {
-#define OT_CASE(RR)                                                                          \
-    case RR:                                                                                 \
-        hipLaunchKernelGGL(k_lk_track<RR>, dim3(n), dim3(64), lds, stream, prev, next, pts, n, \
-                           prm, next_pts, status, err, iters_out, lam_out);                  \
+#define OT_CASE(RR)                                                 \
+    case RR:                                                        \
+        if (grads) OT_LAUNCH(RR, 0, 0, true); else OT_LAUNCH(RR, 0, 0, false); \
         break;
         OT_LK_ROWS(OT_CASE)
 #undef OT_CASE
         default:
             return hipErrorInvalidValue;
     }
+#undef OT_LAUNCH
     return hipGetLastError();
 }
 

@@ -259,7 +259,9 @@ struct LkResult {
 
 // FIXED: the geometry g is a compile-time constant (the caller's window and
 // margin are template arguments), so fixed-count loops are unrolled.
-template <int R, bool FIXED, class PyrRef>
+// GRADS: the template pyramid carries materialized Scharr sums, which are
+// read (at clamped indices) instead of computed.
+template <int R, bool FIXED, bool GRADS, class PyrRef>
 __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, float ux, float uy,
                                              int L, int iters, float eps2, float min_eig,
                                              const LkGeom& g, unsigned char* __restrict__ smem,
@@ -317,7 +319,33 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         // level takes the gradient of the nearest edge pixel.  The responses are
         // kept as the integer sums (32x the gradient); the factor is exact and
         // is taken out in the tensor, the gate and the solve.
-        if (x0 >= 1 && x0 + g.TW <= w - 1 && y0 >= 1 && y0 + g.RR <= h - 1) {
+        if constexpr (GRADS) {
+            // the planes hold the sums of every level pixel; a tap outside the
+            // level reads the nearest edge pixel's sums
+            const int32_t* __restrict__ Gl = P.grad[l];
+            const int gp = P.gpitch[l];
+            const bool inside = x0 >= 0 && x0 + g.TW <= w && y0 >= 0 && y0 + g.RR <= h;
+            const int dr = udiv_small(64, g.TW), dc = 64 - dr * g.TW;
+            int ty = udiv_small(lane, g.TW), tx = lane - ty * g.TW;
+            const int ntap = g.RR * g.TW;
+            auto tap = [&](int e) {
+                if (e < ntap) {
+                    const int qx = inside ? x0 + tx : clampi(x0 + tx, 0, w - 1);
+                    const int qy = inside ? y0 + ty : clampi(y0 + ty, 0, h - 1);
+                    const int32_t v = Gl[(size_t)qy * gp + qx];
+                    grad[e] = make_float2((float)(int16_t)(v & 0xFFFF), (float)(v >> 16));
+                }
+                tx += dc;
+                ty += dr;
+                if (tx >= g.TW) {
+                    tx -= g.TW;
+                    ++ty;
+                }
+            };
+            const int nk = (ntap + 63) >> 6;
+#pragma unroll 2
+            for (int k = 0; k < nk; ++k) tap(lane + 64 * k);
+        } else if (x0 >= 1 && x0 + g.TW <= w - 1 && y0 >= 1 && y0 + g.RR <= h - 1) {
             // interior: no clamping; ncg groups of TW lanes each slide a 3x3
             // window down GR consecutive taps of a column, so a tap costs three
             // byte reads.  With d = right - left and t = 3 left + 10 centre +

@@ -11,6 +11,38 @@ __global__ __launch_bounds__(PYR_THREADS) void k_pyr_stage(DevPyr P, int l0, int
     pyr_fused(P, l0, K, blockIdx.x, blockIdx.y, sm);
 }
 
+// Gradient planes of levels 0..levels-1: workgroup t takes tile t of the
+// levels' tile lists laid end to end (tpre: first tile of each level).
+struct GradLaunch {
+    DevPyr P;
+    int32_t tpre[OT_MAX_LEVELS + 1];
+    int32_t cols[OT_MAX_LEVELS];
+    int32_t levels;
+};
+
+__global__ __launch_bounds__(GRAD_THREADS) void k_grad(GradLaunch g) {
+    __shared__ GradSmem sm;
+    const int t = blockIdx.x;
+    int l = 0;
+    while (l + 1 < g.levels && t >= g.tpre[l + 1]) ++l;
+    const int lt = t - g.tpre[l], cols = g.cols[l];
+    grad_tile(g.P.lvl[l], g.P.w[l], g.P.h[l], g.P.pitch[l], const_cast<int32_t*>(g.P.grad[l]),
+              g.P.gpitch[l], lt % cols, lt / cols, sm);
+}
+
+hipError_t launch_grad(const DevPyr& P, int levels, hipStream_t stream) {
+    GradLaunch g;
+    g.P = P;
+    g.levels = levels;
+    g.tpre[0] = 0;
+    for (int l = 0; l < levels; ++l) {
+        g.cols[l] = (P.w[l] + GRAD_TW - 1) / GRAD_TW;
+        g.tpre[l + 1] = g.tpre[l] + g.cols[l] * ((P.h[l] + GRAD_TH - 1) / GRAD_TH);
+    }
+    hipLaunchKernelGGL(k_grad, dim3(g.tpre[levels]), dim3(GRAD_THREADS), 0, stream, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_pyr_stage(const DevPyr& P, int l0, int K, hipStream_t stream) {
     const int top = l0 + K;
     const dim3 grid((P.w[top] + PYR_FTW - 1) / PYR_FTW, (P.h[top] + PYR_FTH - 1) / PYR_FTH);

@@ -151,4 +151,46 @@ __device__ __forceinline__ void pyr_fused(const DevPyr& P, int l0, int K, int tx
     }
 }
 
+// ---------------------------------------------------------------------------
+// Materialized Scharr sums of one level: one GRAD_THREADS workgroup per
+// GRAD_TW x GRAD_TH tile stages the tile plus a one-pixel halo (clamped to
+// the level, so border pixels see their clamped neighbours) in LDS and
+// writes (Sx & 0xFFFF) | (Sy << 16) per pixel.
+// ---------------------------------------------------------------------------
+constexpr int GRAD_TW = 64, GRAD_TH = 16, GRAD_THREADS = 256;
+
+struct GradSmem {
+    uint8_t in[GRAD_TH + 2][GRAD_TW + 4];
+};
+
+__device__ __forceinline__ void grad_tile(const uint8_t* __restrict__ src, int w, int h, int sp,
+                                          int32_t* __restrict__ dst, int gp, int tx, int ty,
+                                          GradSmem& sm) {
+    const int tid = threadIdx.x;
+    const int x0 = tx * GRAD_TW - 1, y0 = ty * GRAD_TH - 1;
+    constexpr int IR = GRAD_TH + 2, IC = GRAD_TW + 2;
+    for (int e = tid; e < IR * IC; e += GRAD_THREADS) {
+        const int r = e / IC, c = e - r * IC;
+        sm.in[r][c] = src[(size_t)clampi(y0 + r, 0, h - 1) * sp + clampi(x0 + c, 0, w - 1)];
+    }
+    __syncthreads();
+    // one thread per 4 horizontally adjacent pixels
+    const int r = tid / (GRAD_TW / 4), c0 = (tid - r * (GRAD_TW / 4)) * 4;
+    const int y = ty * GRAD_TH + r;
+    if (y >= h) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = c0 + k, x = tx * GRAD_TW + c;
+        if (x >= w) break;
+        const uint8_t* u = &sm.in[r][c];  // (x-1, y-1)
+        const uint8_t* m = u + (GRAD_TW + 4);
+        const uint8_t* d = m + (GRAD_TW + 4);
+        const int sx = 3 * ((int)u[2] - (int)u[0]) + 10 * ((int)m[2] - (int)m[0]) +
+                       3 * ((int)d[2] - (int)d[0]);
+        const int sy = 3 * ((int)d[0] - (int)u[0]) + 10 * ((int)d[1] - (int)u[1]) +
+                       3 * ((int)d[2] - (int)u[2]);
+        dst[(size_t)y * gp + x] = (int32_t)(((uint32_t)sx & 0xFFFFu) | ((uint32_t)sy << 16));
+    }
+}
+
 }  // namespace ot

@@ -32,10 +32,14 @@ class OtError(RuntimeError):
         self.code = code
 
 
+OT_PYR_GRADS = 1
+
+
 class OtPyr(C.Structure):
     _fields_ = [("level", C.c_void_p * OT_MAX_LEVELS), ("w", C.c_int32 * OT_MAX_LEVELS),
                 ("h", C.c_int32 * OT_MAX_LEVELS), ("pitch", C.c_int32 * OT_MAX_LEVELS),
-                ("levels", C.c_int32), ("flags", C.c_int32)]
+                ("levels", C.c_int32), ("flags", C.c_int32),
+                ("grad", C.c_void_p * OT_MAX_LEVELS), ("gpitch", C.c_int32 * OT_MAX_LEVELS)]
 
 
 class OtLkOpts(C.Structure):
@@ -129,8 +133,8 @@ def _need(t, dtype, shape_last=None, what="tensor"):
     del torch
 
 
-def pyramid_bytes(W: int, H: int, levels: int) -> int:
-    return int(lib().ot_pyramid_bytes(W, H, levels, 0))
+def pyramid_bytes(W: int, H: int, levels: int, flags: int = 0) -> int:
+    return int(lib().ot_pyramid_bytes(W, H, levels, flags))
 
 
 class Pyramid:
@@ -153,32 +157,52 @@ class Pyramid:
         rows = self.ws[off:off + d.pitch[l] * d.h[l]].view(d.h[l], d.pitch[l])
         return rows[:, :d.w[l]]
 
+    @property
+    def has_grads(self) -> bool:
+        return bool(self.desc.flags & OT_PYR_GRADS)
 
-def alloc_workspace(W: int, H: int, levels: int, device="cuda"):
+    def grads(self, l: int):
+        """(sx, sy) int32 tensors of level l's materialized Scharr sums."""
+        torch = _torch()
+        d = self.desc
+        if not self.has_grads:
+            raise ValueError("pyramid was built without OT_PYR_GRADS")
+        off = d.grad[l] - self.ws.data_ptr()
+        words = self.ws[off:off + 4 * d.gpitch[l] * d.h[l]].view(torch.int32)
+        v = words.view(d.h[l], d.gpitch[l])[:, :d.w[l]]
+        sx = (v << 16) >> 16          # sign-extend the low half
+        sy = v >> 16
+        return sx, sy
+
+
+def alloc_workspace(W: int, H: int, levels: int, device="cuda", grads: bool = False):
     torch = _torch()
-    nb = pyramid_bytes(W, H, levels)
+    nb = pyramid_bytes(W, H, levels, OT_PYR_GRADS if grads else 0)
     # torch's caching allocator hands out 512-byte aligned blocks
     return torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
 
 
-def pyramid_build(frame, levels: int, ws=None, stream=None) -> Pyramid:
-    """Build levels 1..levels-1 of `frame` ((H, W) uint8 CUDA tensor)."""
+def pyramid_build(frame, levels: int, ws=None, stream=None, grads: bool = False) -> Pyramid:
+    """Build levels 1..levels-1 of `frame` ((H, W) uint8 CUDA tensor); with
+    `grads` also the Scharr gradient planes of every level."""
     torch = _torch()
     _need(frame, torch.uint8, what="frame")
     H, W = frame.shape
     if ws is None:
-        ws = alloc_workspace(W, H, levels, frame.device)
+        ws = alloc_workspace(W, H, levels, frame.device, grads=grads)
     desc = OtPyr()
+    flags = OT_PYR_GRADS if grads else 0
     check(lib().ot_pyramid_build(_ptr(frame), W, H, frame.stride(0), levels, _ptr(ws), ws.numel(),
-                                 0, C.byref(desc), _stream_handle(stream)), "ot_pyramid_build")
+                                 flags, C.byref(desc), _stream_handle(stream)), "ot_pyramid_build")
     return Pyramid(frame, ws, desc)
 
 
-def pyramid_layout(frame, levels: int, ws) -> Pyramid:
+def pyramid_layout(frame, levels: int, ws, grads: bool = False) -> Pyramid:
     H, W = frame.shape
     desc = OtPyr()
     check(lib().ot_pyramid_layout(_ptr(frame), W, H, frame.stride(0), levels, _ptr(ws),
-                                  ws.numel(), 0, C.byref(desc)), "ot_pyramid_layout")
+                                  ws.numel(), OT_PYR_GRADS if grads else 0, C.byref(desc)),
+          "ot_pyramid_layout")
     return Pyramid(frame, ws, desc)
 
 

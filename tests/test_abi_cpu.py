@@ -45,7 +45,13 @@ def test_pyramid_bytes(L):
     assert ops.pyramid_bytes(720, 576, 1) == 0
     for bad in [(0, 5, 2), (5, 0, 2), (5, 5, 0), (5, 5, 9), (20000, 5, 2)]:
         assert ops.pyramid_bytes(*bad) == 0
-    assert L.ot_pyramid_bytes(64, 64, 2, 1) == 0  # flags must be 0
+    assert L.ot_pyramid_bytes(64, 64, 2, 2) == 0  # unknown flag
+    # OT_PYR_GRADS adds one int32 per pixel of levels 0..3, pitches rounded to 16
+    # elements, planes 256-aligned: 720, 368 (360), 192 (180), 96 (90)
+    al = lambda v: (v + 255) // 256 * 256
+    planes = al(720 * 576 * 4) + al(368 * 288 * 4) + al(192 * 144 * 4) + al(96 * 72 * 4)
+    assert ops.pyramid_bytes(720, 576, 4, ops.OT_PYR_GRADS) == want + planes
+    assert ops.pyramid_bytes(720, 576, 1, ops.OT_PYR_GRADS) == al(720 * 576 * 4)
 
 
 def layout(L, W=720, H=576, pitch=720, levels=4, ws=FAKE + 4096, wsb=10**7, flags=0):
@@ -66,6 +72,36 @@ def test_pyramid_layout(L):
     assert layout(L, wsb=1000)[0] == ops_err("OT_E_WORKSPACE")
     assert layout(L, levels=1, ws=0, wsb=0)[0] == 0
     assert layout(L, flags=2)[0] == ops_err("OT_E_INVAL")
+    assert d.flags == 0 and all(d.grad[l] is None for l in range(4))
+
+
+def test_pyramid_layout_grads(L):
+    G = ops.OT_PYR_GRADS
+    rc, d = layout(L, flags=G)
+    assert rc == 0 and d.flags == G
+    base = FAKE + 4096 + 384 * 288 + 192 * 144 + 128 * 72   # after the uint8 levels
+    assert d.grad[0] == base
+    assert list(d.gpitch)[:4] == [720, 368, 192, 96]
+    assert d.grad[1] == base + 720 * 576 * 4
+    assert all(d.grad[l] % 256 == 0 for l in range(4))
+    need = ops.pyramid_bytes(720, 576, 4, G)
+    assert layout(L, flags=G, wsb=need)[0] == 0
+    assert layout(L, flags=G, wsb=need - 1)[0] == ops_err("OT_E_WORKSPACE")
+    # a single-level pyramid with planes needs a workspace
+    assert layout(L, levels=1, ws=0, wsb=0, flags=G)[0] == ops_err("OT_E_WORKSPACE")
+    # the tracker rejects a descriptor claiming planes it does not have
+    _, P = layout(L, flags=G)
+    _, Q = layout(L)
+    bad = ops.OtPyr()
+    C.memmove(C.byref(bad), C.byref(P), C.sizeof(P))
+    bad.grad[2] = None
+    assert lk_call(L, bad, Q) == ops_err("OT_E_INVAL")
+    bad.grad[2] = P.grad[2]
+    bad.gpitch[1] = 100
+    assert lk_call(L, bad, Q) == ops_err("OT_E_INVAL")
+    bad.gpitch[1] = P.gpitch[1]
+    bad.flags = 3
+    assert lk_call(L, bad, Q) == ops_err("OT_E_INVAL")
 
 
 def ops_err(name):
