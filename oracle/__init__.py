@@ -87,6 +87,8 @@ def _load(path: str):
                                P, P, P, P, P, P, i32]
     L.orc_lk_track.restype = i32
     L.orc_box_update.argtypes = [P, i32, P, P, P, P, i32, i32, P, P]
+    L.orc_fb_gate.argtypes = [P, P, P, P, i32, C.c_double, P, P]
+    L.orc_box_update_scaled.argtypes = [P, i32, P, P, P, P, i32, P, P, P]
     L.orc_max_threads.restype = i32
     return L
 
@@ -217,6 +219,36 @@ def box_update(boxes, box_id, pts, next_pts, status, use_mean: bool = False):
     lib().orc_box_update(_p(boxes), m, _p(box_id), _p(pts), _p(next_pts), _p(status), n,
                          int(use_mean), _p(out), _p(cnt))
     return out, cnt
+
+
+def fb_gate(pts, back_pts, st_fwd, st_bwd, fb_max: float):
+    """Forward-backward check: (fb_err float64 (n,), status uint8 (n,))."""
+    pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
+    back = np.ascontiguousarray(back_pts, np.float64).reshape(-1, 2)
+    sf = np.ascontiguousarray(st_fwd, np.uint8)
+    sb = np.ascontiguousarray(st_bwd, np.uint8)
+    n = pts.shape[0]
+    err = np.zeros(n, np.float64)
+    st = np.zeros(n, np.uint8)
+    lib().orc_fb_gate(_p(pts), _p(back), _p(sf), _p(sb), n, float(fb_max), _p(err), _p(st))
+    return err, st
+
+
+def box_update_scaled(boxes, box_id, pts, next_pts, status):
+    """Median-Flow box update: (out_boxes (m,4), out_count (m,), scale (m,))."""
+    boxes = np.ascontiguousarray(boxes, np.float64).reshape(-1, 4)
+    m = boxes.shape[0]
+    box_id = np.ascontiguousarray(box_id, np.int32)
+    pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
+    next_pts = np.ascontiguousarray(next_pts, np.float64).reshape(-1, 2)
+    status = np.ascontiguousarray(status, np.uint8)
+    n = pts.shape[0]
+    out = np.zeros((m, 4), np.float64)
+    cnt = np.zeros(m, np.int32)
+    scale = np.zeros(m, np.float64)
+    lib().orc_box_update_scaled(_p(boxes), m, _p(box_id), _p(pts), _p(next_pts), _p(status), n,
+                                _p(out), _p(cnt), _p(scale))
+    return out, cnt, scale
 
 
 def max_threads() -> int:

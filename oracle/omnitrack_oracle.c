@@ -386,6 +386,85 @@ void orc_box_update(const double* boxes, int32_t m, const int32_t* box_id,
     free(dy);
 }
 
+void orc_fb_gate(const double* pts, const double* back_pts, const uint8_t* st_fwd,
+                 const uint8_t* st_bwd, int32_t n, double fb_max, double* fb_err,
+                 uint8_t* status_out) {
+    for (int32_t i = 0; i < n; ++i) {
+        if (st_fwd[i] == 1 && st_bwd[i] == 1) {
+            const double ex = pts[2 * (size_t)i] - back_pts[2 * (size_t)i];
+            const double ey = pts[2 * (size_t)i + 1] - back_pts[2 * (size_t)i + 1];
+            const double e = sqrt(ex * ex + ey * ey);
+            fb_err[i] = e;
+            status_out[i] = (e <= fb_max) ? 1 : 0;
+        } else {
+            fb_err[i] = -1.0;
+            status_out[i] = 0;
+        }
+    }
+}
+
+void orc_box_update_scaled(const double* boxes, int32_t m, const int32_t* box_id,
+                           const double* pts, const double* next_pts, const uint8_t* status,
+                           int32_t n, double* out_boxes, int32_t* out_count, double* out_scale) {
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double* dx = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* dy = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int32_t b = 0; b < m; ++b) {
+        int32_t c = 0;
+        for (int32_t i = 0; i < n; ++i)
+            if (box_id[i] == b && status[i] == 1) {
+                idx[c] = i;
+                dx[c] = next_pts[2 * (size_t)i] - pts[2 * (size_t)i];
+                dy[c] = next_pts[2 * (size_t)i + 1] - pts[2 * (size_t)i + 1];
+                ++c;
+            }
+        double mx = 0.0, my = 0.0, s = 1.0;
+        if (c > 0) {
+            qsort(dx, (size_t)c, sizeof(double), cmp_double);
+            qsort(dy, (size_t)c, sizeof(double), cmp_double);
+            mx = median_sorted(dx, c);
+            my = median_sorted(dy, c);
+        }
+        // scale: all pairs of the box's points
+        const size_t np = (size_t)c * (size_t)(c > 0 ? c - 1 : 0) / 2;
+        double* r = (double*)malloc(sizeof(double) * (np > 0 ? np : 1));
+        int32_t nr = 0;
+        for (int32_t a = 0; a < c; ++a)
+            for (int32_t q = a + 1; q < c; ++q) {
+                const int32_t i = idx[a], j = idx[q];
+                const double ux = pts[2 * (size_t)i] - pts[2 * (size_t)j];
+                const double uy = pts[2 * (size_t)i + 1] - pts[2 * (size_t)j + 1];
+                const double du = sqrt(ux * ux + uy * uy);
+                if (du == 0.0) continue;
+                const double vx = next_pts[2 * (size_t)i] - next_pts[2 * (size_t)j];
+                const double vy = next_pts[2 * (size_t)i + 1] - next_pts[2 * (size_t)j + 1];
+                r[nr++] = sqrt(vx * vx + vy * vy) / du;
+            }
+        if (nr > 0) {
+            qsort(r, (size_t)nr, sizeof(double), cmp_double);
+            s = median_sorted(r, nr);
+        }
+        free(r);
+        const double cx = 0.5 * (boxes[4 * b + 0] + boxes[4 * b + 2]) + mx;
+        const double cy = 0.5 * (boxes[4 * b + 1] + boxes[4 * b + 3]) + my;
+        const double hw = 0.5 * (boxes[4 * b + 2] - boxes[4 * b + 0]);
+        const double hh = 0.5 * (boxes[4 * b + 3] - boxes[4 * b + 1]);
+        if (c > 0) {
+            out_boxes[4 * b + 0] = cx - s * hw;
+            out_boxes[4 * b + 1] = cy - s * hh;
+            out_boxes[4 * b + 2] = cx + s * hw;
+            out_boxes[4 * b + 3] = cy + s * hh;
+        } else {
+            for (int k = 0; k < 4; ++k) out_boxes[4 * b + k] = boxes[4 * b + k];
+        }
+        out_count[b] = c;
+        out_scale[b] = s;
+    }
+    free(idx);
+    free(dx);
+    free(dy);
+}
+
 int32_t orc_max_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

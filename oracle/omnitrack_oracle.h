@@ -82,6 +82,31 @@ void orc_box_update(const double* boxes, int32_t m, const int32_t* box_id,
                     const double* pts, const double* next_pts, const uint8_t* status,
                     int32_t n, int32_t use_mean, double* out_boxes, int32_t* out_count);
 
+/*
+ * Forward-backward check (Kalal, Mikolajczyk & Matas 2010): back_pts are the
+ * forward results tracked back to the first frame.  fb_err[i] = |pts_i -
+ * back_pts_i| (Euclidean) when both tracks succeeded (status 1), else -1;
+ * status_out[i] = 1 when both succeeded and fb_err[i] <= fb_max, else 0.
+ */
+void orc_fb_gate(const double* pts, const double* back_pts, const uint8_t* st_fwd,
+                 const uint8_t* st_bwd, int32_t n, double fb_max, double* fb_err,
+                 uint8_t* status_out);
+
+/*
+ * Median-Flow box update (Kalal et al. 2010) over the points with box_id == b
+ * and status == 1 (count c): the displacement (mx, my) is the component-wise
+ * median of next_pts - pts as in orc_box_update; the scale s is the median,
+ * over the pairs i < j of those points with pts_i != pts_j, of
+ * |next_i - next_j| / |pts_i - pts_j| (1 when there is no such pair).  The box
+ * centre moves by (mx, my) and its half-extents are multiplied by s:
+ * out = (cx - s*hw, cy - s*hh, cx + s*hw, cy + s*hh) with cx = (x0+x1)/2 + mx,
+ * hw = (x1-x0)/2, and likewise in y.  A box without points is copied with
+ * count 0 and scale 1.
+ */
+void orc_box_update_scaled(const double* boxes, int32_t m, const int32_t* box_id,
+                           const double* pts, const double* next_pts, const uint8_t* status,
+                           int32_t n, double* out_boxes, int32_t* out_count, double* out_scale);
+
 /* Number of OpenMP threads a parallel region gets by default. */
 int32_t orc_max_threads(void);
 

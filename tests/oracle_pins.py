@@ -386,6 +386,122 @@ def check_box_outliers():
         assert np.allclose(out[0], [1.5, -2.25, 1.5, -2.25], atol=1e-9)
 
 
+# ---------------------------------------------------------------- Median Flow
+def _pair_median_ratio(pts, nxt):
+    """Independent brute force: median over pairs i < j (pts distinct) of the
+    distance ratio, 1 without pairs."""
+    r = []
+    for i in range(len(pts)):
+        for j in range(i + 1, len(pts)):
+            du = math.hypot(*(pts[i] - pts[j]))
+            if du > 0:
+                r.append(math.hypot(*(nxt[i] - nxt[j])) / du)
+    return float(np.median(r)) if r else 1.0
+
+
+def check_scaled_box_translation():
+    """A common translation: scale exactly 1, box moved by the translation."""
+    rng = np.random.default_rng(31)
+    boxes = rng.uniform(0, 500, (4, 4))
+    boxes[:, 2:] += boxes[:, :2]
+    n = 200
+    box_id = rng.integers(0, 4, n).astype(np.int32)
+    pts = rng.uniform(0, 600, (n, 2))
+    t = np.array([-4.75, 2.5])
+    out, cnt, sc = oracle.box_update_scaled(boxes, box_id, pts, pts + t, np.ones(n, np.uint8))
+    assert np.array_equal(sc, np.ones(4))
+    assert np.allclose(out, boxes + np.concatenate([t, t]), atol=1e-9)
+    assert np.array_equal(cnt, np.bincount(box_id, minlength=4))
+
+
+def check_scaled_box_similarity():
+    """Points scaled by s about the box centre (symmetric grid): scale s, the
+    centre stays, the half-extents scale by s."""
+    for s in (0.95, 1.0, 1.05, 1.3):
+        c = np.array([120.0, 80.0])
+        g = np.stack(np.meshgrid(np.arange(-4, 5), np.arange(-3, 4)), -1).reshape(-1, 2) * 6.0
+        pts = c + g
+        nxt = c + s * g
+        box = np.array([[c[0] - 30, c[1] - 20, c[0] + 30, c[1] + 20]])
+        out, cnt, sc = oracle.box_update_scaled(box, np.zeros(len(pts), np.int32), pts, nxt,
+                                                np.ones(len(pts), np.uint8))
+        assert abs(sc[0] - s) < 1e-12, (s, sc[0])
+        assert np.allclose(out[0], [c[0] - 30 * s, c[1] - 20 * s, c[0] + 30 * s, c[1] + 20 * s],
+                           atol=1e-9)
+
+
+def check_scaled_box_bruteforce():
+    """Random boxes against an independent all-pairs NumPy computation."""
+    rng = np.random.default_rng(32)
+    for trial in range(12):
+        m = int(rng.integers(1, 5))
+        n = int(rng.integers(0, 60))
+        boxes = rng.uniform(0, 300, (m, 4))
+        box_id = rng.integers(-1, m, n).astype(np.int32)
+        pts = np.round(rng.uniform(0, 6, (n, 2))) * 7.0     # many coincident positions
+        nxt = pts * rng.uniform(0.9, 1.1) + rng.normal(0, 0.5, (n, 2))
+        st = (rng.uniform(size=n) < 0.8).astype(np.uint8)
+        out, cnt, sc = oracle.box_update_scaled(boxes, box_id, pts, nxt, st)
+        for b in range(m):
+            sel = (box_id == b) & (st == 1)
+            assert cnt[b] == sel.sum()
+            if sel.sum() == 0:
+                assert np.array_equal(out[b], boxes[b]) and sc[b] == 1.0
+                continue
+            s = _pair_median_ratio(pts[sel], nxt[sel])
+            assert abs(sc[b] - s) < 1e-12
+            d = nxt[sel] - pts[sel]
+            mx, my = np.median(d[:, 0]), np.median(d[:, 1])
+            cx = 0.5 * (boxes[b, 0] + boxes[b, 2]) + mx
+            cy = 0.5 * (boxes[b, 1] + boxes[b, 3]) + my
+            hw = 0.5 * (boxes[b, 2] - boxes[b, 0])
+            hh = 0.5 * (boxes[b, 3] - boxes[b, 1])
+            assert np.allclose(out[b], [cx - s * hw, cy - s * hh, cx + s * hw, cy + s * hh],
+                               atol=1e-9)
+
+
+def check_scaled_box_outliers():
+    """A tenth of the points thrown far away corrupt under half of the pairs,
+    so the median ratio stays the common scale."""
+    rng = np.random.default_rng(33)
+    s = 1.04
+    pts = rng.uniform(0, 100, (60, 2))
+    nxt = 50 + s * (pts - 50)
+    nxt[:6] = rng.uniform(-1000, 1000, (6, 2))
+    _, _, sc = oracle.box_update_scaled(np.zeros((1, 4)), np.zeros(60, np.int32), pts, nxt,
+                                        np.ones(60, np.uint8))
+    assert abs(sc[0] - s) < 1e-9
+
+
+def check_fb_gate():
+    """FB error is the Euclidean distance; the threshold is inclusive; a failed
+    track in either direction loses the point."""
+    pts = np.array([[10.0, 10.0], [20.0, 5.0], [0.0, 0.0], [7.0, 7.0]])
+    back = pts + np.array([[3.0, 4.0], [0.375, 0.5], [0.0, 0.0], [-6.0, 8.0]])  # exact lengths
+    sf = np.array([1, 1, 0, 1], np.uint8)
+    sb = np.array([1, 1, 1, 1], np.uint8)
+    err, st = oracle.fb_gate(pts, back, sf, sb, 5.0)
+    assert np.array_equal(err, [5.0, 0.625, -1.0, 10.0])
+    assert np.array_equal(st, [1, 1, 0, 0])
+    err, st = oracle.fb_gate(pts, back, sf, sb, 4.999)
+    assert np.array_equal(st, [0, 1, 0, 0])
+    err, st = oracle.fb_gate(pts, back, sf, np.array([1, 0, 1, 1], np.uint8), 5.0)
+    assert np.array_equal(st, [1, 0, 0, 0]) and err[1] == -1.0
+
+
+def check_fb_roundtrip_shift():
+    """A pure sub-pixel shift tracked forward then backward by the oracle
+    returns to the start: FB error under 0.02 px at interior points."""
+    w = synth.sd_shift_workload(seed=8, mode="analytic")
+    fwd = oracle.lk_track(w.frame0, w.frame1, w.pts, win=21, levels=3)
+    bwd = oracle.lk_track(w.frame1, w.frame0, fwd.next_pts.astype(np.float32), win=21, levels=3)
+    err, st = oracle.fb_gate(w.pts, bwd.next_pts, fwd.status, bwd.status, 1.0)
+    inner = (w.pts[:, 0] > 40) & (w.pts[:, 0] < 680) & (w.pts[:, 1] > 40) & (w.pts[:, 1] < 536)
+    ok = inner & (st == 1)
+    assert ok.sum() > 0.9 * inner.sum()
+    assert np.median(err[ok]) < 0.005 and err[ok].max() < 0.02, (np.median(err[ok]), err[ok].max())
+
+
 ALL = [check_level_dims, check_pyr_down_library, check_pyramid_closed_forms,
        check_scharr_library, check_scharr_closed_forms, check_bilinear_affine,
        check_bilinear_library, check_structure_tensor_ramp, check_structure_tensor_quadratic,
@@ -393,4 +509,6 @@ ALL = [check_level_dims, check_pyr_down_library, check_pyramid_closed_forms,
        check_integer_shift_bruteforce, check_subpixel_shift, check_large_shift_needs_pyramid,
        check_err_bruteforce, check_gate_and_lost_reasons, check_iteration_control,
        check_lk_structure_tensor_closed_form, check_two_motions,
-       check_box_translation, check_box_median_library, check_box_outliers]
+       check_box_translation, check_box_median_library, check_box_outliers,
+       check_scaled_box_translation, check_scaled_box_similarity, check_scaled_box_bruteforce,
+       check_scaled_box_outliers, check_fb_gate, check_fb_roundtrip_shift]

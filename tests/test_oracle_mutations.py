@@ -38,6 +38,19 @@ MUTATIONS = {
     "out_of_frame_check": ("nx > W0 - 1 || ny > H0 - 1)", "nx > W0 + 5 || ny > H0 + 5)"),
     "convergence_test": ("if (ex * ex + ey * ey < C->eps * C->eps) break;",
                          "if (ex * ex + ey * ey < C->eps) break;"),
+    "fb_threshold_exclusive": ("status_out[i] = (e <= fb_max) ? 1 : 0;",
+                               "status_out[i] = (e < fb_max) ? 1 : 0;"),
+    "fb_error_manhattan": ("const double e = sqrt(ex * ex + ey * ey);",
+                           "const double e = fabs(ex) + fabs(ey);"),
+    "fb_ignores_backward_status": ("if (st_fwd[i] == 1 && st_bwd[i] == 1) {",
+                                   "if (st_fwd[i] == 1) {"),
+    "scale_ratio_inverted": ("r[nr++] = sqrt(vx * vx + vy * vy) / du;",
+                             "r[nr++] = du / sqrt(vx * vx + vy * vy);"),
+    "scale_keeps_coincident_pairs": ("if (du == 0.0) continue;", "(void)0;"),
+    "scale_skips_adjacent_pairs": ("for (int32_t q = a + 1; q < c; ++q) {",
+                                   "for (int32_t q = a + 2; q < c; ++q) {"),
+    "scale_about_corner": ("out_boxes[4 * b + 0] = cx - s * hw;",
+                           "out_boxes[4 * b + 0] = cx - hw;"),
 }
 
 
