@@ -49,6 +49,8 @@ def parse():
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
     p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
     p.add_argument("--no-served", action="store_true", help="skip the served-vs-plain run")
+    p.add_argument("--no-mf", action="store_true",
+                   help="skip the Median-Flow step (forward-backward tracking, scaled boxes)")
     p.add_argument("--served-seconds", type=float, default=3.0,
                    help="length of the 64-stream arrival trace for served and plain")
     p.add_argument("--served-rates", default="1,2,4",
@@ -234,6 +236,9 @@ def main():
                      "flop_per_launch": flops,
                      "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS},
     }
+    if not a.no_mf:
+        out["median_flow"] = bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid,
+                                               WIN, L, ITERS, EPS, MARGIN, cs)
     if not a.no_batched:
         out["batched"] = bench_batched(a)
     if not a.no_served:
@@ -241,6 +246,83 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
     print(json.dumps(out))
+
+
+def _graph_ms(torch, g, cs, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(cs):
+        for _ in range(3):
+            g.replay()
+        e0.record(cs)
+        for _ in range(reps):
+            g.replay()
+        e1.record(cs)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS, EPS, MARGIN, cs):
+    """The Median-Flow step on the same frame pair: next pyramid, forward and
+    backward tracking, the forward-backward gate (1 px) and the scaled box
+    update, one graph replay; the gate and the scaled update are also timed
+    alone."""
+    import torch
+    dev = pts.device
+    n, m = pts.shape[0], boxes.shape[0]
+    nxt = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    back = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    sf = torch.empty(n, dtype=torch.uint8, device=dev)
+    sb = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    fe = torch.empty(n, dtype=torch.float32, device=dev)
+    ob = torch.empty((m, 4), dtype=torch.float32, device=dev)
+    oc = torch.empty(m, dtype=torch.int32, device=dev)
+    osc = torch.empty(m, dtype=torch.float32, device=dev)
+    kw = dict(win=WIN, levels=L, iters=ITERS, eps=EPS, margin=MARGIN)
+    Q = ops.pyramid_build(f1, L, ws=ws1)
+
+    def step():
+        ops.pyramid_build(f1, L, ws=ws1)
+        ops.lk_track(prev, Q, pts, out=(nxt, sf, None), **kw)
+        ops.lk_track(Q, prev, nxt, out=(back, sb, None), **kw)
+        ops.fb_gate(pts, back, sf, sb, 1.0, out=(st, fe))
+        ops.box_update_scaled(boxes, bid, pts, nxt, st, out=(ob, oc, osc))
+
+    def gate():
+        ops.fb_gate(pts, back, sf, sb, 1.0, out=(st, fe))
+
+    def scaled():
+        ops.box_update_scaled(boxes, bid, pts, nxt, st, out=(ob, oc, osc))
+
+    # the step is one replay; each kernel alone is KREP launches per replay so
+    # that the graph's own launch cost is amortised
+    KREP = 10
+    graphs = []
+    for fn, k in ((step, 1), (gate, KREP), (scaled, KREP)):
+        with torch.cuda.stream(cs):
+            fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(k):
+                fn()
+        graphs.append(g)
+    torch.cuda.synchronize()
+    reps = max(20, a.steps)
+    ms = _graph_ms(torch, graphs[0], cs, reps)
+    gate_ms = _graph_ms(torch, graphs[1], cs, reps) / KREP
+    sc_ms = _graph_ms(torch, graphs[2], cs, reps) / KREP
+    c = oc.cpu().numpy().astype(np.int64)
+    pairs = int((c * (c - 1) // 2).sum())
+    gate_bytes = n * (8 + 8 + 1 + 1 + 1 + 4)
+    return {"ms_per_step": ms, "value": n / (ms * 1e-3), "unit": "tracked points/s",
+            "step": "next pyramid + LK forward + LK backward + FB gate (1 px) + scaled box update",
+            "kept_fraction": float(st.float().mean().item()),
+            "fb_gate_us": gate_ms * 1e3,
+            "fb_gate_hbm_frac": gate_bytes / (gate_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "box_scaled_us": sc_ms * 1e3, "box_pairs": pairs,
+            "box_pairs_per_s": pairs / (sc_ms * 1e-3)}
 
 
 def bench_batched(a):

@@ -173,6 +173,49 @@ OT_API ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id
                      int32_t* out_count, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Median Flow (Kalal, Mikolajczyk and Matas 2010), a refinement of the
+ * prediction phase: points are tracked forward (I_{t-1} -> I_t) and back
+ * (I_t -> I_{t-1}) with ot_lk_track, points that do not return to where they
+ * started are dropped, and each box both moves and scales with its points.
+ * ---------------------------------------------------------------------- */
+
+/* Points per box the scaled update takes (all gathered on chip). */
+#define OT_SCALE_MAX_POINTS 6144
+
+/* Forward-backward gate: for point i, if st_fwd[i] == 1 and st_bwd[i] == 1,
+ * e = |pts[i] - back_pts[i]| (Euclidean, float32), fb_err[i] = e and
+ * status_out[i] = (e <= fb_max); otherwise fb_err[i] = -1 and status_out[i]
+ * = 0.  pts are the points tracked forward, back_pts the result of tracking
+ * their forward positions back to the first frame.  pts, back_pts n x 2,
+ * 8-byte aligned; st_fwd, st_bwd, status_out n; fb_err n or NULL.
+ * status_out may alias st_fwd or st_bwd.  n == 0 is a no-op.
+ * Errors: OT_E_INVAL (n < 0, null pointers with n > 0, misalignment, fb_max
+ * negative or NaN), OT_E_LAUNCH. */
+OT_API ot_err ot_fb_gate(const float* pts, const float* back_pts, const uint8_t* st_fwd,
+                  const uint8_t* st_bwd, int32_t n, float fb_max, float* fb_err,
+                  uint8_t* status_out, void* stream);
+
+/* Scaled box prediction: for box b in [0, m), over its points with
+ * box_id == b and status == 1 (count c): (mx, my) = component-wise median
+ * of next_pts - pts, s = the median over all unordered pairs {i, j} of those
+ * points with pts[i] != pts[j] of |next_pts[i] - next_pts[j]| /
+ * |pts[i] - pts[j]| (s = 1 when there is no such pair); medians of an even
+ * count are the mean of the two middle values.  With centre (cx, cy) and
+ * half-extents (hw, hh) of boxes[b], out_boxes[b] = (cx + mx - s*hw,
+ * cy + my - s*hh, cx + mx + s*hw, cy + my + s*hh), out_count[b] = c,
+ * out_scale[b] = s.  A box with c == 0 is copied unchanged with scale 1.  A
+ * box with c > OT_SCALE_MAX_POINTS gets NaN in out_boxes[b] and out_scale[b]
+ * (its count is still written).  Ratios are formed in float32; pairs whose
+ * squared first-frame distance is zero in float32 are skipped.  Layouts as in
+ * ot_box_update; out_scale m float32.  Work per box grows with c^2.
+ * Errors: OT_E_INVAL (negative counts, null pointers with m > 0,
+ * misalignment), OT_E_LAUNCH. */
+OT_API ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t* box_id,
+                            const float* pts, const float* next_pts, const uint8_t* status,
+                            int32_t n, float* out_boxes, int32_t* out_count, float* out_scale,
+                            void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched tick: many independent streams (frame pairs) in one launch per
  * stage.  Stage 1 builds every job's next pyramid (all jobs, one launch per
  * level), stage 2 tracks every job's points in one launch, stage 3 updates

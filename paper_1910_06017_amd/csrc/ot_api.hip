@@ -197,6 +197,35 @@ ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id, const
     return OT_OK;
 }
 
+ot_err ot_fb_gate(const float* pts, const float* back_pts, const uint8_t* st_fwd,
+                  const uint8_t* st_bwd, int32_t n, float fb_max, float* fb_err,
+                  uint8_t* status_out, void* stream) {
+    if (n < 0 || !(fb_max >= 0.0f)) return OT_E_INVAL;
+    if (n == 0) return OT_OK;
+    if (!pts || !back_pts || !st_fwd || !st_bwd || !status_out) return OT_E_INVAL;
+    if (((uintptr_t)pts | (uintptr_t)back_pts) & 7) return OT_E_INVAL;
+    if (fb_err && ((uintptr_t)fb_err & 3)) return OT_E_INVAL;
+    if (launch_fb_gate(pts, back_pts, st_fwd, st_bwd, n, fb_max, fb_err, status_out,
+                       static_cast<hipStream_t>(stream)) != hipSuccess)
+        return OT_E_LAUNCH;
+    return OT_OK;
+}
+
+ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t* box_id,
+                            const float* pts, const float* next_pts, const uint8_t* status,
+                            int32_t n, float* out_boxes, int32_t* out_count, float* out_scale,
+                            void* stream) {
+    if (m < 0 || n < 0) return OT_E_INVAL;
+    if (m == 0) return OT_OK;
+    if (!boxes || !out_boxes || !out_count || !out_scale) return OT_E_INVAL;
+    if (n > 0 && (!box_id || !pts || !next_pts || !status)) return OT_E_INVAL;
+    if (((uintptr_t)pts | (uintptr_t)next_pts) & 7) return OT_E_INVAL;
+    if (launch_box_scaled(boxes, m, box_id, pts, next_pts, status, n, out_boxes, out_count,
+                          out_scale, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return OT_E_LAUNCH;
+    return OT_OK;
+}
+
 // ------------------------------------------------------------------ batched
 static bool cfg_valid(const ot_batch_cfg* c) {
     return c && c->max_jobs >= 1 && c->max_points >= 0 && c->max_boxes >= 0 &&

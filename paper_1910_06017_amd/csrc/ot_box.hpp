@@ -30,18 +30,24 @@ __device__ __forceinline__ float key2f(uint32_t k) {
 constexpr int BOX_NB = 1024;   // buckets per round
 constexpr int BOX_CAND = 64;   // a shared bucket this small is ranked by one wave
 
+// Selection state for NA axes (one selection of two ranks per axis).
+template <int NA>
+struct SelSmem {
+    uint32_t hist[NA][BOX_NB];
+    uint32_t klo[NA], khi[NA];  // per axis: key range holding both targets
+    uint32_t rank[NA][2];       // the targets' ranks among the keys in that range
+    int32_t bkt[NA][2];         // the targets' buckets this round
+    int32_t mode[NA];           // 0 done, 1 two buckets, 2 rank candidates, 3 narrow
+    uint32_t red[NA][4];        // max of bucket 0, min of bucket 1, min and max of bucket 0
+    uint32_t ncand[NA];
+    uint32_t cand[NA][BOX_CAND];
+    uint32_t res[NA][2];        // selected keys
+};
+
 struct BoxSmem {
     float dx[BOX_CAP];
     float dy[BOX_CAP];
-    uint32_t hist[2][BOX_NB];
-    uint32_t klo[2], khi[2];    // per axis: key range holding both targets
-    uint32_t rank[2][2];        // the targets' ranks among the keys in that range
-    int32_t bkt[2][2];          // the targets' buckets this round
-    int32_t mode[2];            // 0 done, 1 two buckets, 2 rank candidates, 3 narrow
-    uint32_t red[2][4];         // max of bucket 0, min of bucket 1, min and max of bucket 0
-    uint32_t ncand[2];
-    uint32_t cand[2][BOX_CAND];
-    uint32_t res[2][2];         // selected keys
+    SelSmem<2> sel;
     int32_t count;
 };
 
@@ -93,28 +99,69 @@ __device__ __forceinline__ BoxMap box_map(uint32_t lo, uint32_t hi, bool linear)
     return m;
 }
 
-// Keys of x and y at ranks (c-1)/2 and c/2 (c > 0) into sm.res.  On entry
-// sm.klo/khi hold each axis' smallest and largest key, sm.rank the two ranks
-// and sm.hist is zero (all written before a barrier that precedes the first
-// read).
-__device__ __forceinline__ void box_select(bool in_lds, BoxSmem& sm, int c, int b,
-                                           const int32_t* __restrict__ box_id,
-                                           const uint8_t* __restrict__ status,
-                                           const float* __restrict__ pts,
-                                           const float* __restrict__ next_pts, int n) {
+// Keys at ranks sel.rank[a][0..1] of every axis a < NA of the elements that
+// visit() presents (visit(f) calls f(v) with float v[NA] once per element, all
+// threads of the workgroup taking part) into sel.res.  On entry sel.klo/khi
+// hold each axis' smallest and largest key, sel.rank the two ranks and
+// sel.hist is zero, all written before a barrier that precedes the call.
+// Every axis must hold at least one element, and visit() must present the
+// same multiset with the same values on every call.  value_linear selects
+// value-linear buckets for the first round (else key-linear).  Waves 0..NA-1 do the per-axis
+// bookkeeping, so NA <= BOX_THREADS / 64.
+template <int NA, class Visit>
+__device__ __forceinline__ void select_ranks(SelSmem<NA>& sm, bool value_linear, Visit&& visit) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int round = 0; round < 8; ++round) {
-        const int mode0 = round == 0 ? 3 : sm.mode[0], mode1 = round == 0 ? 3 : sm.mode[1];
-        if (mode0 == 0 && mode1 == 0) break;
-        const BoxMap m0 = box_map(sm.klo[0], sm.khi[0], round == 0);
-        const BoxMap m1 = box_map(sm.klo[1], sm.khi[1], round == 0);
-        box_visit(in_lds, sm, c, b, box_id, status, pts, next_pts, n, [&](float vx, float vy) {
-            const uint32_t kx = f2key(vx), ky = f2key(vy);
-            if (mode0 != 0 && m0.in(kx)) atomicAdd(&sm.hist[0][m0.bucket(kx, vx)], 1u);
-            if (mode1 != 0 && m1.in(ky)) atomicAdd(&sm.hist[1][m1.bucket(ky, vy)], 1u);
+        int mode[NA];
+        bool any = false;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            mode[a] = round == 0 ? 3 : sm.mode[a];
+            any = any || mode[a] != 0;
+        }
+        if (!any) break;
+        BoxMap mp[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) mp[a] = box_map(sm.klo[a], sm.khi[a], value_linear && round == 0);
+        // runs of equal buckets are counted in registers and added once: a
+        // tight cluster would otherwise serialise on one LDS address
+        int cur[NA];
+        uint32_t run[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            cur[a] = 0;
+            run[a] = 0u;
+        }
+        visit([&](const float (&v)[NA]) {
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const uint32_t k = f2key(v[a]);
+                if (mode[a] != 0 && mp[a].in(k)) {
+                    const int bu = mp[a].bucket(k, v[a]);
+                    if (bu != cur[a]) {
+                        if (run[a]) atomicAdd(&sm.hist[a][cur[a]], run[a]);
+                        cur[a] = bu;
+                        run[a] = 0u;
+                    }
+                    ++run[a];
+                }
+            }
         });
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+            if (run[a]) atomicAdd(&sm.hist[a][cur[a]], run[a]);
         __syncthreads();
-        if (wave < 2 && (wave == 0 ? mode0 : mode1) != 0) {
+        // per-wave copies by selection rather than by a dynamic index into
+        // register arrays (which would spill them to scratch)
+        int mw = 0;
+        BoxMap mwp = mp[0];
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+            if (wave == a) {
+                mw = mode[a];
+                mwp = mp[a];
+            }
+        if (wave < NA && mw != 0) {
             // lane owns buckets 16*lane .. 16*lane+15; find the targets' buckets
             const uint4* hs = reinterpret_cast<const uint4*>(&sm.hist[wave][16 * lane]);
             uint32_t cnt[16];
@@ -158,7 +205,7 @@ __device__ __forceinline__ void box_select(bool in_lds, BoxSmem& sm, int c, int 
                 if (t == 0) nb = (uint32_t)__builtin_amdgcn_readlane((int)nbin, src);
             }
             if (lane == 0) {
-                const BoxMap& m = wave == 0 ? m0 : m1;
+                const BoxMap& m = mwp;
                 int md;
                 if (m.lo == m.hi) {
                     md = 0;
@@ -190,39 +237,47 @@ __device__ __forceinline__ void box_select(bool in_lds, BoxSmem& sm, int c, int 
         __syncthreads();
         // one pass for what each axis needs from its target buckets
         {
-            const int md0 = sm.mode[0], md1 = sm.mode[1];
-            const int b00 = sm.bkt[0][0], b01 = sm.bkt[0][1], b10 = sm.bkt[1][0], b11 = sm.bkt[1][1];
-            uint32_t acc[2][4] = {{0u, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u}, {0u, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u}};
-            auto take = [&](int a, int md, uint32_t k, float v, const BoxMap& m, int bA, int bB) {
-                if (md == 0 || !m.in(k)) return;
-                const int bu = m.bucket(k, v);
-                if (md == 1) {
-                    if (bu == bA) acc[a][0] = max(acc[a][0], k);
-                    if (bu == bB) acc[a][1] = min(acc[a][1], k);
-                } else if (bu == bA) {
-                    if (md == 2) {
-                        const uint32_t s = atomicAdd(&sm.ncand[a], 1u);
-                        if (s < (uint32_t)BOX_CAND) sm.cand[a][s] = k;
-                    } else {
-                        acc[a][2] = min(acc[a][2], k);
-                        acc[a][3] = max(acc[a][3], k);
+            int md[NA], bA[NA], bB[NA];
+            uint32_t acc[NA][4];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                md[a] = sm.mode[a];
+                bA[a] = sm.bkt[a][0];
+                bB[a] = sm.bkt[a][1];
+                acc[a][0] = 0u;
+                acc[a][1] = 0xFFFFFFFFu;
+                acc[a][2] = 0xFFFFFFFFu;
+                acc[a][3] = 0u;
+            }
+            visit([&](const float (&v)[NA]) {
+#pragma unroll
+                for (int a = 0; a < NA; ++a) {
+                    const uint32_t k = f2key(v[a]);
+                    if (md[a] == 0 || !mp[a].in(k)) continue;
+                    const int bu = mp[a].bucket(k, v[a]);
+                    if (md[a] == 1) {
+                        if (bu == bA[a]) acc[a][0] = max(acc[a][0], k);
+                        if (bu == bB[a]) acc[a][1] = min(acc[a][1], k);
+                    } else if (bu == bA[a]) {
+                        if (md[a] == 2) {
+                            const uint32_t sl = atomicAdd(&sm.ncand[a], 1u);
+                            if (sl < (uint32_t)BOX_CAND) sm.cand[a][sl] = k;
+                        } else {
+                            acc[a][2] = min(acc[a][2], k);
+                            acc[a][3] = max(acc[a][3], k);
+                        }
                     }
                 }
-            };
-            box_visit(in_lds, sm, c, b, box_id, status, pts, next_pts, n, [&](float vx, float vy) {
-                take(0, md0, f2key(vx), vx, m0, b00, b01);
-                take(1, md1, f2key(vy), vy, m1, b10, b11);
             });
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const int md = a == 0 ? md0 : md1;
-                if (md == 1) {
+            for (int a = 0; a < NA; ++a) {
+                if (md[a] == 1) {
                     const uint32_t r0 = wave_max_u32(acc[a][0]), r1 = wave_min_u32(acc[a][1]);
                     if (lane == 0) {
                         atomicMax(&sm.red[a][0], r0);
                         atomicMin(&sm.red[a][1], r1);
                     }
-                } else if (md == 3) {
+                } else if (md[a] == 3) {
                     const uint32_t r2 = wave_min_u32(acc[a][2]), r3 = wave_max_u32(acc[a][3]);
                     if (lane == 0) {
                         atomicMin(&sm.red[a][2], r2);
@@ -233,8 +288,8 @@ __device__ __forceinline__ void box_select(bool in_lds, BoxSmem& sm, int c, int 
         }
         __syncthreads();
         // results, the next round's ranges, and a cleared histogram
-        for (int e = tid; e < 2 * BOX_NB; e += BOX_THREADS) (&sm.hist[0][0])[e] = 0u;
-        if (wave < 2) {
+        for (int e = tid; e < NA * BOX_NB; e += BOX_THREADS) (&sm.hist[0][0])[e] = 0u;
+        if (wave < NA) {
             const int a = wave, md = sm.mode[a];
             if (md == 1) {
                 if (lane == 0) {
@@ -270,24 +325,23 @@ __device__ __forceinline__ void box_select(bool in_lds, BoxSmem& sm, int c, int 
     }
 }
 
-__device__ __forceinline__ void box_median(const float* __restrict__ boxes, int b,
-                                           const int32_t* __restrict__ box_id,
+// Gather the points of box b with status 1: store(k, p, q) receives slot k
+// (0 <= k < CAP; points beyond CAP are counted but not stored) with the
+// point's position p in the first frame and q in the second, count receives
+// the number of points, and sel.klo/khi the range of the displacement keys
+// q - p per axis (sel.klo/khi initialised to the empty range and count to 0
+// before a barrier that precedes the call).  16 consecutive ids and statuses
+// per thread are in flight (vector loads when aligned); a wave-wide scan of
+// the per-thread match counts and one LDS atomic per wave reserve the slots,
+// so the slots' order is arbitrary.
+template <int CAP, class Store>
+__device__ __forceinline__ void box_gather(int b, const int32_t* __restrict__ box_id,
                                            const float* __restrict__ pts,
                                            const float* __restrict__ next_pts,
                                            const uint8_t* __restrict__ status, int n,
-                                           float* __restrict__ out_boxes,
-                                           int32_t* __restrict__ out_count, BoxSmem& sm) {
+                                           int32_t& count, SelSmem<2>& sel, Store&& store) {
     const int tid = threadIdx.x, lane = tid & 63;
-    if (tid == 0) sm.count = 0;
-    if (tid < 2) {
-        sm.klo[tid] = 0xFFFFFFFFu;
-        sm.khi[tid] = 0u;
-    }
-    for (int e = tid; e < 2 * BOX_NB; e += BOX_THREADS) (&sm.hist[0][0])[e] = 0u;
-    __syncthreads();
     uint32_t kmin[2] = {0xFFFFFFFFu, 0xFFFFFFFFu}, kmax[2] = {0u, 0u};
-    // gather: 16 consecutive ids and statuses per thread in flight (vector
-    // loads when aligned), then wave-ballot compaction of the matches into LDS
     const float2* __restrict__ p2 = reinterpret_cast<const float2*>(pts);
     const float2* __restrict__ n2 = reinterpret_cast<const float2*>(next_pts);
     const bool vec = ((reinterpret_cast<uintptr_t>(box_id) | reinterpret_cast<uintptr_t>(status)) & 15) == 0;
@@ -327,27 +381,20 @@ __device__ __forceinline__ void box_median(const float* __restrict__ boxes, int 
                 pb[j] = n2[i0 + j];
             }
         }
-        // the order of the gathered values does not matter: one wave-wide
-        // exclusive scan of the per-thread match counts and one LDS atomic
-        // per wave reserve the slots
         int mine = 0;
 #pragma unroll
         for (int j = 0; j < PT; ++j) mine += (id[j] == b && st[j] == 1u) ? 1 : 0;
         const int incl = (int)wave_incl_scan_u32((uint32_t)mine);
         const int wtot = __builtin_amdgcn_readlane(incl, 63);
         int off = 0;
-        if (lane == 0 && wtot) off = atomicAdd(&sm.count, wtot);
+        if (lane == 0 && wtot) off = atomicAdd(&count, wtot);
         int k = __builtin_amdgcn_readlane(off, 0) + incl - mine;
 #pragma unroll
         for (int j = 0; j < PT; ++j) {
             if (id[j] == b && st[j] == 1u) {
-                const float vx = pb[j].x - pa[j].x, vy = pb[j].y - pa[j].y;
-                if (k >= 0 && k < BOX_CAP) {
-                    sm.dx[k] = vx;
-                    sm.dy[k] = vy;
-                }
+                if (k >= 0 && k < CAP) store(k, pa[j], pb[j]);
                 ++k;
-                const uint32_t kx = f2key(vx), ky = f2key(vy);
+                const uint32_t kx = f2key(pb[j].x - pa[j].x), ky = f2key(pb[j].y - pa[j].y);
                 kmin[0] = min(kmin[0], kx);
                 kmax[0] = max(kmax[0], kx);
                 kmin[1] = min(kmin[1], ky);
@@ -359,21 +406,56 @@ __device__ __forceinline__ void box_median(const float* __restrict__ boxes, int 
     for (int a = 0; a < 2; ++a) {
         const uint32_t lo = wave_min_u32(kmin[a]), hi = wave_max_u32(kmax[a]);
         if (lane == 0 && lo <= hi) {
-            atomicMin(&sm.klo[a], lo);
-            atomicMax(&sm.khi[a], hi);
+            atomicMin(&sel.klo[a], lo);
+            atomicMax(&sel.khi[a], hi);
         }
     }
+}
+
+// Selection state set-up: empty key ranges and a zero histogram.
+template <int NA>
+__device__ __forceinline__ void sel_init(SelSmem<NA>& sel) {
+    const int tid = threadIdx.x;
+    if (tid < NA) {
+        sel.klo[tid] = 0xFFFFFFFFu;
+        sel.khi[tid] = 0u;
+    }
+    for (int e = tid; e < NA * BOX_NB; e += BOX_THREADS) (&sel.hist[0][0])[e] = 0u;
+}
+
+__device__ __forceinline__ void box_median(const float* __restrict__ boxes, int b,
+                                           const int32_t* __restrict__ box_id,
+                                           const float* __restrict__ pts,
+                                           const float* __restrict__ next_pts,
+                                           const uint8_t* __restrict__ status, int n,
+                                           float* __restrict__ out_boxes,
+                                           int32_t* __restrict__ out_count, BoxSmem& sm) {
+    const int tid = threadIdx.x;
+    if (tid == 0) sm.count = 0;
+    sel_init(sm.sel);
+    __syncthreads();
+    box_gather<BOX_CAP>(b, box_id, pts, next_pts, status, n, sm.count, sm.sel,
+                        [&](int k, float2 p, float2 q) {
+                            sm.dx[k] = q.x - p.x;
+                            sm.dy[k] = q.y - p.y;
+                        });
     __syncthreads();
     const int c = sm.count;
     float mx = 0.0f, my = 0.0f;
     if (c > 0) {
         if (tid < 2) {
-            sm.rank[tid][0] = (uint32_t)((c - 1) / 2);
-            sm.rank[tid][1] = (uint32_t)(c / 2);
+            sm.sel.rank[tid][0] = (uint32_t)((c - 1) / 2);
+            sm.sel.rank[tid][1] = (uint32_t)(c / 2);
         }
-        box_select(c <= BOX_CAP, sm, c, b, box_id, status, pts, next_pts, n);
-        mx = 0.5f * (key2f(sm.res[0][0]) + key2f(sm.res[0][1]));
-        my = 0.5f * (key2f(sm.res[1][0]) + key2f(sm.res[1][1]));
+        const bool in_lds = c <= BOX_CAP;
+        select_ranks<2>(sm.sel, true, [&](auto&& f) {
+            box_visit(in_lds, sm, c, b, box_id, status, pts, next_pts, n, [&](float vx, float vy) {
+                const float v[2] = {vx, vy};
+                f(v);
+            });
+        });
+        mx = 0.5f * (key2f(sm.sel.res[0][0]) + key2f(sm.sel.res[0][1]));
+        my = 0.5f * (key2f(sm.sel.res[1][0]) + key2f(sm.sel.res[1][1]));
     }
     if (tid == 0) {
         out_boxes[4 * b + 0] = boxes[4 * b + 0] + mx;
@@ -382,6 +464,175 @@ __device__ __forceinline__ void box_median(const float* __restrict__ boxes, int 
         out_boxes[4 * b + 3] = boxes[4 * b + 3] + my;
         out_count[b] = c;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Median-Flow box update (Kalal, Mikolajczyk and Matas 2010): the box's
+// centre moves by the component-wise median displacement of its tracked
+// points and its half-extents scale by the median, over all unordered pairs
+// of those points at distinct first-frame positions, of the ratio of the
+// pair's distance in the second frame to its distance in the first.  One
+// BOX_THREADS workgroup per box; up to SCALE_CAP points are gathered into
+// LDS.  The pair ratios are never stored: the selection visits every pair
+// once per pass, keyed by the squared ratio (monotone in the ratio), and the
+// two middle squared ratios are square-rooted at the end.
+// ---------------------------------------------------------------------------
+struct ScaleSmem {
+    float4 pu[SCALE_CAP];  // (x, y) in the first frame, (x, y) in the second
+    SelSmem<2> sel;        // displacement medians
+    SelSmem<1> rsel;       // ratio median
+    int32_t count;
+    uint32_t npairs;
+};
+
+// Visit every unordered pair {i, j} of the c gathered points once as f(r2),
+// r2 the squared distance ratio, skipping pairs whose squared first-frame
+// distance is zero.  Pair q of the c * floor((c-1)/2) + (c even ? c/2 : 0)
+// pairs is (i, (i + d) mod c) with i = q mod c and d = q / c + 1: every
+// circular distance d below c/2 pairs all c points, and for even c the
+// distance c/2 pairs only the first half.  Each thread steps q by BOX_THREADS.
+template <class F>
+__device__ __forceinline__ void visit_pairs(const float4* __restrict__ pu, int c, F&& f) {
+    const uint32_t uc = (uint32_t)c;
+    const uint32_t total = uc * ((uc - 1u) / 2u) + ((uc & 1u) ? 0u : uc / 2u);
+    const uint32_t t = threadIdx.x;
+    if (t >= total) return;
+    uint32_t d = t / uc, i = t - d * uc;
+    const uint32_t sd = (uint32_t)BOX_THREADS / uc, si = (uint32_t)BOX_THREADS - sd * uc;
+    for (uint32_t q = t; q < total; q += BOX_THREADS) {
+        uint32_t j = i + d + 1u;
+        if (j >= uc) j -= uc;
+        const float4 a = pu[i], e = pu[j];
+        const float ux = a.x - e.x, uy = a.y - e.y, vx = a.z - e.z, vy = a.w - e.w;
+        // explicit fmas: every pass must compute the same key for a pair
+        const float du2 = __builtin_fmaf(ux, ux, uy * uy);
+        const float dv2 = __builtin_fmaf(vx, vx, vy * vy);
+        if (du2 > 0.0f) {
+            const float v[1] = {dv2 * __builtin_amdgcn_rcpf(du2)};
+            f(v);
+        }
+        i += si;
+        d += sd;
+        if (i >= uc) {
+            i -= uc;
+            ++d;
+        }
+    }
+}
+
+__device__ __forceinline__ void box_scaled(const float* __restrict__ boxes, int b,
+                                           const int32_t* __restrict__ box_id,
+                                           const float* __restrict__ pts,
+                                           const float* __restrict__ next_pts,
+                                           const uint8_t* __restrict__ status, int n,
+                                           float* __restrict__ out_boxes,
+                                           int32_t* __restrict__ out_count,
+                                           float* __restrict__ out_scale, ScaleSmem& sm) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid == 0) {
+        sm.count = 0;
+        sm.npairs = 0u;
+    }
+    sel_init(sm.sel);
+    sel_init(sm.rsel);
+    __syncthreads();
+    box_gather<SCALE_CAP>(b, box_id, pts, next_pts, status, n, sm.count, sm.sel,
+                          [&](int k, float2 p, float2 q) { sm.pu[k] = make_float4(p.x, p.y, q.x, q.y); });
+    __syncthreads();
+    const int c = sm.count;
+    if (c > SCALE_CAP) {
+        // too many points for the pair pass: no result
+        if (tid == 0) {
+            const float nan = __builtin_nanf("");
+            for (int k = 0; k < 4; ++k) out_boxes[4 * b + k] = nan;
+            out_count[b] = c;
+            out_scale[b] = nan;
+        }
+        return;
+    }
+    float mx = 0.0f, my = 0.0f, s = 1.0f;
+    if (c > 0) {
+        if (tid < 2) {
+            sm.sel.rank[tid][0] = (uint32_t)((c - 1) / 2);
+            sm.sel.rank[tid][1] = (uint32_t)(c / 2);
+        }
+        select_ranks<2>(sm.sel, true, [&](auto&& f) {
+            for (int i = tid; i < c; i += BOX_THREADS) {
+                const float4 p = sm.pu[i];
+                const float v[2] = {p.z - p.x, p.w - p.y};
+                f(v);
+            }
+        });
+        mx = 0.5f * (key2f(sm.sel.res[0][0]) + key2f(sm.sel.res[0][1]));
+        my = 0.5f * (key2f(sm.sel.res[1][0]) + key2f(sm.sel.res[1][1]));
+        // pair pass: key range and number of pairs
+        uint32_t lo = 0xFFFFFFFFu, hi = 0u, np = 0u;
+        visit_pairs(sm.pu, c, [&](const float (&v)[1]) {
+            const uint32_t k = f2key(v[0]);
+            lo = min(lo, k);
+            hi = max(hi, k);
+            ++np;
+        });
+        lo = wave_min_u32(lo);
+        hi = wave_max_u32(hi);
+        np = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(np), 63);
+        if (lane == 0 && np > 0u) {
+            atomicMin(&sm.rsel.klo[0], lo);
+            atomicMax(&sm.rsel.khi[0], hi);
+            atomicAdd(&sm.npairs, np);
+        }
+        __syncthreads();
+        const uint32_t npairs = sm.npairs;
+        if (npairs > 0u) {
+            if (tid == 0) {
+                sm.rsel.rank[0][0] = (npairs - 1u) / 2u;
+                sm.rsel.rank[0][1] = npairs / 2u;
+            }
+            // the first round's buckets follow the key: ratio outliers would
+            // squeeze the bulk into a few value-linear buckets
+            select_ranks<1>(sm.rsel, false, [&](auto&& f) { visit_pairs(sm.pu, c, f); });
+            s = 0.5f * (__builtin_sqrtf(key2f(sm.rsel.res[0][0])) + __builtin_sqrtf(key2f(sm.rsel.res[0][1])));
+        }
+    }
+    if (tid == 0) {
+        const float x0 = boxes[4 * b + 0], y0 = boxes[4 * b + 1], x1 = boxes[4 * b + 2], y1 = boxes[4 * b + 3];
+        if (c > 0) {
+            const float cx = 0.5f * (x0 + x1) + mx, cy = 0.5f * (y0 + y1) + my;
+            const float hw = 0.5f * (x1 - x0), hh = 0.5f * (y1 - y0);
+            out_boxes[4 * b + 0] = cx - s * hw;
+            out_boxes[4 * b + 1] = cy - s * hh;
+            out_boxes[4 * b + 2] = cx + s * hw;
+            out_boxes[4 * b + 3] = cy + s * hh;
+        } else {
+            out_boxes[4 * b + 0] = x0;
+            out_boxes[4 * b + 1] = y0;
+            out_boxes[4 * b + 2] = x1;
+            out_boxes[4 * b + 3] = y1;
+        }
+        out_count[b] = c;
+        out_scale[b] = s;
+    }
+}
+
+// Forward-backward gate (Kalal et al. 2010): a point keeps status 1 when it
+// was tracked forward and back and lands within fb_max of where it started.
+__device__ __forceinline__ void fb_gate_point(const float* __restrict__ pts,
+                                              const float* __restrict__ back_pts,
+                                              const uint8_t* __restrict__ st_fwd,
+                                              const uint8_t* __restrict__ st_bwd, int i,
+                                              float fb_max, float* __restrict__ fb_err,
+                                              uint8_t* __restrict__ status_out) {
+    const float2 p = reinterpret_cast<const float2*>(pts)[i];
+    const float2 q = reinterpret_cast<const float2*>(back_pts)[i];
+    float e = -1.0f;
+    uint8_t st = 0;
+    if (st_fwd[i] == 1 && st_bwd[i] == 1) {
+        const float ex = p.x - q.x, ey = p.y - q.y;
+        e = __builtin_sqrtf(__builtin_fmaf(ex, ex, ey * ey));
+        st = e <= fb_max ? 1 : 0;
+    }
+    if (fb_err) fb_err[i] = e;
+    status_out[i] = st;
 }
 
 }  // namespace ot

@@ -44,6 +44,9 @@ OT_HD inline int pyr_stage_steps(int levels, int l0) {
 #endif
 constexpr int BOX_THREADS = OT_BOX_THREADS;
 constexpr int BOX_CAP = 6144;
+// Median-Flow box update: points per box it can take (all gathered in LDS,
+// 16 bytes each).
+constexpr int SCALE_CAP = OT_SCALE_MAX_POINTS;
 
 constexpr int LK_DEFAULT_MARGIN = 4;
 constexpr int LK_MAX_MARGIN = 16;

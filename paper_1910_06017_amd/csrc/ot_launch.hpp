@@ -24,6 +24,15 @@ hipError_t launch_box(const float* boxes, int m, const int32_t* box_id, const fl
                       const float* next_pts, const uint8_t* status, int n, float* out_boxes,
                       int32_t* out_count, hipStream_t stream);
 
+// Median-Flow box update (centre by the median displacement, extents by the
+// median pairwise distance ratio) and the forward-backward point gate.
+hipError_t launch_box_scaled(const float* boxes, int m, const int32_t* box_id, const float* pts,
+                             const float* next_pts, const uint8_t* status, int n, float* out_boxes,
+                             int32_t* out_count, float* out_scale, hipStream_t stream);
+hipError_t launch_fb_gate(const float* pts, const float* back_pts, const uint8_t* st_fwd,
+                          const uint8_t* st_bwd, int n, float fb_max, float* fb_err,
+                          uint8_t* status_out, hipStream_t stream);
+
 // Batched stages over a device table (layout TableLayout::make(cap)).
 hipError_t launch_batch_pyr(const uint8_t* table, int cap, int l0, int grid, hipStream_t stream);
 hipError_t launch_batch_lk(const uint8_t* table, int cap, int win, int margin, int grid,

@@ -102,6 +102,47 @@ hipError_t launch_box(const float* boxes, int m, const int32_t* box_id, const fl
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(BOX_THREADS) void k_box_scaled(const float* __restrict__ boxes,
+                                                            const int32_t* __restrict__ box_id,
+                                                            const float* __restrict__ pts,
+                                                            const float* __restrict__ next_pts,
+                                                            const uint8_t* __restrict__ status, int n,
+                                                            float* __restrict__ out_boxes,
+                                                            int32_t* __restrict__ out_count,
+                                                            float* __restrict__ out_scale) {
+    __shared__ ScaleSmem sm;
+    box_scaled(boxes, blockIdx.x, box_id, pts, next_pts, status, n, out_boxes, out_count, out_scale, sm);
+}
+
+hipError_t launch_box_scaled(const float* boxes, int m, const int32_t* box_id, const float* pts,
+                             const float* next_pts, const uint8_t* status, int n, float* out_boxes,
+                             int32_t* out_count, float* out_scale, hipStream_t stream) {
+    hipLaunchKernelGGL(k_box_scaled, dim3(m), dim3(BOX_THREADS), 0, stream, boxes, box_id, pts,
+                       next_pts, status, n, out_boxes, out_count, out_scale);
+    return hipGetLastError();
+}
+
+constexpr int FB_THREADS = 256;
+
+__global__ __launch_bounds__(FB_THREADS) void k_fb_gate(const float* __restrict__ pts,
+                                                        const float* __restrict__ back_pts,
+                                                        const uint8_t* __restrict__ st_fwd,
+                                                        const uint8_t* __restrict__ st_bwd, int n,
+                                                        float fb_max, float* __restrict__ fb_err,
+                                                        uint8_t* __restrict__ status_out) {
+    const int i = blockIdx.x * FB_THREADS + threadIdx.x;
+    if (i < n) fb_gate_point(pts, back_pts, st_fwd, st_bwd, i, fb_max, fb_err, status_out);
+}
+
+hipError_t launch_fb_gate(const float* pts, const float* back_pts, const uint8_t* st_fwd,
+                          const uint8_t* st_bwd, int n, float fb_max, float* fb_err,
+                          uint8_t* status_out, hipStream_t stream) {
+    const int grid = (n + FB_THREADS - 1) / FB_THREADS;
+    hipLaunchKernelGGL(k_fb_gate, dim3(grid), dim3(FB_THREADS), 0, stream, pts, back_pts, st_fwd,
+                       st_bwd, n, fb_max, fb_err, status_out);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(BOX_THREADS) void k_batch_box(const uint8_t* __restrict__ table,
                                                            int cap) {
     __shared__ BoxSmem sm;

@@ -22,8 +22,11 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 
 # Every symbol the header declares.
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
-           "ot_lk_track_ex", "ot_box_update", "ot_batch_table_bytes", "ot_batch_pack",
-           "ot_batch_run", "ot_strerror", "ot_version"]
+           "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled",
+           "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_strerror", "ot_version"]
+
+# Points per box the scaled box update takes (OT_SCALE_MAX_POINTS).
+SCALE_MAX_POINTS = 6144
 
 
 class OtError(RuntimeError):
@@ -90,6 +93,10 @@ def lib():
         L.ot_lk_track_ex.restype = i32
         L.ot_box_update.argtypes = [P, i32, P, P, P, P, i32, P, P, P]
         L.ot_box_update.restype = i32
+        L.ot_fb_gate.argtypes = [P, P, P, P, i32, f32, P, P, P]
+        L.ot_fb_gate.restype = i32
+        L.ot_box_update_scaled.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P]
+        L.ot_box_update_scaled.restype = i32
         L.ot_batch_table_bytes.argtypes = [C.POINTER(OtBatchCfg)]
         L.ot_batch_table_bytes.restype = sz
         L.ot_batch_pack.argtypes = [C.POINTER(OtJob), i32, C.POINTER(OtBatchCfg), P, sz, PP]
@@ -251,6 +258,56 @@ def box_update(boxes, box_id, pts, next_pts, status, out=None, stream=None):
                               _ptr(status), n, _ptr(ob), _ptr(oc), _stream_handle(stream)),
           "ot_box_update")
     return ob, oc
+
+
+def fb_gate(pts, back_pts, st_fwd, st_bwd, fb_max: float, want_err: bool = True,
+            out=None, stream=None):
+    """Forward-backward gate.  Returns (status (n,) uint8, fb_err (n,) float32
+    or None): a point keeps status 1 when both tracks succeeded and
+    |pts - back_pts| <= fb_max; fb_err is -1 where a track failed."""
+    torch = _torch()
+    _need(pts, torch.float32, 2, "pts")
+    _need(back_pts, torch.float32, 2, "back_pts")
+    _need(st_fwd, torch.uint8, None, "st_fwd")
+    _need(st_bwd, torch.uint8, None, "st_bwd")
+    n = pts.shape[0]
+    if back_pts.shape[0] != n or st_fwd.numel() != n or st_bwd.numel() != n:
+        raise ValueError("fb_gate: pts, back_pts, st_fwd and st_bwd must hold n points")
+    if out is None:
+        st = torch.empty(n, dtype=torch.uint8, device=pts.device)
+        fe = torch.empty(n, dtype=torch.float32, device=pts.device) if want_err else None
+    else:
+        st, fe = out
+    check(lib().ot_fb_gate(_ptr(pts), _ptr(back_pts), _ptr(st_fwd), _ptr(st_bwd), n,
+                           float(fb_max), _ptr(fe) if fe is not None else None, _ptr(st),
+                           _stream_handle(stream)), "ot_fb_gate")
+    return st, fe
+
+
+def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, stream=None):
+    """Median-Flow box update: the centre moves by the median displacement
+    and the half-extents scale by the median pairwise distance ratio.
+    Returns (out_boxes (m,4), out_count (m,), out_scale (m,))."""
+    torch = _torch()
+    _need(boxes, torch.float32, 4, "boxes")
+    _need(pts, torch.float32, 2, "pts")
+    _need(next_pts, torch.float32, 2, "next_pts")
+    _need(box_id, torch.int32, None, "box_id")
+    _need(status, torch.uint8, None, "status")
+    m = boxes.shape[0]
+    n = pts.shape[0]
+    if next_pts.shape[0] != n or box_id.numel() != n or status.numel() != n:
+        raise ValueError("box_update_scaled: pts, next_pts, box_id and status must hold n points")
+    if out is None:
+        ob = torch.empty((m, 4), dtype=torch.float32, device=boxes.device)
+        oc = torch.empty(m, dtype=torch.int32, device=boxes.device)
+        os_ = torch.empty(m, dtype=torch.float32, device=boxes.device)
+    else:
+        ob, oc, os_ = out
+    check(lib().ot_box_update_scaled(_ptr(boxes), m, _ptr(box_id), _ptr(pts), _ptr(next_pts),
+                                     _ptr(status), n, _ptr(ob), _ptr(oc), _ptr(os_),
+                                     _stream_handle(stream)), "ot_box_update_scaled")
+    return ob, oc, os_
 
 
 def strerror(code: int) -> str:

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 11
+    assert len(syms) == 13
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -150,6 +150,36 @@ def test_box_validation(L):
     assert L.ot_box_update(FAKE, 3, None, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None) == E
     assert L.ot_box_update(None, 0, None, None, None, None, 5, None, None, None) == 0
     assert L.ot_box_update(FAKE, 3, FAKE, FAKE + 4, FAKE, FAKE, 5, FAKE, FAKE, None) == E  # pts not 8-aligned
+
+
+def test_fb_gate_validation(L):
+    E = ops_err("OT_E_INVAL")
+    g = L.ot_fb_gate
+    assert g(FAKE, FAKE, FAKE, FAKE, -1, 1.0, FAKE, FAKE, None) == E
+    assert g(FAKE, FAKE, FAKE, FAKE, 5, -0.5, FAKE, FAKE, None) == E          # negative threshold
+    assert g(FAKE, FAKE, FAKE, FAKE, 5, float("nan"), FAKE, FAKE, None) == E
+    assert g(None, FAKE, FAKE, FAKE, 5, 1.0, FAKE, FAKE, None) == E
+    assert g(FAKE, FAKE, FAKE, None, 5, 1.0, FAKE, FAKE, None) == E
+    assert g(FAKE, FAKE, FAKE, FAKE, 5, 1.0, FAKE, None, None) == E           # no status output
+    assert g(FAKE, FAKE + 4, FAKE, FAKE, 5, 1.0, FAKE, FAKE, None) == E       # back_pts not 8-aligned
+    assert g(FAKE, FAKE, FAKE, FAKE, 5, 1.0, FAKE + 2, FAKE, None) == E       # fb_err not 4-aligned
+    assert g(None, None, None, None, 0, 1.0, None, None, None) == 0           # n == 0: no-op
+
+
+def test_box_scaled_validation(L):
+    E = ops_err("OT_E_INVAL")
+    u = L.ot_box_update_scaled
+    assert u(FAKE, -1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, -5, FAKE, FAKE, FAKE, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None, None) == E  # no scale output
+    assert u(FAKE, 3, None, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE + 4, FAKE, 5, FAKE, FAKE, FAKE, None) == E  # next_pts not 8-aligned
+    assert u(None, 0, None, None, None, None, 5, None, None, None, None) == 0
+
+
+def test_scale_cap_matches_header():
+    txt = open(HEADER).read()
+    assert re.search(r"#define OT_SCALE_MAX_POINTS (\d+)", txt).group(1) == str(ops.SCALE_MAX_POINTS)
 
 
 def make_cfg(**kw):

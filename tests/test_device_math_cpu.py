@@ -21,3 +21,40 @@ def test_reciprocal_small_division_is_exact():
         for r in cands:
             q = np.floor((a + np.float32(0.5)) * r).astype(np.int64)
             assert np.array_equal(q, want), (b, r)
+
+
+def _pairs_like_kernel(c, threads):
+    """The scaled box update's pair walk: pair q of c*floor((c-1)/2) +
+    (c even ? c/2 : 0) is (q mod c, (q mod c + q div c + 1) mod c); each
+    thread starts at q = t and steps by `threads` with an incremental
+    (d, i) update in place of a division."""
+    total = c * ((c - 1) // 2) + (0 if c & 1 else c // 2)
+    out = []
+    for t in range(min(threads, total)):
+        d, i = t // c, t % c
+        sd, si = threads // c, threads % c
+        q = t
+        while q < total:
+            j = i + d + 1
+            if j >= c:
+                j -= c
+            assert 0 <= i < c and 0 <= j < c
+            out.append((i, j))
+            i += si
+            d += sd
+            if i >= c:
+                i -= c
+                d += 1
+            q += threads
+    return out
+
+
+def test_pair_walk_visits_every_unordered_pair_once():
+    for threads, cs in ((1024, list(range(1, 70)) + [511, 512, 1023, 1024, 1025, 2049]),
+                        (64, list(range(1, 70)) + [129]), (7, list(range(1, 40)))):
+        for c in cs:
+            got = _pairs_like_kernel(c, threads)
+            assert len(got) == c * (c - 1) // 2, (c, threads)
+            keys = {(min(i, j), max(i, j)) for i, j in got}
+            assert len(keys) == len(got), (c, threads)
+            assert all(i != j for i, j in got)

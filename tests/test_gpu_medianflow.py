@@ -1,0 +1,282 @@
+"""Median Flow on the GPU (forward-backward gate and scaled box update)
+against the CPU oracle, through the C ABI.
+
+Same-input parity: both sides get identical float32 inputs.  The gate's
+error is one float32 subtraction per axis, a fused multiply-add and a
+correctly rounded square root, so it lies within a few float32 ulps of the
+oracle's FP64 value (rtol 2e-6); its status must match wherever the FP64
+error is not within 1e-5 px of the threshold.  The scaled update selects
+exact order statistics of float32 keys; a float32 pair ratio is within
+about 4 ulps of the FP64 one, and an order statistic moves by at most the
+largest perturbation of its inputs, so the scale matches within 1e-5
+(relative) and box corners (|value| < 2048 px, a few float32 roundings)
+within 1e-3 px.  Counts are exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_06017_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ERR_RTOL = 2e-6
+SCALE_RTOL = 1e-5
+BOX_ATOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_06017_amd import ops as o
+    o.lib()
+    return o
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def gate_inputs(seed, n, fb_max):
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform([0, 0], [1920, 1080], (n, 2)).astype(np.float32)
+    off = rng.normal(0.0, 1.5 * fb_max, (n, 2))
+    back = (pts + off).astype(np.float32)
+    sf = (rng.random(n) < 0.92).astype(np.uint8)
+    sb = (rng.random(n) < 0.92).astype(np.uint8)
+    sf[rng.random(n) < 0.01] = 7      # only status 1 counts as tracked
+    return pts, back, sf, sb
+
+
+def check_gate(ops, pts, back, sf, sb, fb_max):
+    st, fe = ops.fb_gate(dev(pts), dev(back), dev(sf), dev(sb), fb_max)
+    torch.cuda.synchronize()
+    st, fe = host(st), host(fe)
+    oe, ost = oracle.fb_gate(pts, back, sf, sb, fb_max)
+    both = (sf == 1) & (sb == 1)
+    assert np.all(fe[~both] == -1.0)
+    np.testing.assert_allclose(fe[both], oe[both], rtol=ERR_RTOL, atol=1e-6)
+    sure = np.abs(oe - fb_max) > 1e-5
+    assert np.array_equal(st[sure], ost[sure])
+    assert np.all(st[~both] == 0)
+    return st, fe, oe
+
+
+@pytest.mark.parametrize("n,fb_max,seed", [(1, 1.0, 1), (255, 0.5, 2), (10007, 1.0, 3),
+                                           (200003, 2.0, 4)])
+def test_fb_gate_matches_oracle(ops, n, fb_max, seed):
+    pts, back, sf, sb = gate_inputs(seed, n, fb_max)
+    check_gate(ops, pts, back, sf, sb, fb_max)
+
+
+def test_fb_gate_threshold_inclusive_and_exact(ops):
+    # offsets (3/4, 1) and (-3, 4) have exact float32 lengths 1.25 and 5
+    pts = np.array([[100.5, 200.25], [10.0, 10.0], [640.0, 360.0], [0.0, 0.0]], np.float32)
+    back = pts + np.array([[0.75, 1.0], [-3.0, 4.0], [0.0, 0.0], [0.0, 0.0]], np.float32)
+    one = np.ones(4, np.uint8)
+    st, fe = ops.fb_gate(dev(pts), dev(back), dev(one), dev(one), 1.25)
+    assert host(fe).tolist() == [1.25, 5.0, 0.0, 0.0]
+    assert host(st).tolist() == [1, 0, 1, 1]
+    st, fe = ops.fb_gate(dev(pts), dev(back), dev(one), dev(one), 5.0, want_err=False)
+    assert fe is None and host(st).tolist() == [1, 1, 1, 1]
+    st, _ = ops.fb_gate(dev(pts), dev(back), dev(one), dev(one), 0.0)
+    assert host(st).tolist() == [0, 0, 1, 1]
+
+
+def test_fb_gate_in_place_and_empty(ops):
+    pts, back, sf, sb = gate_inputs(5, 3001, 1.0)
+    _, ost = oracle.fb_gate(pts, back, sf, sb, 1.0)
+    oe, _ = oracle.fb_gate(pts, back, sf, sb, 1.0)
+    s_dev = dev(sf)
+    st, _ = ops.fb_gate(dev(pts), dev(back), s_dev, dev(sb), 1.0, out=(s_dev, None))
+    torch.cuda.synchronize()
+    sure = np.abs(oe - 1.0) > 1e-5
+    assert np.array_equal(host(s_dev)[sure], ost[sure])
+    z2 = torch.zeros((0, 2), dtype=torch.float32, device="cuda")
+    z1 = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    st, fe = ops.fb_gate(z2, z2, z1, z1, 1.0)
+    assert st.numel() == 0 and fe.numel() == 0
+
+
+# ---------------------------------------------------------------- scaled box
+def box_scene(seed, counts, outlier_frac=0.1, lost_frac=0.05, dup=False, extra_ids=True):
+    """Boxes with `counts[b]` points each, moving by a similarity plus noise,
+    some outliers and lost points, ids interleaved in random order."""
+    rng = np.random.default_rng(seed)
+    m = len(counts)
+    boxes, P, Q, ids = [], [], [], []
+    for b, c in enumerate(counts):
+        w, h = rng.uniform(20, 400, 2)
+        x0, y0 = rng.uniform(0, 1500), rng.uniform(0, 700)
+        boxes.append([x0, y0, x0 + w, y0 + h])
+        s = rng.uniform(0.9, 1.1)
+        t = rng.uniform(-30, 30, 2)
+        p = rng.uniform([x0, y0], [x0 + w, y0 + h], (c, 2))
+        if dup and c > 4:
+            p[c // 2:] = p[: c - c // 2]   # every point has a coincident twin
+        cen = np.array([x0 + w / 2, y0 + h / 2])
+        q = cen + t + s * (p - cen) + rng.normal(0, 0.05, (c, 2))
+        bad = rng.random(c) < outlier_frac
+        q[bad] += rng.normal(0, 25, (bad.sum(), 2))
+        P.append(p)
+        Q.append(q)
+        ids.append(np.full(c, b, np.int32))
+    P = np.concatenate(P) if P else np.zeros((0, 2))
+    Q = np.concatenate(Q) if Q else np.zeros((0, 2))
+    ids = np.concatenate(ids) if ids else np.zeros(0, np.int32)
+    if extra_ids:
+        k = max(1, len(ids) // 50)
+        P = np.concatenate([P, rng.uniform(0, 1000, (k, 2))])
+        Q = np.concatenate([Q, rng.uniform(0, 1000, (k, 2))])
+        ids = np.concatenate([ids, rng.choice([-1, m, m + 7], k).astype(np.int32)])
+    st = (rng.random(len(ids)) >= lost_frac).astype(np.uint8)
+    perm = rng.permutation(len(ids))
+    return (np.asarray(boxes, np.float32), ids[perm].astype(np.int32), P[perm].astype(np.float32),
+            Q[perm].astype(np.float32), st[perm])
+
+
+def run_scaled(ops, boxes, ids, P, Q, st):
+    ob, oc, os_ = ops.box_update_scaled(dev(boxes), dev(ids), dev(P), dev(Q), dev(st))
+    torch.cuda.synchronize()
+    return host(ob), host(oc), host(os_)
+
+
+def check_scaled(ops, boxes, ids, P, Q, st):
+    g = run_scaled(ops, boxes, ids, P, Q, st)
+    ob, oc, os_ = oracle.box_update_scaled(boxes, ids, P, Q, st)
+    assert np.array_equal(g[1], oc)
+    np.testing.assert_allclose(g[2], os_, rtol=SCALE_RTOL, atol=0)
+    np.testing.assert_allclose(g[0], ob, rtol=0, atol=BOX_ATOL)
+    return g, (ob, oc, os_)
+
+
+@pytest.mark.parametrize("counts,seed", [
+    ([0, 1, 2, 3, 4, 5, 17, 64, 65], 11),
+    ([400] * 20, 12),
+    ([1023, 1024, 1025, 2049], 13),
+    ([3000, 7], 14),
+])
+def test_box_scaled_matches_oracle(ops, counts, seed):
+    check_scaled(ops, *box_scene(seed, counts))
+
+
+def test_box_scaled_at_cap(ops):
+    cap = ops.SCALE_MAX_POINTS
+    boxes, ids, P, Q, st = box_scene(15, [cap, 100], lost_frac=0.0)
+    g, _ = check_scaled(ops, boxes, ids, P, Q, st)
+    assert g[1][0] == cap
+
+
+def test_box_scaled_duplicates_and_no_pairs(ops):
+    boxes, ids, P, Q, st = box_scene(21, [200, 9, 3, 2], dup=True, lost_frac=0.0,
+                                     extra_ids=False)
+    # box 2: three coincident points (no pair of distinct positions) -> scale 1
+    sel = np.where(ids == 2)[0]
+    P[sel] = P[sel[0]]
+    g, o = check_scaled(ops, boxes, ids, P, Q, st)
+    assert g[2][2] == 1.0 and o[2][2] == 1.0
+    # box 3: two points, one pair -> that pair's ratio
+    sel = np.where(ids == 3)[0]
+    r = np.linalg.norm(Q[sel[0]].astype(np.float64) - Q[sel[1]]) / \
+        np.linalg.norm(P[sel[0]].astype(np.float64) - P[sel[1]])
+    assert abs(g[2][3] - r) <= SCALE_RTOL * r
+
+
+def test_box_scaled_empty_and_lost(ops):
+    boxes, ids, P, Q, st = box_scene(22, [50, 30, 0], extra_ids=True)
+    st[ids == 1] = 0                      # every point of box 1 lost
+    g, _ = check_scaled(ops, boxes, ids, P, Q, st)
+    assert g[1][1] == 0 and g[1][2] == 0
+    assert np.array_equal(g[0][1], boxes[1]) and np.array_equal(g[0][2], boxes[2])
+    assert g[2][1] == 1.0 and g[2][2] == 1.0
+    # no points at all
+    e2 = np.zeros((0, 2), np.float32)
+    ob, oc, os_ = ops.box_update_scaled(dev(boxes), dev(np.zeros(0, np.int32)), dev(e2), dev(e2),
+                                        dev(np.zeros(0, np.uint8)))
+    assert np.array_equal(host(ob), boxes) and host(oc).tolist() == [0, 0, 0]
+    assert host(os_).tolist() == [1.0, 1.0, 1.0]
+
+
+def test_box_scaled_order_independent(ops):
+    """The selection is exact, so the point order cannot change a bit."""
+    boxes, ids, P, Q, st = box_scene(23, [700, 333, 1500])
+    g1 = run_scaled(ops, boxes, ids, P, Q, st)
+    perm = np.random.default_rng(5).permutation(len(ids))
+    g2 = run_scaled(ops, boxes, ids[perm], P[perm], Q[perm], st[perm])
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+
+
+def test_box_scaled_over_cap(ops):
+    cap = ops.SCALE_MAX_POINTS
+    boxes, ids, P, Q, st = box_scene(24, [cap + 1, 10], lost_frac=0.0, extra_ids=False)
+    ob, oc, os_ = run_scaled(ops, boxes, ids, P, Q, st)
+    assert oc.tolist() == [cap + 1, 10]
+    assert np.all(np.isnan(ob[0])) and np.isnan(os_[0])
+    o = oracle.box_update_scaled(boxes[1:], ids[ids == 1] - 1, P[ids == 1], Q[ids == 1],
+                                 st[ids == 1])
+    np.testing.assert_allclose(os_[1], o[2][0], rtol=SCALE_RTOL)
+    np.testing.assert_allclose(ob[1], o[0][0], atol=BOX_ATOL)
+
+
+# ---------------------------------------------------------------- end to end
+def test_median_flow_pipeline_sd_boxes(ops):
+    """Forward and backward tracking on the 720x576 boxes pair, the gate and
+    the scaled update on the GPU.  The gate and update must match the oracle
+    on the GPU's own tracks, and the whole GPU pipeline the oracle's own
+    pipeline.  On this scene a quarter of the forward tracks are off by more
+    than 12 px (small boxes moving up to 20 px, coarse windows dominated by
+    the static background); the 1 px gate drops those and keeps about 60 %
+    of the points."""
+    w = synth.sd_boxes_workload()
+    P = ops.pyramid_build(dev(w.frame0), w.levels)
+    Q = ops.pyramid_build(dev(w.frame1), w.levels)
+    pts = dev(w.pts)
+    nxt, sf, _ = ops.lk_track(P, Q, pts, win=w.win, levels=w.levels, iters=w.iters, eps=w.eps)
+    back, sb, _ = ops.lk_track(Q, P, nxt, win=w.win, levels=w.levels, iters=w.iters, eps=w.eps)
+    fb_max = 1.0
+    st, fe = ops.fb_gate(pts, back, sf, sb, fb_max)
+    ob, oc, os_ = ops.box_update_scaled(dev(w.boxes), dev(w.box_id), pts, nxt, st)
+    torch.cuda.synchronize()
+    nxt_h, back_h, sf_h, sb_h = host(nxt), host(back), host(sf), host(sb)
+    oe, ost = oracle.fb_gate(w.pts, back_h, sf_h, sb_h, fb_max)
+    np.testing.assert_allclose(host(fe)[oe >= 0], oe[oe >= 0], rtol=ERR_RTOL, atol=1e-6)
+    sure = np.abs(oe - fb_max) > 1e-5
+    st_h = host(st)
+    assert np.array_equal(st_h[sure], ost[sure])
+    # the update on exactly the GPU's statuses
+    o_b, o_c, o_s = oracle.box_update_scaled(w.boxes, w.box_id, w.pts, nxt_h, st_h)
+    assert np.array_equal(host(oc), o_c)
+    np.testing.assert_allclose(host(os_), o_s, rtol=SCALE_RTOL)
+    np.testing.assert_allclose(host(ob), o_b, atol=BOX_ATOL)
+    # the whole pipeline in the oracle: its own forward and backward tracks.
+    # Tracks agree within 0.01 px, so statuses may differ near the gate's
+    # threshold and ratios of close pairs move by up to 0.02 px / distance:
+    # the scale must agree within 2e-3 and the boxes within 0.25 px.
+    kw = dict(win=w.win, levels=w.levels, iters=w.iters, eps=float(np.float32(w.eps)))
+    fw = oracle.lk_track(w.frame0, w.frame1, w.pts, **kw)
+    bw = oracle.lk_track(w.frame1, w.frame0, fw.next_pts.astype(np.float32), **kw)
+    _, pst = oracle.fb_gate(w.pts, bw.next_pts, fw.status, bw.status, fb_max)
+    p_b, p_c, p_s = oracle.box_update_scaled(w.boxes, w.box_id, w.pts, fw.next_pts, pst)
+    gs, gb, gc = host(os_), host(ob), host(oc)
+    agree = float((pst == st_h).mean())
+    ds, db = np.abs(gs - p_s).max(), np.abs(gb - p_b).max()
+    b0 = w.boxes.astype(np.float64)
+    s_true = (w.boxes_next[:, 2] - w.boxes_next[:, 0]) / (b0[:, 2] - b0[:, 0])
+    print(f"median flow sd_boxes: kept {st_h.mean():.4f}, gate agreement {agree:.5f}, "
+          f"scale diff {ds:.2e}, box diff {db:.3f} px, count diff "
+          f"{np.abs(gc - p_c).max()}, median |scale - truth| {np.median(np.abs(gs - s_true)):.4f}")
+    assert agree >= 0.995
+    assert np.all(np.abs(gc - p_c) <= 0.01 * p_c + 1)
+    assert ds <= 2e-3 and db <= 0.25
+    # window contamination at box borders biases some small boxes; the
+    # median box still follows its true scale
+    assert np.median(np.abs(gs - s_true)) < 0.01
+    assert st_h.mean() > 0.5
