@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "omnitrack_oracle.c")
 
+from .matching import assign, iou, iou_matrix, track_update  # noqa: E402,F401
+
 GATE_MIN_EIG = 6.5025  # lambda_min / N threshold, (gray levels per pixel)^2 (= 1e-4 on [0,1])
 
 

@@ -502,6 +502,157 @@ def check_fb_roundtrip_shift():
     assert np.median(err[ok]) < 0.005 and err[ok].max() < 0.02, (np.median(err[ok]), err[ok].max())
 
 
+# ------------------------------------------------------- matching and update
+def check_iou_closed_forms():
+    """Hand-computed IoU values of simple configurations."""
+    cases = [([0, 0, 4, 4], [0, 0, 4, 4], 1.0),           # identical
+             ([0, 0, 1, 1], [2, 2, 3, 3], 0.0),           # disjoint
+             ([0, 0, 1, 1], [1, 0, 2, 1], 0.0),           # touching edges
+             ([0, 0, 2, 1], [1, 0, 3, 1], 1.0 / 3.0),     # half overlap
+             ([0, 0, 4, 4], [1, 1, 3, 3], 0.25),          # nested
+             ([0, 1, 4, 2], [1, 0, 2, 4], 1.0 / 7.0),     # a cross
+             ([0, 0, 0, 5], [0, 0, 0, 5], 0.0),           # zero-area boxes
+             ([3, 3, 1, 1], [0, 0, 4, 4], 0.0),           # inverted box has no area
+             ([-2, -1, 2, 1], [0, -1, 4, 1], 1.0 / 3.0)]  # negative coordinates
+    for a, b, want in cases:
+        for x, y in ((a, b), (b, a)):
+            got = oracle.iou(x, y)
+            assert abs(got - want) < 1e-15, (x, y, got, want)
+    M = oracle.iou_matrix([c[0] for c in cases], [c[1] for c in cases])
+    assert np.allclose(np.diag(M), [c[2] for c in cases], atol=1e-15)
+
+
+def check_iou_raster():
+    """Integer boxes: IoU equals the ratio of unit cells counted on a grid."""
+    rng = np.random.default_rng(41)
+    for _ in range(200):
+        a = np.sort(rng.integers(0, 12, (2, 2)), axis=0).T.ravel()[[0, 2, 1, 3]]
+        b = np.sort(rng.integers(0, 12, (2, 2)), axis=0).T.ravel()[[0, 2, 1, 3]]
+        A = np.zeros((12, 12), bool)
+        B = np.zeros((12, 12), bool)
+        A[a[1]:a[3], a[0]:a[2]] = True
+        B[b[1]:b[3], b[0]:b[2]] = True
+        u = (A | B).sum()
+        want = (A & B).sum() / u if u else 0.0
+        assert abs(oracle.iou(a, b) - want) < 1e-15, (a, b)
+
+
+def check_iou_matrix_invariants():
+    """Symmetry, invariance under a common translation and scaling, zero
+    rows for inactive objects, empty shapes."""
+    rng = np.random.default_rng(42)
+    S = rng.uniform(0, 100, (7, 4))
+    S[:, 2:] = S[:, :2] + rng.uniform(1, 50, (7, 2))
+    D = S[[1, 3, 5, 0, 2]] + rng.normal(0, 5, (5, 4))
+    M = oracle.iou_matrix(S, D)
+    assert np.allclose(M, oracle.iou_matrix(D, S).T, atol=1e-15)
+    T = np.array([13.5, -7.25, 13.5, -7.25])
+    assert np.allclose(M, oracle.iou_matrix(2.5 * S + T, 2.5 * D + T), atol=1e-12)
+    act = np.array([1, 0, 1, 1, 0, 1, 1], np.uint8)
+    Ma = oracle.iou_matrix(S, D, active=act)
+    assert np.all(Ma[act == 0] == 0) and np.array_equal(Ma[act == 1], M[act == 1])
+    assert oracle.iou_matrix(np.zeros((0, 4)), D).shape == (0, 5)
+    assert oracle.iou_matrix(S, np.zeros((0, 4))).shape == (7, 0)
+
+
+def _brute_assign(w, iou_min):
+    """Best summed IoU over every one-to-one partial matching."""
+    import itertools
+    m, k = w.shape
+    best = 0.0
+    for r in range(0, min(m, k) + 1):
+        for rows in itertools.combinations(range(m), r):
+            for cols in itertools.permutations(range(k), r):
+                if all(w[i, j] >= iou_min for i, j in zip(rows, cols)):
+                    best = max(best, sum(w[i, j] for i, j in zip(rows, cols)))
+    return best
+
+
+def _valid_matching(w, iou_min, s2d, d2s, score):
+    m, k = w.shape
+    tot = 0.0
+    for i in range(m):
+        if s2d[i] >= 0:
+            assert d2s[s2d[i]] == i and w[i, s2d[i]] >= iou_min
+            tot += w[i, s2d[i]]
+    for j in range(k):
+        if d2s[j] >= 0:
+            assert s2d[d2s[j]] == j
+    assert abs(tot - score) < 1e-12
+
+
+def check_assign_bruteforce():
+    """The optimal score equals exhaustive search on small problems."""
+    rng = np.random.default_rng(43)
+    for _ in range(120):
+        m, k = rng.integers(0, 6, 2)
+        w = rng.uniform(0, 1, (m, k)) * (rng.uniform(size=(m, k)) < 0.6)
+        iou_min = float(rng.choice([0.1, 0.3, 0.5]))
+        s2d, d2s, score = oracle.assign(w, iou_min)
+        _valid_matching(w, iou_min, s2d, d2s, score)
+        assert abs(score - _brute_assign(w, iou_min)) < 1e-12, (w, iou_min)
+
+
+def check_assign_not_greedy_and_threshold():
+    """Greedy takes (0,0) = 0.9 and leaves row 1 unmatched; the optimum
+    pairs crosswise (0.8 + 0.85).  The threshold is inclusive."""
+    w = np.array([[0.9, 0.8], [0.85, 0.0]])
+    s2d, d2s, score = oracle.assign(w, 0.3)
+    assert s2d.tolist() == [1, 0] and d2s.tolist() == [1, 0] and abs(score - 1.65) < 1e-15
+    w = np.array([[0.3, 0.0], [0.0, 0.2999999]])
+    s2d, d2s, score = oracle.assign(w, 0.3)
+    assert s2d.tolist() == [0, -1] and d2s.tolist() == [0, -1]
+    s2d, d2s, score = oracle.assign(np.zeros((3, 0)), 0.3)
+    assert s2d.tolist() == [-1, -1, -1] and score == 0.0
+
+
+def check_track_update():
+    """Matched objects take the detection's box, unmatched active ones are
+    lost, lost ones stay untouched, unmatched detections become new objects
+    with consecutive ids."""
+    boxes = np.array([[0, 0, 10, 10], [20, 20, 30, 30], [50, 50, 60, 60], [70, 70, 80, 80]],
+                     np.float64)
+    ids = np.array([4, 7, 9, 11], np.int32)
+    lost = np.array([0, 0, 1, 0], np.uint8)
+    det = np.array([[21, 19, 31, 29], [100, 100, 110, 110], [1, 1, 11, 11],
+                    [200, 0, 210, 10]], np.float64)
+    s2d = np.array([2, 0, -1, -1], np.int32)
+    d2s = np.array([1, -1, 0, -1], np.int32)
+    nb, ni, nl, nid = oracle.track_update(boxes, ids, lost, det, s2d, d2s, 12)
+    assert np.array_equal(nb[:4], [det[2], det[0], boxes[2], boxes[3]])
+    assert np.array_equal(nb[4:], [det[1], det[3]])
+    assert ni.tolist() == [4, 7, 9, 11, 12, 13] and nid == 14
+    assert nl.tolist() == [0, 0, 1, 1, 0, 0]
+    # a lost object stays as it is even when a matching names it
+    s2d = np.array([2, 0, 3, -1], np.int32)
+    d2s = np.array([1, -1, 0, 2], np.int32)
+    nb, ni, nl, nid = oracle.track_update(boxes, ids, lost, det, s2d, d2s, 12)
+    assert np.array_equal(nb[2], boxes[2]) and nl[2] == 1 and len(nb) == 5
+
+
+def check_match_pipeline():
+    """IoU, matching and update together: detections are the objects'
+    boxes slightly moved, one missing, two new."""
+    rng = np.random.default_rng(44)
+    S = rng.uniform(0, 500, (6, 2))
+    S = np.concatenate([S, S + rng.uniform(30, 80, (6, 2))], axis=1)
+    D = np.concatenate([S[[0, 1, 2, 4, 5]] + rng.normal(0, 2, (5, 4)),
+                        [[900, 900, 950, 950], [1000, 0, 1040, 40]]])
+    perm = rng.permutation(len(D))
+    D = D[perm]
+    M = oracle.iou_matrix(S, D)
+    s2d, d2s, _ = oracle.assign(M, 0.3)
+    nb, ni, nl, nid = oracle.track_update(S, np.arange(6), np.zeros(6, np.uint8), D, s2d, d2s, 6)
+    inv = np.argsort(perm)
+    assert s2d.tolist() == [inv[0], inv[1], inv[2], -1, inv[3], inv[4]]
+    assert nl.tolist() == [0, 0, 0, 1, 0, 0, 0, 0] and nid == 8
+    assert np.array_equal(np.sort(nb[6:, 0]), [900, 1000])
+
+
+MATCHING = [check_iou_closed_forms, check_iou_raster, check_iou_matrix_invariants,
+            check_assign_bruteforce, check_assign_not_greedy_and_threshold, check_track_update,
+            check_match_pipeline]
+
 ALL = [check_level_dims, check_pyr_down_library, check_pyramid_closed_forms,
        check_scharr_library, check_scharr_closed_forms, check_bilinear_affine,
        check_bilinear_library, check_structure_tensor_ramp, check_structure_tensor_quadratic,
@@ -511,4 +662,4 @@ ALL = [check_level_dims, check_pyr_down_library, check_pyramid_closed_forms,
        check_lk_structure_tensor_closed_form, check_two_motions,
        check_box_translation, check_box_median_library, check_box_outliers,
        check_scaled_box_translation, check_scaled_box_similarity, check_scaled_box_bruteforce,
-       check_scaled_box_outliers, check_fb_gate, check_fb_roundtrip_shift]
+       check_scaled_box_outliers, check_fb_gate, check_fb_roundtrip_shift] + MATCHING

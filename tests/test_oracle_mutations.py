@@ -75,3 +75,65 @@ def test_planted_mistake_is_caught(orc, tmp_path, name):
     with oracle.use_library(lib):
         failed = _run_pins()
     assert failed, f"no pin caught the planted mistake {name}"
+
+
+# Planted mistakes in a copy of the matching/update oracle (Python source).
+MATCH_SRC = os.path.join(os.path.dirname(oracle.__file__), "matching.py")
+GREEDY = '''
+
+def _greedy(gain):
+    g = gain.copy()
+    rows, cols = [], []
+    while g.size and g.max() > 0:
+        r, c = divmod(int(g.argmax()), g.shape[1])
+        rows.append(r)
+        cols.append(c)
+        g[r, :] = 0
+        g[:, c] = 0
+    return rows, cols
+'''
+
+MATCH_MUTATIONS = {
+    "iou_union_keeps_intersection": ("box_area(a) + box_area(b) - inter", "box_area(a) + box_area(b)", ""),
+    "iou_intersection_uses_max": ("ix = max(0.0, min(float(a[2]), float(b[2]))",
+                                  "ix = max(0.0, max(float(a[2]), float(b[2]))", ""),
+    "iou_negative_overlap": ("iy = max(0.0, ", "iy = abs(", ""),
+    "area_from_x_only": ("* max(0.0, float(b[3]) - float(b[1]))", "* max(0.0, float(b[2]) - float(b[0]))", ""),
+    "assign_greedy": ("rows, cols = scipy.optimize.linear_sum_assignment(gain, maximize=True)",
+                      "rows, cols = _greedy(gain)", GREEDY),
+    "assign_minimizes": ("maximize=True", "maximize=False", ""),
+    "assign_threshold_exclusive": ("if w[r, c] >= iou_min:", "if w[r, c] > iou_min:", ""),
+    "assign_ignores_threshold": ("gain = np.where(w >= iou_min, w, 0.0)", "gain = w", ""),
+    "update_no_lost_flag": ("            lost[i] = 1", "            pass", ""),
+    "update_no_new_objects": ("if d2s[j] < 0:", "if False:", ""),
+    "update_keeps_predicted_box": ("boxes[i] = det[s2d[i]].copy()", "pass", ""),
+    "update_revives_lost": ("        if lost[i]:\n            continue\n", "", ""),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MATCH_MUTATIONS))
+def test_planted_matching_mistake_is_caught(tmp_path, name):
+    import importlib.util
+    old, new, extra = MATCH_MUTATIONS[name]
+    src = open(MATCH_SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    path = tmp_path / "matching_mut.py"
+    path.write_text(src.replace(old, new, 1) + extra)
+    spec = importlib.util.spec_from_file_location("matching_mut", str(path))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    names = ["iou", "iou_matrix", "assign", "track_update"]
+    saved = {n: getattr(oracle, n) for n in names}
+    try:
+        for n in names:
+            setattr(oracle, n, getattr(mod, n))
+        failed = []
+        for chk in P.MATCHING:
+            try:
+                chk()
+            except AssertionError:
+                failed.append(chk.__name__)
+    finally:
+        for n, f in saved.items():
+            setattr(oracle, n, f)
+    assert failed, f"no pin caught the planted mistake {name}"
