@@ -49,6 +49,8 @@ def parse():
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
     p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
     p.add_argument("--no-served", action="store_true", help="skip the served-vs-plain run")
+    p.add_argument("--no-match", action="store_true",
+                   help="skip the matching/update step (IoU on the GPU, assignment on the host)")
     p.add_argument("--no-mf", action="store_true",
                    help="skip the Median-Flow step (forward-backward tracking, scaled boxes)")
     p.add_argument("--served-seconds", type=float, default=3.0,
@@ -239,6 +241,8 @@ def main():
     if not a.no_mf:
         out["median_flow"] = bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid,
                                                WIN, L, ITERS, EPS, MARGIN, cs)
+    if not a.no_match:
+        out["matching"] = bench_matching(ops, wl, ob, cs)
     if not a.no_batched:
         out["batched"] = bench_batched(a)
     if not a.no_served:
@@ -323,6 +327,63 @@ def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS,
             "fb_gate_hbm_frac": gate_bytes / (gate_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "box_scaled_us": sc_ms * 1e3, "box_pairs": pairs,
             "box_pairs_per_s": pairs / (sc_ms * 1e-3)}
+
+
+def bench_matching(ops, wl, pred, cs):
+    """The matching and update phases after one step of the box scene:
+    scores of the 20 predicted boxes against synthetic detections (true
+    next boxes, 1 px jitter, 10 % missed, 2 new) on the GPU, then the
+    optimal assignment and the update on the host.  Also a 30 x 32 case
+    (the largest box count of the mixed streams)."""
+    import torch
+    from paper_1910_06017_amd import synth
+    res = {}
+    rng = np.random.default_rng(7)
+    cases = [("sd_boxes", pred, synth.detections(wl.boxes_next, rng, wl.W, wl.H))]
+    S30 = rng.uniform(0, 1800, (30, 2))
+    S30 = np.concatenate([S30, S30 + rng.uniform(40, 200, (30, 2))], axis=1).astype(np.float32)
+    cases.append(("30x32", torch.from_numpy(S30).to(pred.device),
+                  synth.detections(S30, rng, 1920, 1080, miss=0.0, extra=2)))
+    KREP = 10
+    for name, S, det in cases:
+        D = torch.from_numpy(det).to(S.device)
+        iou = torch.empty((S.shape[0], D.shape[0]), dtype=torch.float32, device=S.device)
+        with torch.cuda.stream(cs):
+            ops.iou_matrix(S, D, out=iou)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(KREP):
+                ops.iou_matrix(S, D, out=iou)
+        iou_us = _graph_ms(torch, g, cs, 50) / KREP * 1e3
+        # one full step as a caller runs it: scores, copy back, host phases
+        m, k = S.shape[0], D.shape[0]
+        Sh = S.cpu().numpy()
+        B = np.zeros((m + k, 4), np.float32)
+        I = np.zeros(m + k, np.int32)
+        L = np.zeros(m + k, np.uint8)
+        ts = []
+        for _ in range(50):
+            t0 = time.perf_counter()
+            with torch.cuda.stream(cs):
+                ops.iou_matrix(S, D, out=iou)
+                ih = iou.cpu().numpy()
+            s2d, d2s, score = ops.assign(ih, 0.3)
+            B[:m] = Sh
+            I[:m] = np.arange(m)
+            L[:m] = 0
+            mo, _ = ops.track_update(B, I, L, m, det, s2d, d2s, m)
+            ts.append(time.perf_counter() - t0)
+        t_as = []
+        for _ in range(50):
+            t0 = time.perf_counter()
+            ops.assign(ih, 0.3)
+            t_as.append(time.perf_counter() - t0)
+        res[name] = {"objects": m, "detections": k, "matched": int((s2d >= 0).sum()),
+                     "iou_kernel_us": iou_us, "assign_host_us": float(np.median(t_as)) * 1e6,
+                     "step_us_median": float(np.median(ts)) * 1e6,
+                     "step": "IoU on the GPU + copy to host + assignment + update"}
+    return res
 
 
 def bench_batched(a):

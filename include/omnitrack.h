@@ -216,6 +216,52 @@ OT_API ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t*
                             void* stream);
 
 /* ------------------------------------------------------------------------
+ * Matching and update phases (Sec. V-A): the predicted scene objects S_t
+ * are matched one-to-one against the detections D_t, globally optimally
+ * (Hungarian method, Kuhn 1955) with intersection-over-union as the score;
+ * unmatched objects are flagged lost, unmatched detections become new
+ * objects.  The score matrix is built on the GPU, the assignment and the
+ * update run on the host.
+ * ---------------------------------------------------------------------- */
+
+/* iou[i * k + j] = area(S_i & D_j) / area(S_i | D_j) (float32) for every
+ * object i < m and detection j < k; area(x0, y0, x1, y1) = max(0, x1 - x0) *
+ * max(0, y1 - y0); 0 when the union has no area, and 0 in the rows of
+ * objects with active[i] == 0 (active may be NULL: all active).
+ * S m x 4, D k x 4 float32 (x0, y0, x1, y1), 16-byte aligned; active m;
+ * iou m x k.  Device pointers; m == 0 or k == 0 is a no-op.
+ * Errors: OT_E_INVAL (negative sizes, null pointers, misalignment),
+ * OT_E_LAUNCH. */
+OT_API ot_err ot_iou_matrix(const float* S, int32_t m, const float* D, int32_t k,
+                     const uint8_t* active, float* iou, void* stream);
+
+/* (host) Optimal matching on an m x k score matrix (host, row-major): among
+ * one-to-one matchings whose pairs all have iou >= iou_min, one with the
+ * largest summed iou.  s2d[i] = matched detection of object i or -1, d2s[j]
+ * = matched object of detection j or -1; score (may be NULL) = the summed
+ * iou of the matched pairs, in double.  Where several matchings reach the
+ * same sum any one of them is returned.  0 < iou_min <= 1 (so rows of
+ * inactive objects never match).  Allocates O(m k) host memory; O(m k
+ * min(m, k)) time; m * k <= 2^26.
+ * Errors: OT_E_INVAL. */
+OT_API ot_err ot_assign(const float* iou, int32_t m, int32_t k, float iou_min, int32_t* s2d,
+                 int32_t* d2s, double* score);
+
+/* (host) Track update: for every object i < m that is not lost, a match
+ * s2d[i] = j replaces its box by det[j], no match sets lost[i] = 1; lost
+ * objects are left unchanged.  Every detection j with d2s[j] == -1 is then
+ * appended (in detection order) as a new object with id *next_id (which is
+ * incremented) and lost = 0; *m_out receives the new object count.
+ * boxes cap x 4, ids cap, lost cap (host, the first m entries valid on
+ * entry); det k x 4, s2d m, d2s k (host).  s2d and d2s must be mutually
+ * consistent (as ot_assign writes them).  Errors: OT_E_INVAL (sizes,
+ * pointers, inconsistent matching, id overflow), OT_E_WORKSPACE (more than
+ * cap objects would result; nothing is written). */
+OT_API ot_err ot_track_update(float* boxes, int32_t* ids, uint8_t* lost, int32_t m, int32_t cap,
+                       const float* det, int32_t k, const int32_t* s2d, const int32_t* d2s,
+                       int32_t* next_id, int32_t* m_out);
+
+/* ------------------------------------------------------------------------
  * Batched tick: many independent streams (frame pairs) in one launch per
  * stage.  Stage 1 builds every job's next pyramid (all jobs, one launch per
  * level), stage 2 tracks every job's points in one launch, stage 3 updates

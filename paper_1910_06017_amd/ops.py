@@ -23,6 +23,7 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 # Every symbol the header declares.
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
            "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled",
+           "ot_iou_matrix", "ot_assign", "ot_track_update",
            "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_strerror", "ot_version"]
 
 # Points per box the scaled box update takes (OT_SCALE_MAX_POINTS).
@@ -97,6 +98,12 @@ def lib():
         L.ot_fb_gate.restype = i32
         L.ot_box_update_scaled.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P]
         L.ot_box_update_scaled.restype = i32
+        L.ot_iou_matrix.argtypes = [P, i32, P, i32, P, P, P]
+        L.ot_iou_matrix.restype = i32
+        L.ot_assign.argtypes = [P, i32, i32, f32, P, P, P]
+        L.ot_assign.restype = i32
+        L.ot_track_update.argtypes = [P, P, P, i32, i32, P, i32, P, P, P, P]
+        L.ot_track_update.restype = i32
         L.ot_batch_table_bytes.argtypes = [C.POINTER(OtBatchCfg)]
         L.ot_batch_table_bytes.restype = sz
         L.ot_batch_pack.argtypes = [C.POINTER(OtJob), i32, C.POINTER(OtBatchCfg), P, sz, PP]
@@ -308,6 +315,62 @@ def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, stream=Non
                                      _ptr(status), n, _ptr(ob), _ptr(oc), _ptr(os_),
                                      _stream_handle(stream)), "ot_box_update_scaled")
     return ob, oc, os_
+
+
+def iou_matrix(S, D, active=None, out=None, stream=None):
+    """(m, k) float32 IoU of the scene boxes S (m, 4) against the
+    detections D (k, 4), on the GPU; rows of objects with active == 0 are 0."""
+    torch = _torch()
+    _need(S, torch.float32, 4, "S")
+    _need(D, torch.float32, 4, "D")
+    if active is not None:
+        _need(active, torch.uint8, None, "active")
+        if active.numel() != S.shape[0]:
+            raise ValueError("active must hold one flag per object")
+    m, k = S.shape[0], D.shape[0]
+    iou = torch.empty((m, k), dtype=torch.float32, device=S.device) if out is None else out
+    check(lib().ot_iou_matrix(_ptr(S), m, _ptr(D), k, _ptr(active), _ptr(iou),
+                              _stream_handle(stream)), "ot_iou_matrix")
+    return iou
+
+
+def _np(a, dtype, what):
+    import numpy as np
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous):
+        raise ValueError(f"{what} must be a C-contiguous numpy {np.dtype(dtype).name} array")
+    return a.ctypes.data if a.size else None
+
+
+def assign(iou, iou_min: float = 0.3):
+    """Optimal one-to-one matching on a host (m, k) float32 IoU matrix (the
+    host part of the matching phase).  Returns (s2d (m,), d2s (k,), score)."""
+    import numpy as np
+    m, k = iou.shape
+    s2d = np.empty(m, np.int32)
+    d2s = np.empty(k, np.int32)
+    score = C.c_double(0.0)
+    check(lib().ot_assign(_np(iou, np.float32, "iou"), m, k, float(iou_min),
+                          _np(s2d, np.int32, "s2d"), _np(d2s, np.int32, "d2s"),
+                          C.byref(score)), "ot_assign")
+    return s2d, d2s, score.value
+
+
+def track_update(boxes, ids, lost, m: int, det, s2d, d2s, next_id: int):
+    """Host update phase in place on capacity-sized arrays boxes (cap, 4)
+    float32, ids (cap,) int32, lost (cap,) uint8 whose first m entries are
+    the objects.  Returns (new object count, next id)."""
+    import numpy as np
+    cap = boxes.shape[0]
+    if ids.shape[0] != cap or lost.shape[0] != cap or boxes.shape[1:] != (4,):
+        raise ValueError("boxes, ids and lost must share one capacity")
+    nid = C.c_int32(next_id)
+    mo = C.c_int32(0)
+    check(lib().ot_track_update(_np(boxes, np.float32, "boxes"), _np(ids, np.int32, "ids"),
+                                _np(lost, np.uint8, "lost"), m, cap,
+                                _np(det, np.float32, "det"), det.shape[0],
+                                _np(s2d, np.int32, "s2d"), _np(d2s, np.int32, "d2s"),
+                                C.byref(nid), C.byref(mo)), "ot_track_update")
+    return mo.value, nid.value
 
 
 def strerror(code: int) -> str:

@@ -448,6 +448,23 @@ class Stream:
         return pts.astype(np.float32), np.concatenate(bid), bx.astype(np.float32)
 
 
+def detections(true_boxes, rng: np.random.Generator, W: int, H: int, jitter: float = 1.0,
+               miss: float = 0.1, extra: int = 2, side=(30.0, 120.0)) -> np.ndarray:
+    """Synthetic detector output for one frame: each true box, with
+    probability 1 - miss, plus N(0, jitter) px per coordinate; then `extra`
+    boxes of random size at random places (objects entering the scene), all
+    in random order.  (k, 4) float32 (x0, y0, x1, y1)."""
+    tb = np.asarray(true_boxes, np.float64).reshape(-1, 4)
+    keep = rng.uniform(size=len(tb)) >= miss
+    d = tb[keep] + rng.normal(0.0, jitter, (int(keep.sum()), 4))
+    d[:, 2] = np.maximum(d[:, 2], d[:, 0] + 2.0)
+    d[:, 3] = np.maximum(d[:, 3], d[:, 1] + 2.0)
+    wh = rng.uniform(side[0], side[1], (extra, 2))
+    xy = rng.uniform([0.0, 0.0], [W - side[1], H - side[1]], (extra, 2))
+    d = np.concatenate([d, np.concatenate([xy, xy + wh], axis=1)])
+    return d[rng.permutation(len(d))].astype(np.float32)
+
+
 def served_streams(seed: int = 505, nstreams: int = 64, nframes: int = 20,
                    npts_range=(500, 20000), nbox_range=(4, 30),
                    resolutions=RESOLUTIONS) -> list:

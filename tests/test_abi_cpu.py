@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 13
+    assert len(syms) == 16
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
