@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "omnitrack_oracle.c")
 
 from .matching import assign, iou, iou_matrix, track_update  # noqa: E402,F401
+from .working import lk_track_working, working_level  # noqa: E402,F401
 
 GATE_MIN_EIG = 6.5025  # lambda_min / N threshold, (gray levels per pixel)^2 (= 1e-4 on [0,1])
 

@@ -649,6 +649,44 @@ def check_match_pipeline():
     assert np.array_equal(np.sort(nb[6:, 0]), [900, 1000])
 
 
+# ------------------------------------------------------------ working level
+def check_working_level():
+    """SD stays at full resolution, 2K-wide frames drop one level, 4K two;
+    the chosen level is the first whose (ceil-halved) width fits."""
+    cases = {(720, 576): 0, (1280, 720): 0, (1281, 720): 1, (1920, 1080): 1, (2560, 1280): 1,
+             (2561, 1440): 2, (3840, 2160): 2, (4096, 2160): 2, (5121, 2880): 3, (7680, 4320): 3}
+    for (W, H), want in cases.items():
+        assert oracle.working_level(W, H) == want, (W, H)
+    assert oracle.working_level(1000, 10, max_width=250) == 2
+    assert oracle.working_level(1001, 10, max_width=250) == 3
+    assert oracle.working_level(0, 10) == -1 and oracle.working_level(10, 10, 0) == -1
+    for W in range(1, 6000, 7):
+        l = oracle.working_level(W, 1, max_width=300)
+        w = [W]
+        for _ in range(l):
+            w.append(-(-w[-1] // 2))
+        assert w[-1] <= 300 and (l == 0 or w[-2] > 300)
+
+
+def check_working_level_tracking():
+    """A known sub-pixel global shift tracked at working level 1 (the
+    half-resolution pyramid) is recovered in level-0 pixels."""
+    f0, f1, (dx, dy) = synth.shifted_pair(606, W=320, H=256, shift=(2.6, -1.7))
+    g = np.stack(np.meshgrid(np.arange(60, 261, 20), np.arange(60, 197, 20)), -1).reshape(-1, 2)
+    pts = g.astype(np.float32)
+    r = oracle.lk_track_working(f0, f1, pts, base=1, levels=2)
+    ok = r.status == 1
+    assert ok.mean() > 0.9
+    e = np.hypot(r.next_pts[ok, 0] - pts[ok, 0] - dx, r.next_pts[ok, 1] - pts[ok, 1] - dy)
+    assert np.median(e) < 0.05 and e.max() < 0.2, (np.median(e), e.max())
+    # points enter and leave in level-0 pixels: base 0 is the plain tracker
+    r0 = oracle.lk_track_working(f0, f1, pts, base=0, levels=3)
+    p0 = oracle.lk_track(f0, f1, pts, levels=3)
+    assert np.array_equal(r0.next_pts, p0.next_pts)
+
+
+WORKING = [check_working_level, check_working_level_tracking]
+
 MATCHING = [check_iou_closed_forms, check_iou_raster, check_iou_matrix_invariants,
             check_assign_bruteforce, check_assign_not_greedy_and_threshold, check_track_update,
             check_match_pipeline]
@@ -662,4 +700,4 @@ ALL = [check_level_dims, check_pyr_down_library, check_pyramid_closed_forms,
        check_lk_structure_tensor_closed_form, check_two_motions,
        check_box_translation, check_box_median_library, check_box_outliers,
        check_scaled_box_translation, check_scaled_box_similarity, check_scaled_box_bruteforce,
-       check_scaled_box_outliers, check_fb_gate, check_fb_roundtrip_shift] + MATCHING
+       check_scaled_box_outliers, check_fb_gate, check_fb_roundtrip_shift] + MATCHING + WORKING

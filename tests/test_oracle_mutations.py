@@ -111,24 +111,23 @@ MATCH_MUTATIONS = {
 }
 
 
-@pytest.mark.parametrize("name", sorted(MATCH_MUTATIONS))
-def test_planted_matching_mistake_is_caught(tmp_path, name):
+def _python_mutant_caught(tmp_path, src_path, names, old, new, extra, pins):
+    """Load a mutated copy of an oracle Python module, route the oracle's
+    functions `names` to it, and report whether any pin fails."""
     import importlib.util
-    old, new, extra = MATCH_MUTATIONS[name]
-    src = open(MATCH_SRC).read()
+    src = open(src_path).read()
     assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
-    path = tmp_path / "matching_mut.py"
+    path = tmp_path / "oracle_mut.py"
     path.write_text(src.replace(old, new, 1) + extra)
-    spec = importlib.util.spec_from_file_location("matching_mut", str(path))
+    spec = importlib.util.spec_from_file_location("oracle_mut", str(path))
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    names = ["iou", "iou_matrix", "assign", "track_update"]
     saved = {n: getattr(oracle, n) for n in names}
+    failed = []
     try:
         for n in names:
             setattr(oracle, n, getattr(mod, n))
-        failed = []
-        for chk in P.MATCHING:
+        for chk in pins:
             try:
                 chk()
             except AssertionError:
@@ -136,4 +135,31 @@ def test_planted_matching_mistake_is_caught(tmp_path, name):
     finally:
         for n, f in saved.items():
             setattr(oracle, n, f)
+    return failed
+
+
+@pytest.mark.parametrize("name", sorted(MATCH_MUTATIONS))
+def test_planted_matching_mistake_is_caught(tmp_path, name):
+    old, new, extra = MATCH_MUTATIONS[name]
+    failed = _python_mutant_caught(tmp_path, MATCH_SRC, ["iou", "iou_matrix", "assign", "track_update"],
+                                   old, new, extra, P.MATCHING)
+    assert failed, f"no pin caught the planted mistake {name}"
+
+
+WORKING_SRC = os.path.join(os.path.dirname(oracle.__file__), "working.py")
+WORKING_MUTATIONS = {
+    "halving_floors": ("w = -(-w // 2)", "w = w // 2"),
+    "first_level_over": ("while w > max_width:", "while w >= max_width:"),
+    "points_not_scaled_in": ("np.asarray(pts, np.float32) * s", "np.asarray(pts, np.float32)"),
+    "results_not_scaled_out": ("r.next_pts = r.next_pts * 2.0 ** base", "r.next_pts = r.next_pts"),
+    "wrong_level_slice": ("oracle.pyramid(frame1, base + levels)[base:]",
+                          "oracle.pyramid(frame1, base + levels + 1)[base + 1:]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WORKING_MUTATIONS))
+def test_planted_working_level_mistake_is_caught(orc, tmp_path, name):
+    old, new = WORKING_MUTATIONS[name]
+    failed = _python_mutant_caught(tmp_path, WORKING_SRC, ["working_level", "lk_track_working"],
+                                   old, new, "", P.WORKING)
     assert failed, f"no pin caught the planted mistake {name}"
