@@ -49,6 +49,8 @@ def parse():
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
     p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
     p.add_argument("--no-served", action="store_true", help="skip the served-vs-plain run")
+    p.add_argument("--no-working", action="store_true",
+                   help="skip the 1920x1080 full-resolution vs working-level comparison")
     p.add_argument("--no-match", action="store_true",
                    help="skip the matching/update step (IoU on the GPU, assignment on the host)")
     p.add_argument("--no-mf", action="store_true",
@@ -243,6 +245,8 @@ def main():
                                                WIN, L, ITERS, EPS, MARGIN, cs)
     if not a.no_match:
         out["matching"] = bench_matching(ops, wl, ob, cs)
+    if not a.no_working:
+        out["working_level"] = bench_working_level(ops, cs)
     if not a.no_batched:
         out["batched"] = bench_batched(a)
     if not a.no_served:
@@ -327,6 +331,44 @@ def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS,
             "fb_gate_hbm_frac": gate_bytes / (gate_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "box_scaled_us": sc_ms * 1e3, "box_pairs": pairs,
             "box_pairs_per_s": pairs / (sc_ms * 1e-3)}
+
+
+def bench_working_level(ops, cs):
+    """The 1920x1080 box scene (14,400 points, window 21) tracked at full
+    resolution (5 levels) and at its working level (level 1, 4 levels):
+    next-frame pyramid + tracking per graph replay."""
+    import torch
+    from paper_1910_06017_amd import synth
+    w = synth.hd_boxes_workload()
+    dev = torch.device("cuda:0")
+    f0 = torch.from_numpy(w.frame0).to(dev)
+    f1 = torch.from_numpy(w.frame1).to(dev)
+    pts = torch.from_numpy(w.pts).to(dev)
+    n = pts.shape[0]
+    base = ops.working_level(w.W, w.H)
+    res = {"workload": "1920x1080, 16 boxes, 14400 points, window 21, 30 iterations",
+           "working_level": base}
+    for name, b, L in (("full_resolution", 0, 5), ("working_level", base, 5 - base)):
+        prev = ops.pyramid_build(f0, b + L)
+        ws = ops.alloc_workspace(w.W, w.H, b + L)
+        nxt = torch.empty((n, 2), dtype=torch.float32, device=dev)
+        st = torch.empty(n, dtype=torch.uint8, device=dev)
+
+        def step():
+            Q = ops.pyramid_build(f1, b + L, ws=ws)
+            ops.lk_track(prev, Q, pts, levels=L, base_level=b, out=(nxt, st, None))
+
+        with torch.cuda.stream(cs):
+            step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            step()
+        ms = _graph_ms(torch, g, cs, 50)
+        res[name] = {"levels": L, "base_level": b, "ms_per_step": ms,
+                     "tracked_points_per_s": n / (ms * 1e-3),
+                     "ok_fraction": float(st.float().mean().item())}
+    return res
 
 
 def bench_matching(ops, wl, pred, cs):

@@ -129,7 +129,19 @@ typedef struct {
     uint8_t* iters_out; /* device n x levels, iterations run per level, or NULL */
     float* lam_out;     /* device n x levels, lambda_min/win^2 per level, or NULL */
     int32_t margin;     /* LDS search margin in pixels, 0 = default (4), max 16 */
+    int32_t base_level; /* working level (Sec. V-A preprocessing), 0 = full resolution:
+                           levels base_level .. base_level+levels-1 of both pyramids are
+                           tracked as a pyramid whose level 0 is base_level; pts and
+                           next_pts stay level-0 pixels (scaled by 2^-base_level in and
+                           2^base_level out, exactly), the in-frame test and err refer to
+                           level base_level.  See ot_working_level. */
 } ot_lk_opts;
+
+/* (host) Working-level policy for a frame of W x H pixels: the smallest
+ * level l >= 0 whose width w_l (w_0 = W, w_l = ceil(w_{l-1} / 2)) is at most
+ * max_width; 720x576 gives 0, 2560x1280 gives 1, 3840x2160 gives 2 for
+ * max_width 1280.  Returns -1 for W, H or max_width < 1. */
+OT_API int32_t ot_working_level(int32_t W, int32_t H, int32_t max_width);
 
 /* Pyramidal iterative Lucas-Kanade (Bouguet 2000) from prev_pyr to next_pyr.
  * For each point u (pts, n x 2 float32 interleaved x,y):

@@ -87,20 +87,21 @@ bool pyr_valid(const ot_pyr* p) {
     return true;
 }
 
-DevPyr to_dev(const ot_pyr& p) {
+// Device descriptor of levels base.. of p (base 0: the whole pyramid).
+DevPyr to_dev(const ot_pyr& p, int base = 0) {
     DevPyr d;
     memset(&d, 0, sizeof(d));
-    for (int l = 0; l < p.levels; ++l) {
-        d.lvl[l] = p.level[l];
-        d.w[l] = p.w[l];
-        d.h[l] = p.h[l];
-        d.pitch[l] = p.pitch[l];
+    for (int l = 0; l + base < p.levels; ++l) {
+        d.lvl[l] = p.level[l + base];
+        d.w[l] = p.w[l + base];
+        d.h[l] = p.h[l + base];
+        d.pitch[l] = p.pitch[l + base];
         if (p.flags & OT_PYR_GRADS) {
-            d.grad[l] = p.grad[l];
-            d.gpitch[l] = p.gpitch[l];
+            d.grad[l] = p.grad[l + base];
+            d.gpitch[l] = p.gpitch[l + base];
         }
     }
-    d.levels = p.levels;
+    d.levels = p.levels - base;
     d.flags = p.flags;
     return d;
 }
@@ -120,6 +121,8 @@ ot_err lk_params(int32_t win, int32_t levels, int32_t iters, float eps, float mi
     prm->eps2 = eps * eps;
     prm->min_eig = min_eig;
     prm->margin = m;
+    prm->pscale = 1.0f;
+    prm->pscale_inv = 1.0f;
     return OT_OK;
 }
 
@@ -161,15 +164,20 @@ ot_err ot_lk_track_ex(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const floa
                       void* stream) {
     if (n < 0) return OT_E_INVAL;
     if (!pyr_valid(prev_pyr) || !pyr_valid(next_pyr)) return OT_E_INVAL;
-    if (levels > prev_pyr->levels || levels > next_pyr->levels) return OT_E_INVAL;
+    const int base = opts ? opts->base_level : 0;
+    if (base < 0 || base >= OT_MAX_LEVELS || levels > OT_MAX_LEVELS ||
+        levels + base > prev_pyr->levels || levels + base > next_pyr->levels)
+        return OT_E_INVAL;
     if (prev_pyr->w[0] != next_pyr->w[0] || prev_pyr->h[0] != next_pyr->h[0]) return OT_E_SHAPE;
     LkParams prm;
     const float min_eig = opts ? opts->min_eig : OT_DEFAULT_MIN_EIG;
     const ot_err e = lk_params(win, levels, iters, eps, min_eig, opts ? opts->margin : 0, &prm);
     if (e != OT_OK) return e;
+    prm.pscale = ldexpf(1.0f, -base);
+    prm.pscale_inv = ldexpf(1.0f, base);
     if (n == 0) return OT_OK;
     if (!pts || !next_pts || !status) return OT_E_INVAL;
-    if (launch_lk(to_dev(*prev_pyr), to_dev(*next_pyr), pts, n, prm, next_pts, status, err,
+    if (launch_lk(to_dev(*prev_pyr, base), to_dev(*next_pyr, base), pts, n, prm, next_pts, status, err,
                   opts ? opts->iters_out : nullptr, opts ? opts->lam_out : nullptr,
                   static_cast<hipStream_t>(stream)) != hipSuccess)
         return OT_E_LAUNCH;
@@ -181,6 +189,16 @@ ot_err ot_lk_track(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* 
                    uint8_t* status, float* err, void* stream) {
     return ot_lk_track_ex(prev_pyr, next_pyr, pts, n, win, levels, iters, eps, next_pts, status,
                           err, nullptr, stream);
+}
+
+int32_t ot_working_level(int32_t W, int32_t H, int32_t max_width) {
+    if (W < 1 || H < 1 || max_width < 1) return -1;
+    int32_t l = 0, w = W;
+    while (w > max_width) {
+        w = (w + 1) / 2;
+        ++l;
+    }
+    return l;
 }
 
 ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id, const float* pts,

@@ -72,6 +72,8 @@ struct LkParams {
     float eps2;
     float min_eig;
     int32_t margin;
+    float pscale;      // point coordinates are multiplied by pscale on entry
+    float pscale_inv;  // and results by pscale_inv (powers of two: a working level)
 };
 
 // One stream's frame pair in the batched table.

@@ -23,7 +23,7 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 # Every symbol the header declares.
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
            "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled",
-           "ot_iou_matrix", "ot_assign", "ot_track_update",
+           "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
            "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_strerror", "ot_version"]
 
 # Points per box the scaled box update takes (OT_SCALE_MAX_POINTS).
@@ -48,7 +48,7 @@ class OtPyr(C.Structure):
 
 class OtLkOpts(C.Structure):
     _fields_ = [("min_eig", C.c_float), ("iters_out", C.c_void_p), ("lam_out", C.c_void_p),
-                ("margin", C.c_int32)]
+                ("margin", C.c_int32), ("base_level", C.c_int32)]
 
 
 class OtJob(C.Structure):
@@ -98,6 +98,8 @@ def lib():
         L.ot_fb_gate.restype = i32
         L.ot_box_update_scaled.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P]
         L.ot_box_update_scaled.restype = i32
+        L.ot_working_level.argtypes = [i32, i32, i32]
+        L.ot_working_level.restype = i32
         L.ot_iou_matrix.argtypes = [P, i32, P, i32, P, P, P]
         L.ot_iou_matrix.restype = i32
         L.ot_assign.argtypes = [P, i32, i32, f32, P, P, P]
@@ -223,12 +225,14 @@ def pyramid_layout(frame, levels: int, ws, grads: bool = False) -> Pyramid:
 def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None = None,
              iters: int = 30, eps: float = 0.01, min_eig: float = OT_DEFAULT_MIN_EIG,
              margin: int = 0, want_err: bool = True, want_diag: bool = False, out=None,
-             stream=None):
-    """Track (n, 2) float32 points.  Returns (next_pts, status, err[, iters, lam])."""
+             stream=None, base_level: int = 0):
+    """Track (n, 2) float32 points.  Returns (next_pts, status, err[, iters, lam]).
+    base_level > 0 tracks at that working level (levels base_level.. of both
+    pyramids); points stay in level-0 pixels."""
     torch = _torch()
     _need(pts, torch.float32, 2, "pts")
     n = pts.shape[0]
-    L = prev.levels if levels is None else levels
+    L = prev.levels - base_level if levels is None else levels
     dev = pts.device
     if out is None:
         next_pts = torch.empty((n, 2), dtype=torch.float32, device=dev)
@@ -236,7 +240,7 @@ def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None
         err = torch.empty(n, dtype=torch.float32, device=dev) if want_err else None
     else:
         next_pts, status, err = out
-    opts = OtLkOpts(min_eig, None, None, margin)
+    opts = OtLkOpts(min_eig, None, None, margin, base_level)
     it = lam = None
     if want_diag:
         it = torch.zeros((n, L), dtype=torch.uint8, device=dev)
@@ -315,6 +319,11 @@ def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, stream=Non
                                      _ptr(status), n, _ptr(ob), _ptr(oc), _ptr(os_),
                                      _stream_handle(stream)), "ot_box_update_scaled")
     return ob, oc, os_
+
+
+def working_level(W: int, H: int, max_width: int = 1280) -> int:
+    """The working level for a W x H frame (smallest level at most max_width wide)."""
+    return int(lib().ot_working_level(W, H, max_width))
 
 
 def iou_matrix(S, D, active=None, out=None, stream=None):

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 16
+    assert len(syms) == 17
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -136,6 +136,10 @@ def test_lk_validation(L):
     C.memmove(C.byref(bad), C.byref(P), C.sizeof(P))
     bad.w[1] = 361                                # inconsistent descriptor
     assert lk_call(L, bad, Q) == E
+    for base, lv in ((1, 4), (-1, 2), (4, 1), (8, 1)):   # base + levels beyond the pyramids
+        opts = ops.OtLkOpts(6.5, None, None, 0, base)
+        assert L.ot_lk_track_ex(C.byref(P), C.byref(Q), FAKE, 10, 21, lv, 30, 0.01, FAKE, FAKE,
+                                None, C.byref(opts), None) == E
     opts = ops.OtLkOpts(6.5, None, None, 17)      # margin above the maximum
     assert L.ot_lk_track_ex(C.byref(P), C.byref(Q), FAKE, 10, 21, 4, 30, 0.01, FAKE, FAKE,
                             None, C.byref(opts), None) == E
@@ -255,3 +259,10 @@ def test_strerror(L):
     for code in ops.ERRORS:
         assert ops.strerror(code)
     assert ops.version() >= 100
+
+
+def test_working_level_policy(L):
+    import oracle
+    for W in list(range(1, 5000, 13)) + [720, 1280, 1281, 2560, 2561, 3840]:
+        assert L.ot_working_level(W, 10, 1280) == oracle.working_level(W, 10, 1280)
+    assert L.ot_working_level(0, 10, 1280) == -1 and L.ot_working_level(10, 10, 0) == -1
