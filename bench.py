@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--profile-only", action="store_true",
                    help="run only the timed GPU region (for rocprofv3)")
+    p.add_argument("--profile-extra", action="store_true",
+                   help="run only the Median-Flow step and the matching step (for rocprofv3)")
     p.add_argument("--copy-calib", action="store_true",
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
     p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
@@ -179,6 +181,11 @@ def main():
     ms_step = t0.elapsed_time(t1) / a.steps
     if a.profile_only:
         print(json.dumps({"ms_per_step": ms_step}))
+        return
+    if a.profile_extra:
+        print(json.dumps({"median_flow": bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid,
+                                                           WIN, L, ITERS, EPS, MARGIN, cs),
+                          "matching": bench_matching(ops, wl, ob, cs)}))
         return
 
     # ---- per-step latency distribution (events around each replay)
@@ -347,7 +354,7 @@ def bench_working_level(ops, cs):
     n = pts.shape[0]
     base = ops.working_level(w.W, w.H)
     res = {"workload": "1920x1080, 16 boxes, 14400 points, window 21, 30 iterations",
-           "working_level": base}
+           "level": base}
     for name, b, L in (("full_resolution", 0, 5), ("working_level", base, 5 - base)):
         prev = ops.pyramid_build(f0, b + L)
         ws = ops.alloc_workspace(w.W, w.H, b + L)
