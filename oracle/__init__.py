@@ -18,6 +18,7 @@ _SRC = os.path.join(_HERE, "omnitrack_oracle.c")
 
 from .matching import assign, iou, iou_matrix, track_update  # noqa: E402,F401
 from .working import lk_track_working, working_level  # noqa: E402,F401
+from . import tvl1  # noqa: E402,F401
 
 GATE_MIN_EIG = 6.5025  # lambda_min / N threshold, (gray levels per pixel)^2 (= 1e-4 on [0,1])
 

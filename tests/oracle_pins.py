@@ -687,6 +687,125 @@ def check_working_level_tracking():
 
 WORKING = [check_working_level, check_working_level_tracking]
 
+
+# ------------------------------------------------------------------ TV-L1
+def check_tv_div_adjoint():
+    """div is the negative adjoint of grad: <grad u, p> = -<u, div p>."""
+    T = oracle.tvl1
+    rng = np.random.default_rng(51)
+    for shape in ((1, 1), (1, 7), (6, 1), (2, 2), (9, 13)):
+        u = rng.normal(size=shape)
+        px, py = rng.normal(size=shape), rng.normal(size=shape)
+        gx, gy = T.grad(u)
+        assert abs((gx * px + gy * py).sum() + (u * T.div(px, py)).sum()) < 1e-12, shape
+    u = np.arange(12.0).reshape(3, 4) ** 2
+    gx, gy = T.grad(u)
+    assert np.array_equal(gx[:, -1], np.zeros(3)) and np.array_equal(gy[-1], np.zeros(4))
+    assert np.array_equal(gx[:, :-1], u[:, 1:] - u[:, :-1])
+
+
+def check_rof_closed_forms():
+    """A constant image is its own structure; a vertical step a|b with n1
+    and n2 columns converges to a + theta/n1 | b - theta/n2 (the 1-D ROF
+    minimiser: each side moves until theta times the slope of the TV term
+    balances the fidelity term)."""
+    T = oracle.tvl1
+    f = np.full((5, 9), 0.37)
+    assert np.array_equal(T.rof(f, 0.1, 0.125, 30), f)
+    prm = T.TvL1Params()
+    assert np.allclose(T.texture(np.full((4, 6), 200, np.uint8), prm), (1 - prm.alpha) * 200 / 255,
+                       atol=1e-15)
+    f = np.zeros((4, 20))
+    f[:, :8] = 0.2
+    f[:, 8:] = 0.8
+    s = T.rof(f, 0.1, 0.125, 3000)
+    assert np.allclose(s[:, :8], 0.2 + 0.1 / 8, atol=2e-3), s[0]
+    assert np.allclose(s[:, 8:], 0.8 - 0.1 / 12, atol=2e-3), s[0]
+
+
+def check_tv_data_step_bruteforce():
+    """The data step's v minimises |v - u|^2/(2 theta) + lam |rho0 + g.v|;
+    the minimiser lies on u + s g, found here by a dense search over s."""
+    T = oracle.tvl1
+    rng = np.random.default_rng(52)
+    lam, theta = 0.15, 0.3
+    for _ in range(200):
+        u = rng.normal(size=2)
+        g = rng.normal(size=2) * rng.choice([0.01, 0.3, 2.0])
+        rho0 = rng.normal() * 0.2
+        v1, v2 = T.data_step(np.array([u[0]]), np.array([u[1]]), np.array([g[0]]),
+                             np.array([g[1]]), np.array([rho0]), lam * theta)
+        sgrid = np.linspace(-3 * lam * theta, 3 * lam * theta, 120001)
+        vv = u[None, :] + sgrid[:, None] * g[None, :]
+        E = ((vv - u) ** 2).sum(1) / (2 * theta) + lam * np.abs(rho0 + vv @ g)
+        vb = vv[E.argmin()]
+        assert np.hypot(v1[0] - vb[0], v2[0] - vb[1]) < 1e-4 * max(1.0, np.linalg.norm(g)), (u, g, rho0)
+    v1, v2 = T.data_step(np.array([0.5]), np.array([-0.25]), np.zeros(1), np.zeros(1),
+                         np.array([0.3]), 0.045)
+    assert v1[0] == 0.5 and v2[0] == -0.25          # no gradient: u unchanged
+
+
+def check_tvl1_zero_motion_and_dual():
+    """Identical frames give exactly zero flow; the dual stays in the unit
+    ball on real motion."""
+    T = oracle.tvl1
+    f0, f1, _ = synth.shifted_pair(611, W=96, H=80, shift=(1.25, -0.5))
+    prm = T.TvL1Params(levels=2, warps=2, iters=10)
+    P0 = oracle.pyramid(f0, 2)
+    u1, u2 = T.tvl1_flow(P0, P0, prm)
+    assert np.all(u1 == 0) and np.all(u2 == 0)
+    # a flow step of 3 px on flat images: the dual saturates at the step
+    # (the unprojected update would reach (tau/theta) * 3 / (1 + tau eps/theta))
+    I = np.full((12, 16), 0.5)
+    u1 = np.zeros((12, 16))
+    u1[:, 8:] = 3.0
+    _, _, p = T.tvl1_level(I, I, u1, np.zeros_like(u1), prm, return_dual=True)
+    n1 = np.hypot(p[0], p[1])
+    assert n1.max() <= 1 + 1e-12 and abs(n1[:, 7].min() - 1.0) < 1e-12
+    assert np.all(p[2] == 0) and np.all(p[3] == 0)
+
+
+def check_tvl1_global_shift():
+    """A sub-pixel global shift of a textured image is recovered."""
+    T = oracle.tvl1
+    f0, f1, (dx, dy) = synth.shifted_pair(612, W=160, H=128, shift=(1.3, -0.7))
+    prm = T.TvL1Params(levels=3, warps=5, iters=30)
+    u1, u2 = T.tvl1_flow(oracle.pyramid(f0, 3), oracle.pyramid(f1, 3), prm)
+    e = np.hypot(u1 - dx, u2 - dy)[16:-16, 16:-16]
+    assert np.median(e) < 0.02 and np.percentile(e, 90) < 0.05, (np.median(e), np.percentile(e, 90))
+
+
+def check_tv_upsample():
+    """A constant coarse flow doubles; a linear one keeps its slope in fine
+    pixels (away from the clamped last column)."""
+    T = oracle.tvl1
+    c = np.full((5, 6), 0.75)
+    assert np.array_equal(T.upsample_flow(c, 12, 10), np.full((10, 12), 1.5))
+    lin = np.tile(np.arange(6.0) * 0.5, (5, 1))
+    up = T.upsample_flow(lin, 11, 9)
+    assert np.allclose(up[:, :11], np.tile(np.arange(11.0) * 0.5, (9, 1)), atol=1e-12)
+
+
+def check_box_mean_flow():
+    """The mean over the box's pixel centres (edges included), empty boxes
+    unchanged."""
+    T = oracle.tvl1
+    rng = np.random.default_rng(53)
+    u1, u2 = rng.normal(size=(30, 40)), rng.normal(size=(30, 40))
+    boxes = np.array([[2, 3, 10, 7], [2.5, 3.5, 9.5, 7.5], [-5, -5, 3, 2], [20, 20, 20, 20],
+                      [50, 0, 60, 10], [3.2, 3.2, 3.8, 3.8]])
+    out, cnt, mean = T.box_mean_flow(u1, u2, boxes)
+    assert cnt.tolist() == [9 * 5, 7 * 4, 4 * 3, 1, 0, 0]
+    assert np.isclose(mean[0, 0], u1[3:8, 2:11].mean()) and np.isclose(mean[1, 1], u2[4:8, 3:10].mean())
+    assert np.isclose(mean[2, 0], u1[0:3, 0:4].mean()) and mean[3, 1] == u2[20, 20]
+    assert np.array_equal(out[4], boxes[4]) and np.array_equal(out[5], boxes[5])
+    assert np.allclose(out[0], boxes[0] + [mean[0, 0], mean[0, 1]] * 2)
+
+
+TVL1 = [check_tv_div_adjoint, check_rof_closed_forms, check_tv_data_step_bruteforce,
+        check_tvl1_zero_motion_and_dual, check_tvl1_global_shift, check_tv_upsample,
+        check_box_mean_flow]
+
 MATCHING = [check_iou_closed_forms, check_iou_raster, check_iou_matrix_invariants,
             check_assign_bruteforce, check_assign_not_greedy_and_threshold, check_track_update,
             check_match_pipeline]
@@ -700,4 +819,4 @@ ALL = [check_level_dims, check_pyr_down_library, check_pyramid_closed_forms,
        check_lk_structure_tensor_closed_form, check_two_motions,
        check_box_translation, check_box_median_library, check_box_outliers,
        check_scaled_box_translation, check_scaled_box_similarity, check_scaled_box_bruteforce,
-       check_scaled_box_outliers, check_fb_gate, check_fb_roundtrip_shift] + MATCHING + WORKING
+       check_scaled_box_outliers, check_fb_gate, check_fb_roundtrip_shift] + MATCHING + WORKING + TVL1

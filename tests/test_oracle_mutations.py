@@ -163,3 +163,50 @@ def test_planted_working_level_mistake_is_caught(orc, tmp_path, name):
     failed = _python_mutant_caught(tmp_path, WORKING_SRC, ["working_level", "lk_track_working"],
                                    old, new, "", P.WORKING)
     assert failed, f"no pin caught the planted mistake {name}"
+
+
+TVL1_SRC = os.path.join(os.path.dirname(oracle.__file__), "tvl1.py")
+TVL1_MUTATIONS = {
+    "grad_backward": ("gx[:, :-1] = u[:, 1:] - u[:, :-1]", "gx[:, 1:] = u[:, 1:] - u[:, :-1]"),
+    "div_keeps_last_column": ("qx[:, -1] = 0.0", "pass"),
+    "rof_sign": ("return f - theta * div(px, py)", "return f + theta * div(px, py)"),
+    "texture_ignores_alpha": ("f - prm.alpha * rof(", "f - rof("),
+    "threshold_sign": ("s[lo] = lam_theta", "s[lo] = -lam_theta"),
+    "projection_sign": ("s[mid] = -rho[mid] / g2[mid]", "s[mid] = rho[mid] / g2[mid]"),
+    "no_dual_projection": ("n = np.maximum(1.0, np.sqrt(qx * qx + qy * qy))", "n = 1.0"),
+    "warp_sign": ("wx = xs + u1", "wx = xs - u1"),
+    "upsample_no_doubling": ("return 2.0 * bilinear_clamped", "return bilinear_clamped"),
+    "primal_sign": ("u1 = v1 + prm.theta * div(p[0], p[1])", "u1 = v1 - prm.theta * div(p[0], p[1])"),
+    "linearisation_sign": ("rho0 = I1w - gx * u1 - gy * u2 - I0", "rho0 = I1w + gx * u1 + gy * u2 - I0"),
+    "box_excludes_right_edge": ("min(W - 1, int(np.floor(x1)))", "min(W - 1, int(np.floor(x1)) - 1)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TVL1_MUTATIONS))
+def test_planted_tvl1_mistake_is_caught(orc, tmp_path, name):
+    import importlib.util
+    old, new = TVL1_MUTATIONS[name]
+    src = open(TVL1_SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    path = tmp_path / "tvl1_mut.py"
+    path.write_text(src.replace(old, new, 1))
+    import sys
+    spec = importlib.util.spec_from_file_location("tvl1_mut", str(path))
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules["tvl1_mut"] = mod          # dataclasses look their module up
+    try:
+        spec.loader.exec_module(mod)
+    finally:
+        sys.modules.pop("tvl1_mut", None)
+    saved = oracle.tvl1
+    failed = []
+    try:
+        oracle.tvl1 = mod
+        for chk in P.TVL1:
+            try:
+                chk()
+            except AssertionError:
+                failed.append(chk.__name__)
+    finally:
+        oracle.tvl1 = saved
+    assert failed, f"no pin caught the planted mistake {name}"
