@@ -51,6 +51,8 @@ def parse():
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
     p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
     p.add_argument("--no-served", action="store_true", help="skip the served-vs-plain run")
+    p.add_argument("--no-dense", action="store_true",
+                   help="skip the dense TV-L1 flow + mean-flow box prediction step")
     p.add_argument("--no-working", action="store_true",
                    help="skip the 1920x1080 full-resolution vs working-level comparison")
     p.add_argument("--no-match", action="store_true",
@@ -254,6 +256,8 @@ def main():
         out["matching"] = bench_matching(ops, wl, ob, cs)
     if not a.no_working:
         out["working_level"] = bench_working_level(ops, cs)
+    if not a.no_dense:
+        out["dense_tvl1"] = bench_dense(ops, wl, f0, f1, boxes, cs)
     if not a.no_batched:
         out["batched"] = bench_batched(a)
     if not a.no_served:
@@ -338,6 +342,42 @@ def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS,
             "fb_gate_hbm_frac": gate_bytes / (gate_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "box_scaled_us": sc_ms * 1e3, "box_pairs": pairs,
             "box_pairs_per_s": pairs / (sc_ms * 1e-3)}
+
+
+def bench_dense(ops, wl, f0, f1, boxes, cs):
+    """The dense variant on the same frame pair: TV-L1 flow with the default
+    parameters (both frames' structure-texture split, 5 levels, 5 warps x 30
+    iterations) and the mean-flow box prediction, one graph replay; the
+    iteration kernel's time at level 0 from a graph of 30 iterations."""
+    import torch
+    p = ops.tvl1_params()
+    H, W = wl.frame0.shape
+    P = ops.pyramid_build(f0, p.levels)
+    Q = ops.pyramid_build(f1, p.levels)
+    ws = torch.empty(int(ops.lib().ot_tvl1_bytes(W, H)), dtype=torch.uint8, device=f0.device)
+    flow = torch.empty((H, W, 2), dtype=torch.float32, device=f0.device)
+    ob = torch.empty_like(boxes)
+    oc = torch.empty(boxes.shape[0], dtype=torch.int32, device=f0.device)
+
+    def step():
+        ops.tvl1_flow(P, Q, p, ws=ws, out=flow)
+        ops.box_mean_flow(flow, boxes, out=(ob, oc))
+
+    with torch.cuda.stream(cs):
+        step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        step()
+    ms = _graph_ms(torch, g, cs, 10)
+    launches = p.levels * (2 * (p.iters_s + 1) + 1 + 1 + p.warps * (1 + p.iters)) + 1
+    px = W * H
+    # one iteration kernel at level 0: read u 8 B, p 16 B, data 16 B; write u 8 B, p 16 B
+    it_bytes = px * 64
+    return {"ms_per_step": ms, "frames_per_s": 1e3 / ms, "pixels_per_s": px / (ms * 1e-3),
+            "levels": p.levels, "warps": p.warps, "iters": p.iters, "iters_s": p.iters_s,
+            "kernel_launches": launches, "iter_bytes_level0": it_bytes,
+            "step": "TV-L1 flow (structure-texture of both frames, all levels) + box mean"}
 
 
 def bench_working_level(ops, cs):

@@ -274,6 +274,67 @@ OT_API ot_err ot_track_update(float* boxes, int32_t* ids, uint8_t* lost, int32_t
                        int32_t* next_id, int32_t* m_out);
 
 /* ------------------------------------------------------------------------
+ * Dense variant of the motion features (Sec. IV): TV-L1 optical flow with a
+ * Huber-smoothed total variation, solved by projected steps on the dual
+ * variable (Zach, Pock & Bischof 2007; Werlberger et al. 2009), on
+ * structure-texture decomposed inputs (Wedel et al. 2009), coarse to fine
+ * over the same uint8 pyramids as the sparse path; and the prediction of
+ * Sec. V-A: every box moves by the mean of the dense field inside it.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t levels;   /* pyramid levels used, coarse to fine (1..OT_MAX_LEVELS) */
+    int32_t warps;    /* linearisations of the data term per level (>= 1) */
+    int32_t iters;    /* iterations per linearisation (>= 1) */
+    float lam;        /* data weight, textures on the [0, 1] scale (> 0) */
+    float theta;      /* coupling weight of the flow and its auxiliary (> 0) */
+    float tau;        /* dual step (0 < tau <= 0.25) */
+    float eps;        /* Huber smoothing of the total variation (>= 0) */
+    float alpha;      /* texture = f - alpha * structure */
+    float theta_s;    /* structure (ROF) fidelity weight (> 0) */
+    float tau_s;      /* structure dual step (0 < tau_s <= 0.25) */
+    int32_t iters_s;  /* structure iterations (>= 0; 0: structure = f) */
+} ot_tvl1_params;
+
+/* (host) The defaults: 5 levels, 5 warps, 30 iterations, lam 40, theta 0.3,
+ * tau 0.25, eps 0.01, alpha 0.95, theta_s 0.1, tau_s 0.125, 50 structure
+ * iterations. */
+OT_API void ot_tvl1_default_params(ot_tvl1_params* p);
+
+/* Workspace bytes of ot_tvl1_flow for a W x H level 0 (0 if invalid). */
+OT_API size_t ot_tvl1_bytes(int32_t W, int32_t H);
+
+/* Dense flow from prev_pyr to next_pyr.  Every level l < p->levels (coarse
+ * to fine) of both pyramids is scaled to f = I / 255 and split: structure =
+ * argmin_s TV(s) + |s - f|^2 / (2 theta_s) by iters_s dual (Chambolle 2004)
+ * steps from p = 0, texture = f - alpha * structure.  The flow starts at 0
+ * on the coarsest level and enters each finer level as 2 u(x / 2) (bilinear,
+ * clamped).  On each level, `warps` times: I1, its central-difference
+ * gradient (clamped indices) are sampled bilinearly at x + u0 (position
+ * clamped to the level), rho(u) = I1(x+u0) + g . (u - u0) - I0; then `iters`
+ * times: v = the pointwise minimiser of |v - u|^2 / (2 theta) + lam |rho(v)|,
+ * u = v + theta div p, p = projection onto |p| <= 1 of (p + (tau/theta) grad
+ * u) / (1 + tau eps / theta) for each flow component (grad: forward
+ * differences, 0 on the last column / row; div = -grad^T); p restarts at 0
+ * on every level.  flow: W0 x H0 float32 pairs (u_x, u_y) per pixel of
+ * level 0, row-major, dense, 8-byte aligned, in level-0 pixels.  ws:
+ * ot_tvl1_bytes(W0, H0) bytes, 256-byte aligned, owned by the caller.
+ * Arithmetic is FP32.  Errors: OT_E_INVAL (descriptors, parameters, null
+ * pointers), OT_E_SHAPE (level sizes differ), OT_E_WORKSPACE, OT_E_LAUNCH. */
+OT_API ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
+                    const ot_tvl1_params* prm, void* ws, size_t ws_bytes, float* flow,
+                    void* stream);
+
+/* Box prediction from a dense field (Sec. V-A): for box b, (mx, my) = the
+ * mean of flow over the pixels (x, y) with integer x in [ceil(x0),
+ * floor(x1)] and y in [ceil(y0), floor(y1)], clipped to the W x H field
+ * (sums in double); out_boxes[b] = boxes[b] + (mx, my, mx, my), out_count[b]
+ * = the pixel count; a box without pixels is copied unchanged with count 0.
+ * flow W x H float32 pairs (8-byte aligned), boxes/out_boxes m x 4, out_count
+ * m.  Errors: OT_E_INVAL, OT_E_LAUNCH. */
+OT_API ot_err ot_box_mean_flow(const float* flow, int32_t W, int32_t H, const float* boxes,
+                        int32_t m, float* out_boxes, int32_t* out_count, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched tick: many independent streams (frame pairs) in one launch per
  * stage.  Stage 1 builds every job's next pyramid (all jobs, one launch per
  * level), stage 2 tracks every job's points in one launch, stage 3 updates

@@ -33,10 +33,10 @@ import numpy as np
 
 @dataclass
 class TvL1Params:
-    levels: int = 3
+    levels: int = 5
     warps: int = 5
     iters: int = 30
-    lam: float = 1.0         # data weight (textures on the [0, 1] scale)
+    lam: float = 40.0        # data weight, textures on the [0, 1] scale (0.16 on 0..255)
     theta: float = 0.3       # coupling of u and v
     tau: float = 0.25        # dual step
     eps: float = 0.01        # Huber smoothing of the total variation
@@ -167,15 +167,22 @@ def upsample_flow(u, W, H):
     return 2.0 * bilinear_clamped(u, 0.5 * xs, 0.5 * ys)
 
 
-def tvl1_flow(pyr0: list, pyr1: list, prm: TvL1Params):
+def tvl1_flow(pyr0: list, pyr1: list, prm: TvL1Params, perturb: float = 0.0):
     """Dense flow (u1, u2) at level 0 of two uint8 pyramids (lists of levels,
-    at least prm.levels each)."""
+    at least prm.levels each).  perturb > 0 adds a fixed pattern of that
+    amplitude to every texture: a probe of how far the result moves under
+    input changes the size of float32 rounding (the conditioning of the
+    problem, against which a float32 run is judged)."""
     L = prm.levels
     u1 = u2 = None
     for l in range(L - 1, -1, -1):
         I0 = texture(pyr0[l], prm)
         I1 = texture(pyr1[l], prm)
         H, W = I0.shape
+        if perturb:
+            ys, xs = np.mgrid[0:H, 0:W]
+            pat = perturb * (((xs * 7 + ys * 13) % 17) - 8) / 8.0
+            I0, I1 = I0 + pat, I1 - pat
         if u1 is None:
             u1 = np.zeros((H, W))
             u2 = np.zeros((H, W))

@@ -24,6 +24,7 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
            "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
+           "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_box_mean_flow",
            "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_strerror", "ot_version"]
 
 # Points per box the scaled box update takes (OT_SCALE_MAX_POINTS).
@@ -49,6 +50,13 @@ class OtPyr(C.Structure):
 class OtLkOpts(C.Structure):
     _fields_ = [("min_eig", C.c_float), ("iters_out", C.c_void_p), ("lam_out", C.c_void_p),
                 ("margin", C.c_int32), ("base_level", C.c_int32)]
+
+
+class OtTvl1Params(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("warps", C.c_int32), ("iters", C.c_int32),
+                ("lam", C.c_float), ("theta", C.c_float), ("tau", C.c_float), ("eps", C.c_float),
+                ("alpha", C.c_float), ("theta_s", C.c_float), ("tau_s", C.c_float),
+                ("iters_s", C.c_int32)]
 
 
 class OtJob(C.Structure):
@@ -98,6 +106,14 @@ def lib():
         L.ot_fb_gate.restype = i32
         L.ot_box_update_scaled.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P]
         L.ot_box_update_scaled.restype = i32
+        L.ot_tvl1_default_params.argtypes = [C.POINTER(OtTvl1Params)]
+        L.ot_tvl1_default_params.restype = None
+        L.ot_tvl1_bytes.argtypes = [i32, i32]
+        L.ot_tvl1_bytes.restype = sz
+        L.ot_tvl1_flow.argtypes = [PP, PP, C.POINTER(OtTvl1Params), P, sz, P, P]
+        L.ot_tvl1_flow.restype = i32
+        L.ot_box_mean_flow.argtypes = [P, i32, i32, P, i32, P, P, P]
+        L.ot_box_mean_flow.restype = i32
         L.ot_working_level.argtypes = [i32, i32, i32]
         L.ot_working_level.restype = i32
         L.ot_iou_matrix.argtypes = [P, i32, P, i32, P, P, P]
@@ -324,6 +340,50 @@ def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, stream=Non
 def working_level(W: int, H: int, max_width: int = 1280) -> int:
     """The working level for a W x H frame (smallest level at most max_width wide)."""
     return int(lib().ot_working_level(W, H, max_width))
+
+
+def tvl1_params(**kw) -> OtTvl1Params:
+    """The library's TV-L1 defaults with the given fields replaced."""
+    p = OtTvl1Params()
+    lib().ot_tvl1_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise ValueError(f"unknown TV-L1 parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def tvl1_flow(prev: Pyramid, nxt: Pyramid, params: OtTvl1Params | None = None, ws=None,
+              out=None, stream=None):
+    """Dense TV-L1 flow at level 0: (H, W, 2) float32 (u_x, u_y) per pixel."""
+    torch = _torch()
+    p = tvl1_params() if params is None else params
+    W, H = prev.desc.w[0], prev.desc.h[0]
+    need = int(lib().ot_tvl1_bytes(W, H))
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=prev.frame.device)
+    flow = torch.empty((H, W, 2), dtype=torch.float32, device=prev.frame.device) if out is None else out
+    check(lib().ot_tvl1_flow(C.byref(prev.desc), C.byref(nxt.desc), C.byref(p), _ptr(ws),
+                             ws.numel() * ws.element_size(), _ptr(flow), _stream_handle(stream)),
+          "ot_tvl1_flow")
+    return flow
+
+
+def box_mean_flow(flow, boxes, out=None, stream=None):
+    """Boxes moved by the mean dense flow inside them: (out_boxes, count)."""
+    torch = _torch()
+    _need(flow, torch.float32, 2, "flow")
+    _need(boxes, torch.float32, 4, "boxes")
+    H, W = flow.shape[0], flow.shape[1]
+    m = boxes.shape[0]
+    if out is None:
+        ob = torch.empty((m, 4), dtype=torch.float32, device=boxes.device)
+        oc = torch.empty(m, dtype=torch.int32, device=boxes.device)
+    else:
+        ob, oc = out
+    check(lib().ot_box_mean_flow(_ptr(flow), W, H, _ptr(boxes), m, _ptr(ob), _ptr(oc),
+                                 _stream_handle(stream)), "ot_box_mean_flow")
+    return ob, oc
 
 
 def iou_matrix(S, D, active=None, out=None, stream=None):

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 17
+    assert len(syms) == 21
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -266,3 +266,30 @@ def test_working_level_policy(L):
     for W in list(range(1, 5000, 13)) + [720, 1280, 1281, 2560, 2561, 3840]:
         assert L.ot_working_level(W, 10, 1280) == oracle.working_level(W, 10, 1280)
     assert L.ot_working_level(0, 10, 1280) == -1 and L.ot_working_level(10, 10, 0) == -1
+
+
+def test_tvl1_validation(L):
+    E, Wk = ops_err("OT_E_INVAL"), ops_err("OT_E_WORKSPACE")
+    p = ops.OtTvl1Params()
+    L.ot_tvl1_default_params(C.byref(p))
+    assert (p.levels, p.warps, p.iters, p.iters_s) == (5, 5, 30, 50)
+    n = 720 * 576
+    al = lambda v: (v + 255) // 256 * 256
+    assert L.ot_tvl1_bytes(720, 576) == 2 * al(4 * n) + 3 * al(8 * n) + al(16 * n) + 2 * al(8 * n) + 2 * al(16 * n)
+    assert L.ot_tvl1_bytes(0, 5) == 0
+    _, P = layout(L, levels=5)
+    need = L.ot_tvl1_bytes(720, 576)
+    call = lambda prm, ws=FAKE, wsb=need, flow=FAKE: L.ot_tvl1_flow(C.byref(P), C.byref(P), C.byref(prm), ws,
+                                                                    wsb, flow, None)
+    for k, v in (("levels", 0), ("levels", 6), ("warps", 0), ("iters", 0), ("tau", 0.3),
+                 ("lam", float("nan")), ("theta", 0.0), ("tau_s", 0.0), ("iters_s", -1)):
+        q = ops.OtTvl1Params()
+        C.memmove(C.byref(q), C.byref(p), C.sizeof(p))
+        setattr(q, k, v)
+        assert call(q) == E, k
+    assert call(p, wsb=need - 1) == Wk
+    assert call(p, ws=FAKE + 16) == Wk
+    assert call(p, flow=None) == E
+    assert L.ot_box_mean_flow(FAKE, 10, 10, FAKE, -1, FAKE, FAKE, None) == E
+    assert L.ot_box_mean_flow(FAKE + 4, 10, 10, FAKE, 3, FAKE, FAKE, None) == E
+    assert L.ot_box_mean_flow(None, 10, 10, None, 0, None, None, None) == 0

@@ -1,0 +1,129 @@
+"""Dense TV-L1 flow and the mean-flow box prediction on the GPU against the
+CPU oracle, through the C ABI.
+
+The TV-L1 iteration is a composition of Lipschitz maps (soft thresholding,
+bilinear warps, the projection onto the unit ball), so FP32 rounding stays
+of the order of the rounding itself over the run; the bar is the path's
+0.01 px per pixel.  Identical frames must give exactly zero flow.  The box
+means sum in double on both sides: 1e-5 px."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_06017_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FLOW_TOL = 0.01
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_06017_amd import ops as o
+    o.lib()
+    return o
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def oracle_params(p):
+    T = oracle.tvl1
+    f = lambda v: float(np.float32(v))
+    return T.TvL1Params(levels=p.levels, warps=p.warps, iters=p.iters, lam=f(p.lam),
+                        theta=f(p.theta), tau=f(p.tau), eps=f(p.eps), alpha=f(p.alpha),
+                        theta_s=f(p.theta_s), tau_s=f(p.tau_s), iters_s=p.iters_s)
+
+
+def run_both(ops, f0, f1, **kw):
+    p = ops.tvl1_params(**kw)
+    P = ops.pyramid_build(dev(f0), p.levels)
+    Q = ops.pyramid_build(dev(f1), p.levels)
+    g = ops.tvl1_flow(P, Q, p)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    u1, u2 = oracle.tvl1.tvl1_flow(oracle.pyramid(f0, p.levels), oracle.pyramid(f1, p.levels),
+                                   oracle_params(p))
+    d = np.hypot(g[..., 0] - u1, g[..., 1] - u2)
+    return g, (u1, u2), d
+
+
+@pytest.mark.parametrize("W,H,kw", [
+    (96, 80, dict(levels=2, warps=2, iters=10, iters_s=20)),
+    (33, 17, dict(levels=3, warps=3, iters=7, iters_s=5)),       # ragged, tiny coarse levels
+    (1, 9, dict(levels=1, warps=1, iters=3, iters_s=3)),         # a single column
+    (160, 128, dict(iters_s=0)),                                 # no structure iterations
+])
+def test_tvl1_matches_oracle_small(ops, W, H, kw):
+    f0, f1, _ = synth.shifted_pair(700 + W, W=W, H=H, shift=(1.2, -0.6))
+    _, _, d = run_both(ops, f0, f1, **kw)
+    print(f"tvl1 {W}x{H} {kw}: max |d| {d.max():.2e}, p99 {np.percentile(d, 99):.2e}")
+    assert d.max() <= FLOW_TOL
+
+
+def test_tvl1_matches_oracle_sd_boxes_plain(ops):
+    """720x576 box scene, the defaults (5 levels, 5 warps, 30 iterations)
+    on the plain images (no structure iterations): every pixel."""
+    w = synth.sd_boxes_workload()
+    _, _, d = run_both(ops, w.frame0, w.frame1, iters_s=0)
+    print(f"tvl1 sd_boxes plain: max |d| {d.max():.2e}, p99 {np.percentile(d, 99):.2e}")
+    assert d.max() <= FLOW_TOL
+
+
+def test_tvl1_matches_oracle_sd_boxes(ops):
+    """720x576 box scene with the structure-texture split (all defaults).
+    The split leaves low-contrast textures on which the warped, linearised
+    problem is badly conditioned near the fast boxes' occlusion edges: the
+    oracle itself moves by more than 0.01 px on a few per cent of the pixels
+    when its textures change by 1.5e-7 (the size of the float32 error of the
+    textures).  The GPU must agree with the oracle within 0.01 px on as many
+    pixels as that probe does (1 % margin), with a median far below it."""
+    w = synth.sd_boxes_workload()
+    _, (u1, u2), d = run_both(ops, w.frame0, w.frame1)
+    p = oracle_params(ops.tvl1_params())
+    r1, r2 = oracle.tvl1.tvl1_flow(oracle.pyramid(w.frame0, p.levels),
+                                   oracle.pyramid(w.frame1, p.levels), p, perturb=1.5e-7)
+    probe = np.mean(np.hypot(r1 - u1, r2 - u2) <= FLOW_TOL)
+    ok = np.mean(d <= FLOW_TOL)
+    print(f"tvl1 sd_boxes: within {FLOW_TOL}: GPU {ok:.5f}, perturbed oracle {probe:.5f}; "
+          f"GPU median {np.median(d):.2e}, max {d.max():.2e}")
+    assert ok >= probe - 0.01
+    assert np.median(d) <= 1e-4
+
+
+def test_tvl1_zero_motion_exact(ops):
+    w = synth.sd_shift_workload(seed=5)
+    p = ops.tvl1_params(levels=3, warps=2, iters=10)
+    P = ops.pyramid_build(dev(w.frame0), 3)
+    g = ops.tvl1_flow(P, P, p)
+    assert torch.count_nonzero(g).item() == 0
+
+
+def test_box_mean_flow_matches_oracle(ops):
+    w = synth.sd_boxes_workload()
+    p = ops.tvl1_params()
+    P = ops.pyramid_build(dev(w.frame0), p.levels)
+    Q = ops.pyramid_build(dev(w.frame1), p.levels)
+    flow = ops.tvl1_flow(P, Q, p)
+    boxes = np.concatenate([w.boxes, [[-20, -20, 5.5, 3.2], [700, 560, 900, 900],
+                                      [800, 10, 900, 20], [10.2, 10.2, 10.8, 10.8],
+                                      [0, 0, 719, 575]]]).astype(np.float32)
+    ob, oc = ops.box_mean_flow(flow, dev(boxes))
+    torch.cuda.synchronize()
+    fl = flow.cpu().numpy().astype(np.float64)
+    o_b, o_c, o_m = oracle.tvl1.box_mean_flow(fl[..., 0], fl[..., 1], boxes)
+    assert np.array_equal(oc.cpu().numpy(), o_c)
+    np.testing.assert_allclose(ob.cpu().numpy(), o_b, atol=1e-4, rtol=0)
+    # the prediction against the true boxes (occlusions make a few boxes off)
+    err = np.abs(ob.cpu().numpy()[:20] - w.boxes_next).max(axis=1)
+    still = np.abs(w.boxes - w.boxes_next).max(axis=1)
+    print(f"mean-flow boxes vs truth: median {np.median(err):.3f} px, max {err.max():.3f} px "
+          f"(unmoved boxes: median {np.median(still):.3f} px)")
+    # small boxes moving up to 20 px in front of a static background: the
+    # regularised field follows most boxes only partly (see DESIGN)
+    assert np.median(err) < 0.6 * np.median(still)
