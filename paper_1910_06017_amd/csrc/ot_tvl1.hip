@@ -3,11 +3,13 @@
 // warps (Zach, Pock & Bischof 2007; Werlberger et al. 2009; Wedel et al.
 // 2009); and the per-box mean of the dense field (Sec. V-A prediction).
 //
-// Every pass is a 2-D stencil over float planes, one thread per pixel in
-// 64 x 4 workgroups (a wave covers 64 consecutive pixels of a row, so every
-// plane read is a coalesced row segment; the neighbour reads of a stencil
-// hit the same lines in L1/L2).  Iterations ping-pong between two buffers so
-// no workgroup reads what another one writes in the same launch.
+// Every pass is a 2-D stencil over float planes.  The pointwise passes run
+// one thread per pixel in 64 x 4 workgroups (a wave reads a row segment of
+// every plane; neighbour reads hit the same lines in L1/L2).  The iterated
+// passes (the structure dual and the TV-L1 iteration) run up to TV_K
+// iterations per launch on LDS tiles with a TV_K-pixel halo.  Launches
+// ping-pong between two buffers so no workgroup reads what another one
+// writes in the same launch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,27 +40,6 @@ __device__ __forceinline__ float div_at(int x, int y, int W, int H, GetX&& px, G
 }
 
 // ---------------------------------------------------------------- structure
-// One dual step of the structure (ROF) problem on f = img / 255:
-// w = div p - f / theta at (x, y), (x+1, y), (x, y+1); p <- (p + tau grad w)
-// / (1 + tau |grad w|).  p_in unused (taken as 0) when `first`.
-__global__ __launch_bounds__(TV_BX* TV_BY) void k_rof_step(const uint8_t* __restrict__ img, int pitch,
-                                                           int W, int H, const float2* __restrict__ p_in,
-                                                           float2* __restrict__ p_out, float inv_theta,
-                                                           float tau, int first) {
-    const int x = blockIdx.x * TV_BX + threadIdx.x, y = blockIdx.y * TV_BY + threadIdx.y;
-    if (x >= W || y >= H) return;
-    auto f = [&](int xx, int yy) { return (float)img[(size_t)yy * pitch + xx] * (1.0f / 255.0f); };
-    auto pxf = [&](int xx, int yy) { return first ? 0.0f : p_in[(size_t)yy * W + xx].x; };
-    auto pyf = [&](int xx, int yy) { return first ? 0.0f : p_in[(size_t)yy * W + xx].y; };
-    auto w = [&](int xx, int yy) { return div_at(xx, yy, W, H, pxf, pyf) - f(xx, yy) * inv_theta; };
-    const float wc = w(x, y);
-    const float gx = x + 1 < W ? w(x + 1, y) - wc : 0.0f;
-    const float gy = y + 1 < H ? w(x, y + 1) - wc : 0.0f;
-    const float nrm = 1.0f + tau * sqrtf(gx * gx + gy * gy);
-    const float2 p = first ? make_float2(0.0f, 0.0f) : p_in[(size_t)y * W + x];
-    p_out[(size_t)y * W + x] = make_float2((p.x + tau * gx) / nrm, (p.y + tau * gy) / nrm);
-}
-
 // texture = f - alpha * (f - theta div p)
 __global__ __launch_bounds__(TV_BX* TV_BY) void k_texture(const uint8_t* __restrict__ img, int pitch,
                                                           int W, int H, const float2* __restrict__ p,
@@ -123,50 +104,198 @@ __device__ __forceinline__ float2 data_step(float2 u, float4 d, float lt) {
     float s;
     if (rho < -t) s = lt;
     else if (rho > t) s = -lt;
-    else if (d.w > 0.0f) s = -rho / d.w;
+    else if (d.w > 0.0f) s = -rho * __builtin_amdgcn_rcpf(d.w);
     else s = 0.0f;
     return make_float2(u.x + s * d.x, u.y + s * d.y);
 }
 
-// One TV-L1 iteration: v = data step of u_in, u = v + theta div p_in (both
-// flow components), p = projection onto the unit ball of (p_in + (tau/theta)
-// grad u) / (1 + tau eps / theta).  The thread also forms u at its right and
-// lower neighbours (the gradient's other taps) from the same inputs.  p is
-// (p1x, p1y, p2x, p2y) per pixel; p_in taken as 0 when `first`.
-__global__ __launch_bounds__(TV_BX* TV_BY) void k_tvl1_iter(const float4* __restrict__ data,
-                                                            const float2* __restrict__ u_in,
-                                                            const float4* __restrict__ p_in,
-                                                            float2* __restrict__ u_out,
-                                                            float4* __restrict__ p_out, int W, int H,
-                                                            float lt, float theta, float k,
-                                                            float inv_shrink, int first) {
-    const int x = blockIdx.x * TV_BX + threadIdx.x, y = blockIdx.y * TV_BY + threadIdx.y;
-    if (x >= W || y >= H) return;
-    auto P = [&](int xx, int yy) {
-        return first ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : p_in[(size_t)yy * W + xx];
-    };
-    auto unew = [&](int xx, int yy) {
-        const size_t j = (size_t)yy * W + xx;
-        const float2 v = data_step(u_in[j], data[j], lt);
-        const float d1 = div_at(xx, yy, W, H, [&](int a, int b) { return P(a, b).x; },
-                                [&](int a, int b) { return P(a, b).y; });
-        const float d2 = div_at(xx, yy, W, H, [&](int a, int b) { return P(a, b).z; },
-                                [&](int a, int b) { return P(a, b).w; });
-        return make_float2(v.x + theta * d1, v.y + theta * d2);
-    };
-    const float2 uc = unew(x, y);
-    const float2 ur = x + 1 < W ? unew(x + 1, y) : uc;
-    const float2 ud = y + 1 < H ? unew(x, y + 1) : uc;
-    const size_t i = (size_t)y * W + x;
-    const float4 p = P(x, y);
-    float q1x = (p.x + k * fwd_x(uc.x, ur.x, x, W)) * inv_shrink;
-    float q1y = (p.y + k * fwd_y(uc.x, ud.x, y, H)) * inv_shrink;
-    float q2x = (p.z + k * fwd_x(uc.y, ur.y, x, W)) * inv_shrink;
-    float q2y = (p.w + k * fwd_y(uc.y, ud.y, y, H)) * inv_shrink;
-    const float n1 = fmaxf(1.0f, sqrtf(q1x * q1x + q1y * q1y));
-    const float n2 = fmaxf(1.0f, sqrtf(q2x * q2x + q2y * q2y));
-    u_out[i] = uc;
-    p_out[i] = make_float4(q1x / n1, q1y / n1, q2x / n2, q2y / n2);
+// ------------------------------------------------------ temporally blocked
+// Up to K iterations in one launch: a workgroup owns a TX x TY tile and
+// loads the state of the tile plus a K-pixel halo into LDS.  Each iteration
+// has two phases separated by barriers, both in place: phase A needs the
+// dual at the pixel and its left and upper neighbours, phase B the primal
+// at the pixel and its right and lower neighbours, so every iteration
+// invalidates one more ring of the region on each side and after n <= K
+// iterations exactly the tile is exact.  Region pixels outside the frame are
+// never used (the difference rules at the frame's edges do not reach past
+// it); reads past the region's own edge fall in the invalid ring and take 0
+// (dual) or the pixel's own value (primal).
+#ifndef OT_TV_K
+#define OT_TV_K 5
+#endif
+
+// Tile TX x TY outputs, NT threads; the region is the tile plus the halo.
+template <int K, int TX, int TY, int NT>
+struct TileGeom {
+    static constexpr int RX = TX + 2 * K, RY = TY + 2 * K, RN = RX * RY;
+    static constexpr int PER = (RN + NT - 1) / NT;  // region pixels per thread
+};
+// Large tiles for large levels; small ones where large tiles would leave
+// most compute units idle (each workgroup's critical path is its region).
+constexpr int TBL_X = 64, TBL_Y = 16, TBL_T = 1024;
+constexpr int TBS_X = 16, TBS_Y = 8, TBS_T = 256;
+
+// n (<= K) TV-L1 iterations: v = data step of u, u = v + theta div p (both
+// flow components), p = projection onto the unit ball of (p + (tau/theta)
+// grad u) / (1 + tau eps / theta); p is (p1x, p1y, p2x, p2y) per pixel and
+// taken as 0 when `first`.
+template <int K, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_tvl1_block(const float4* __restrict__ data,
+                                                           const float2* __restrict__ u_in,
+                                                           const float4* __restrict__ p_in,
+                                                           float2* __restrict__ u_out,
+                                                           float4* __restrict__ p_out, int W, int H,
+                                                           float lt, float theta, float k,
+                                                           float inv_shrink, int first, int n) {
+    using G = TileGeom<K, TX, TY, NT>;
+    __shared__ float2 su[G::RN];
+    __shared__ float4 sp[G::RN];
+    const int tid = threadIdx.x;
+    const int ox = blockIdx.x * TX - K, oy = blockIdx.y * TY - K;
+    float4 dat[G::PER];
+#pragma unroll
+    for (int q = 0; q < G::PER; ++q) {
+        const int r = tid + q * NT;
+        if (r >= G::RN) break;
+        const int gx = ox + r % G::RX, gy = oy + r / G::RX;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const size_t i = in ? (size_t)gy * W + gx : 0;
+        su[r] = in ? u_in[i] : make_float2(0.0f, 0.0f);
+        sp[r] = (in && !first) ? p_in[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        dat[q] = in ? data[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    __syncthreads();
+    for (int it = 0; it < n; ++it) {
+        // phase A: u = data step of u + theta div p
+#pragma unroll
+        for (int q = 0; q < G::PER; ++q) {
+            const int r = tid + q * NT;
+            if (r >= G::RN) break;
+            const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
+            if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+            const float2 v = data_step(su[r], dat[q], lt);
+            const float4 pc = sp[r];
+            const float4 pl = (gx > 0 && lx > 0) ? sp[r - 1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const float4 pu = (gy > 0 && ly > 0) ? sp[r - G::RX] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float d1 = 0.0f, d2 = 0.0f;
+            if (gx + 1 < W) {
+                d1 += pc.x;
+                d2 += pc.z;
+            }
+            if (gx > 0) {
+                d1 -= pl.x;
+                d2 -= pl.z;
+            }
+            if (gy + 1 < H) {
+                d1 += pc.y;
+                d2 += pc.w;
+            }
+            if (gy > 0) {
+                d1 -= pu.y;
+                d2 -= pu.w;
+            }
+            su[r] = make_float2(v.x + theta * d1, v.y + theta * d2);
+        }
+        __syncthreads();
+        // phase B: dual step and projection
+#pragma unroll
+        for (int q = 0; q < G::PER; ++q) {
+            const int r = tid + q * NT;
+            if (r >= G::RN) break;
+            const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
+            if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+            const float2 uc = su[r];
+            const float2 ur = lx + 1 < G::RX ? su[r + 1] : uc;
+            const float2 ud = ly + 1 < G::RY ? su[r + G::RX] : uc;
+            const float4 p = sp[r];
+            const float q1x = (p.x + k * fwd_x(uc.x, ur.x, gx, W)) * inv_shrink;
+            const float q1y = (p.y + k * fwd_y(uc.x, ud.x, gy, H)) * inv_shrink;
+            const float q2x = (p.z + k * fwd_x(uc.y, ur.y, gx, W)) * inv_shrink;
+            const float q2y = (p.w + k * fwd_y(uc.y, ud.y, gy, H)) * inv_shrink;
+            // projection: scale by min(1, 1/|q|) (|q| = 0 gives inf, so 1)
+            const float s1 = fminf(1.0f, __builtin_amdgcn_rsqf(q1x * q1x + q1y * q1y));
+            const float s2 = fminf(1.0f, __builtin_amdgcn_rsqf(q2x * q2x + q2y * q2y));
+            sp[r] = make_float4(q1x * s1, q1y * s1, q2x * s2, q2y * s2);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < G::PER; ++q) {
+        const int r = tid + q * NT;
+        if (r >= G::RN) break;
+        const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
+        if (lx < K || lx >= K + TX || ly < K || ly >= K + TY || gx >= W || gy >= H) continue;
+        const size_t i = (size_t)gy * W + gx;
+        u_out[i] = su[r];
+        p_out[i] = sp[r];
+    }
+}
+
+// n (<= K) dual steps of the structure (ROF) problem on f = img / 255:
+// w = div p - f / theta, p <- (p + tau grad w) / (1 + tau |grad w|); p taken
+// as 0 when `first`.
+template <int K, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_rof_block(const uint8_t* __restrict__ img, int pitch,
+                                                          int W, int H, const float2* __restrict__ p_in,
+                                                          float2* __restrict__ p_out, float inv_theta,
+                                                          float tau, int first, int n) {
+    using G = TileGeom<K, TX, TY, NT>;
+    __shared__ float2 sp[G::RN];
+    __shared__ float sw[G::RN];
+    const int tid = threadIdx.x;
+    const int ox = blockIdx.x * TX - K, oy = blockIdx.y * TY - K;
+    float fs[G::PER];
+#pragma unroll
+    for (int q = 0; q < G::PER; ++q) {
+        const int r = tid + q * NT;
+        if (r >= G::RN) break;
+        const int gx = ox + r % G::RX, gy = oy + r / G::RX;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        sp[r] = (in && !first) ? p_in[(size_t)gy * W + gx] : make_float2(0.0f, 0.0f);
+        fs[q] = in ? (float)img[(size_t)gy * pitch + gx] * (1.0f / 255.0f) * inv_theta : 0.0f;
+    }
+    __syncthreads();
+    for (int it = 0; it < n; ++it) {
+        // phase A: w = div p - f / theta
+#pragma unroll
+        for (int q = 0; q < G::PER; ++q) {
+            const int r = tid + q * NT;
+            if (r >= G::RN) break;
+            const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
+            if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+            const float2 pc = sp[r];
+            float d = 0.0f;
+            if (gx + 1 < W) d += pc.x;
+            if (gx > 0) d -= lx > 0 ? sp[r - 1].x : 0.0f;
+            if (gy + 1 < H) d += pc.y;
+            if (gy > 0) d -= ly > 0 ? sp[r - G::RX].y : 0.0f;
+            sw[r] = d - fs[q];
+        }
+        __syncthreads();
+        // phase B: p <- (p + tau grad w) / (1 + tau |grad w|)
+#pragma unroll
+        for (int q = 0; q < G::PER; ++q) {
+            const int r = tid + q * NT;
+            if (r >= G::RN) break;
+            const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
+            if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+            const float wc = sw[r];
+            const float gxv = gx + 1 < W ? (lx + 1 < G::RX ? sw[r + 1] : wc) - wc : 0.0f;
+            const float gyv = gy + 1 < H ? (ly + 1 < G::RY ? sw[r + G::RX] : wc) - wc : 0.0f;
+            const float inrm = __builtin_amdgcn_rcpf(1.0f + tau * sqrtf(gxv * gxv + gyv * gyv));
+            const float2 p = sp[r];
+            sp[r] = make_float2((p.x + tau * gxv) * inrm, (p.y + tau * gyv) * inrm);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < G::PER; ++q) {
+        const int r = tid + q * NT;
+        if (r >= G::RN) break;
+        const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
+        if (lx < K || lx >= K + TX || ly < K || ly >= K + TY || gx >= W || gy >= H) continue;
+        p_out[(size_t)gy * W + gx] = sp[r];
+    }
 }
 
 // Flow of a finer level (W x H) from the coarser one (Wc x Hc): 2 u(x / 2).
@@ -240,6 +369,9 @@ __global__ __launch_bounds__(BM_THREADS) void k_box_mean(const float2* __restric
 }
 
 // ------------------------------------------------------------------ host side
+// iterations per blocked launch (the halo width)
+constexpr int TV_K = OT_TV_K;
+
 inline dim3 grid2(int W, int H) { return dim3((W + TV_BX - 1) / TV_BX, (H + TV_BY - 1) / TV_BY); }
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -342,15 +474,25 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
     for (int l = L - 1; l >= 0; --l) {
         const int W = prev_pyr->w[l], H = prev_pyr->h[l];
         const dim3 gr = grid2(W, H), bl(TV_BX, TV_BY);
+        const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
+        const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
+        const bool large = gbl.x * gbl.y >= 256;
         // textures of both frames
         for (int f = 0; f < 2; ++f) {
             const ot_pyr* py = f == 0 ? prev_pyr : next_pyr;
             const uint8_t* img = py->level[l];
             const int pitch = py->pitch[l];
             int cr = 0;
-            for (int it = 0; it < prm->iters_s; ++it) {
-                hipLaunchKernelGGL(k_rof_step, gr, bl, 0, s, img, pitch, W, H, R[cr], R[cr ^ 1],
-                                   1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0);
+            for (int it = 0; it < prm->iters_s; it += TV_K) {
+                const int nb = prm->iters_s - it < TV_K ? prm->iters_s - it : TV_K;
+                if (large)
+                    hipLaunchKernelGGL((k_rof_block<TV_K, TBL_X, TBL_Y, TBL_T>), gbl, dim3(TBL_T), 0, s, img,
+                                       pitch, W, H, R[cr], R[cr ^ 1], 1.0f / prm->theta_s, prm->tau_s,
+                                       it == 0 ? 1 : 0, nb);
+                else
+                    hipLaunchKernelGGL((k_rof_block<TV_K, TBS_X, TBS_Y, TBS_T>), gbs, dim3(TBS_T), 0, s, img,
+                                       pitch, W, H, R[cr], R[cr ^ 1], 1.0f / prm->theta_s, prm->tau_s,
+                                       it == 0 ? 1 : 0, nb);
                 cr ^= 1;
             }
             if (prm->iters_s == 0) {
@@ -375,9 +517,16 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
         bool first = true;
         for (int wv = 0; wv < prm->warps; ++wv) {
             hipLaunchKernelGGL(k_warp, gr, bl, 0, s, T0, T1, G, W, H, U[cu], D);
-            for (int it = 0; it < prm->iters; ++it) {
-                hipLaunchKernelGGL(k_tvl1_iter, gr, bl, 0, s, D, U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W,
-                                   H, lt, prm->theta, k, inv_shrink, first ? 1 : 0);
+            for (int it = 0; it < prm->iters; it += TV_K) {
+                const int nb = prm->iters - it < TV_K ? prm->iters - it : TV_K;
+                if (large)
+                    hipLaunchKernelGGL((k_tvl1_block<TV_K, TBL_X, TBL_Y, TBL_T>), gbl, dim3(TBL_T), 0, s, D,
+                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       inv_shrink, first ? 1 : 0, nb);
+                else
+                    hipLaunchKernelGGL((k_tvl1_block<TV_K, TBS_X, TBS_Y, TBS_T>), gbs, dim3(TBS_T), 0, s, D,
+                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       inv_shrink, first ? 1 : 0, nb);
                 cu ^= 1;
                 cp ^= 1;
                 first = false;
