@@ -104,6 +104,9 @@ __device__ __forceinline__ BoxMap box_map(uint32_t lo, uint32_t hi, bool linear)
 // threads of the workgroup taking part) into sel.res.  On entry sel.klo/khi
 // hold each axis' smallest and largest key, sel.rank the two ranks and
 // sel.hist is zero, all written before a barrier that precedes the call.
+// The two ranks of an axis must be equal or adjacent (two targets in
+// different buckets are taken as the largest key of the lower bucket and the
+// smallest of the upper one).
 // Every axis must hold at least one element, and visit() must present the
 // same multiset with the same values on every call.  value_linear selects
 // value-linear buckets for the first round (else key-linear).  Waves 0..NA-1 do the per-axis
@@ -477,17 +480,56 @@ __device__ __forceinline__ void box_median(const float* __restrict__ boxes, int 
 // once per pass, keyed by the squared ratio (monotone in the ratio), and the
 // two middle squared ratios are square-rooted at the end.
 // ---------------------------------------------------------------------------
+constexpr int SCALE_BAND = 6144;    // keys around the median held for the final selection
+constexpr int SCALE_SAMPLE = 4096;  // sampled pairs (in the band's storage, used first)
+
 struct ScaleSmem {
-    float4 pu[SCALE_CAP];  // (x, y) in the first frame, (x, y) in the second
-    SelSmem<2> sel;        // displacement medians
-    SelSmem<1> rsel;       // ratio median
+    float4 pu[SCALE_CAP];      // (x, y) in the first frame, (x, y) in the second
+    uint32_t band[SCALE_BAND];  // sampled keys, then the keys of the band
+    SelSmem<2> sel;            // displacement medians
+    SelSmem<1> rsel;           // ratio median
     int32_t count;
-    uint32_t npairs;
+    uint32_t npairs, nbelow, nabove, nsample, nband;
 };
 
-// Visit every unordered pair {i, j} of the c gathered points once as f(r2),
-// r2 the squared distance ratio, skipping pairs whose squared first-frame
-// distance is zero.  Pair q of the c * floor((c-1)/2) + (c even ? c/2 : 0)
+// Key of the pair (a, e): the order-preserving key of the squared distance
+// ratio; false when the squared first-frame distance is 0.  Every pass goes
+// through this one function (explicit FMAs, the hardware reciprocal), so a
+// pair gets the same key every time.
+__device__ __forceinline__ bool pair_key(const float4& a, const float4& e, uint32_t& key) {
+    const float ux = a.x - e.x, uy = a.y - e.y, vx = a.z - e.z, vy = a.w - e.w;
+    const float du2 = __builtin_fmaf(ux, ux, uy * uy);
+    const float dv2 = __builtin_fmaf(vx, vx, vy * vy);
+    key = f2key(dv2 * __builtin_amdgcn_rcpf(du2));
+    return du2 > 0.0f;
+}
+
+// A fixed bijective mixing of 32-bit integers (xor-shift and odd-multiply
+// rounds), used to draw sample indices.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Slot for each active lane with pred set, reserved with one LDS atomic per
+// wave on *counter (lanes may be inactive; slots follow lane order).
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
+    const unsigned long long m = __ballot(pred);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const int leader = __ffsll(__ballot(1)) - 1;
+    uint32_t base = 0u;
+    if ((int)(threadIdx.x & 63) == leader && m) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    return base + below;
+}
+
+// Visit every unordered pair {i, j} of the c gathered points once as f(key),
+// key that of the squared distance ratio (pair_key), skipping pairs whose
+// squared first-frame distance is zero.  Pair q of the c * floor((c-1)/2) + (c even ? c/2 : 0)
 // pairs is (i, (i + d) mod c) with i = q mod c and d = q / c + 1: every
 // circular distance d below c/2 pairs all c points, and for even c the
 // distance c/2 pairs only the first half.  Each thread steps q by BOX_THREADS.
@@ -502,15 +544,8 @@ __device__ __forceinline__ void visit_pairs(const float4* __restrict__ pu, int c
     for (uint32_t q = t; q < total; q += BOX_THREADS) {
         uint32_t j = i + d + 1u;
         if (j >= uc) j -= uc;
-        const float4 a = pu[i], e = pu[j];
-        const float ux = a.x - e.x, uy = a.y - e.y, vx = a.z - e.z, vy = a.w - e.w;
-        // explicit fmas: every pass must compute the same key for a pair
-        const float du2 = __builtin_fmaf(ux, ux, uy * uy);
-        const float dv2 = __builtin_fmaf(vx, vx, vy * vy);
-        if (du2 > 0.0f) {
-            const float v[1] = {dv2 * __builtin_amdgcn_rcpf(du2)};
-            f(v);
-        }
+        uint32_t key;
+        if (pair_key(pu[i], pu[j], key)) f(key);
         i += si;
         d += sd;
         if (i >= uc) {
@@ -532,6 +567,10 @@ __device__ __forceinline__ void box_scaled(const float* __restrict__ boxes, int 
     if (tid == 0) {
         sm.count = 0;
         sm.npairs = 0u;
+        sm.nbelow = 0u;
+        sm.nabove = 0u;
+        sm.nsample = 0u;
+        sm.nband = 0u;
     }
     sel_init(sm.sel);
     sel_init(sm.rsel);
@@ -565,32 +604,201 @@ __device__ __forceinline__ void box_scaled(const float* __restrict__ boxes, int 
         });
         mx = 0.5f * (key2f(sm.sel.res[0][0]) + key2f(sm.sel.res[0][1]));
         my = 0.5f * (key2f(sm.sel.res[1][0]) + key2f(sm.sel.res[1][1]));
-        // pair pass: key range and number of pairs
-        uint32_t lo = 0xFFFFFFFFu, hi = 0u, np = 0u;
-        visit_pairs(sm.pu, c, [&](const float (&v)[1]) {
-            const uint32_t k = f2key(v[0]);
-            lo = min(lo, k);
-            hi = max(hi, k);
+        // Ratio median, exact, in two passes over the pairs in the common
+        // case.  (1) A fixed pseudo-random sample of at most SCALE_SAMPLE
+        // pairs gives two sample quantiles A <= B around its median, 14
+        // standard deviations of the sample median's rank away on each
+        // side.  (2) Pass one counts all pairs, those below A and above B,
+        // and histograms the keys in [A, B] into BOX_NB buckets.  (3) The histogram names
+        // the bucket(s) holding both middle ranks; pass two keeps the keys
+        // of those buckets and the exact selection runs on them alone (on
+        // all pairs of that key range if they do not fit).  If a middle rank
+        // lies outside [A, B], the exact selection runs on all pairs.
+        const uint32_t uc = (uint32_t)c;
+        const uint32_t total = uc * ((uc - 1u) / 2u) + ((uc & 1u) ? 0u : uc / 2u);
+        // pairs drawn by a hashed index: neighbouring pairs of the walk
+        // share their points, so an evenly strided sample is far from random
+        const uint32_t ns = min(total, (uint32_t)SCALE_SAMPLE);
+        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+        for (uint32_t t = tid; t < ns; t += BOX_THREADS) {
+            const uint32_t q = (uint32_t)(((uint64_t)mix32(t) * total) >> 32), d = q / uc, i = q - d * uc;
+            uint32_t j = i + d + 1u;
+            if (j >= uc) j -= uc;
+            uint32_t key;
+            const bool ok = pair_key(sm.pu[i], sm.pu[j], key);
+            const uint32_t slot = wave_append(ok, &sm.nsample);
+            if (ok) {
+                sm.band[slot] = key;
+                lo = min(lo, key);
+                hi = max(hi, key);
+            }
+        }
+        lo = wave_min_u32(lo);
+        hi = wave_max_u32(hi);
+        // the two bracket ranks are far apart: each is its own (equal-rank)
+        // target, as two axes of one selection over the sample
+        if (tid < 2) {
+            sm.sel.klo[tid] = 0xFFFFFFFFu;
+            sm.sel.khi[tid] = 0u;
+        }
+        __syncthreads();
+        if (lane == 0 && lo <= hi) {
+            for (int a = 0; a < 2; ++a) {
+                atomicMin(&sm.sel.klo[a], lo);
+                atomicMax(&sm.sel.khi[a], hi);
+            }
+        }
+        __syncthreads();
+        const uint32_t msmp = sm.nsample;
+        uint32_t A = 0u, B = 0xFFFFFFFFu;
+        if (msmp > 0u) {
+            const uint32_t h = 2u + (uint32_t)ceilf(7.0f * sqrtf((float)msmp));
+            const uint32_t rc = (msmp - 1u) / 2u;
+            if (tid == 0) {
+                sm.sel.rank[0][0] = sm.sel.rank[0][1] = rc > h ? rc - h : 0u;
+                sm.sel.rank[1][0] = sm.sel.rank[1][1] = min(msmp - 1u, msmp / 2u + h);
+            }
+            __syncthreads();
+            select_ranks<2>(sm.sel, false, [&](auto&& f) {
+                for (uint32_t t = tid; t < msmp; t += BOX_THREADS) {
+                    const float k = key2f(sm.band[t]);
+                    const float v[2] = {k, k};
+                    f(v);
+                }
+            });
+            A = sm.sel.res[0][0];
+            B = sm.sel.res[1][0];
+        }
+        // pass one: counts and the histogram of [A, B] (runs of equal
+        // buckets added once, as in the selection)
+        const uint32_t span = B - A;
+        const int sh = max(0, (span == 0u ? 0 : 32 - __clz((int)span)) - 10);
+        uint32_t np = 0u, nbelow = 0u, nabove = 0u;
+        int cur = 0;
+        uint32_t run = 0u;
+        lo = 0xFFFFFFFFu;
+        hi = 0u;
+        uint32_t* hist = sm.rsel.hist[0];
+        visit_pairs(sm.pu, c, [&](uint32_t key) {
             ++np;
+            lo = min(lo, key);
+            hi = max(hi, key);
+            if (key < A) {
+                ++nbelow;
+            } else if (key > B) {
+                ++nabove;
+            } else {
+                const int bu = (int)((key - A) >> sh);
+                if (bu != cur) {
+                    if (run) atomicAdd(&hist[cur], run);
+                    cur = bu;
+                    run = 0u;
+                }
+                ++run;
+            }
         });
+        if (run) atomicAdd(&hist[cur], run);
         lo = wave_min_u32(lo);
         hi = wave_max_u32(hi);
         np = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(np), 63);
+        nbelow = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nbelow), 63);
+        nabove = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nabove), 63);
+        if (tid == 0) {
+            sm.rsel.klo[0] = 0xFFFFFFFFu;
+            sm.rsel.khi[0] = 0u;
+        }
+        __syncthreads();
         if (lane == 0 && np > 0u) {
             atomicMin(&sm.rsel.klo[0], lo);
             atomicMax(&sm.rsel.khi[0], hi);
             atomicAdd(&sm.npairs, np);
+            atomicAdd(&sm.nbelow, nbelow);
+            atomicAdd(&sm.nabove, nabove);
         }
         __syncthreads();
         const uint32_t npairs = sm.npairs;
         if (npairs > 0u) {
-            if (tid == 0) {
-                sm.rsel.rank[0][0] = (npairs - 1u) / 2u;
-                sm.rsel.rank[0][1] = npairs / 2u;
+            const uint32_t t0 = (npairs - 1u) / 2u, t1 = npairs / 2u;
+            const uint32_t below = sm.nbelow, above = sm.nabove;
+            const bool inside = msmp > 0u && below <= t0 && t1 < npairs - above;
+            // scan: the buckets of both middle ranks among the keys in [A, B]
+            if (inside && tid < 64) {
+                uint32_t cnt[16];
+                uint32_t tot = 0u;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    cnt[j] = hist[16 * lane + j];
+                    tot += cnt[j];
+                }
+                const uint32_t incl = wave_incl_scan_u32(tot), excl = incl - tot;
+                int bk[2];
+                uint32_t base[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const uint32_t k = (t == 0 ? t0 : t1) - below;
+                    const bool mine = k >= excl && k < incl;
+                    int bin = 16 * lane;
+                    uint32_t acc = excl, bse = excl;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        if (k >= acc + cnt[j]) {
+                            bin = 16 * lane + j + 1;
+                            bse = acc + cnt[j];
+                        }
+                        acc += cnt[j];
+                    }
+                    const int src = __ffsll((unsigned long long)__ballot(mine)) - 1;
+                    bk[t] = __builtin_amdgcn_readlane(bin, src);
+                    base[t] = (uint32_t)__builtin_amdgcn_readlane((int)bse, src);
+                }
+                if (lane == 0) {
+                    // keys of buckets bk[0] .. bk[1] (at most two adjacent ones)
+                    const uint32_t klo = A + ((uint32_t)bk[0] << sh);
+                    const uint64_t khi64 = (uint64_t)A + ((uint64_t)(bk[1] + 1) << sh) - 1u;
+                    sm.rsel.klo[0] = klo;
+                    sm.rsel.khi[0] = (uint32_t)min(khi64, (uint64_t)B);
+                    sm.rsel.rank[0][0] = t0 - below - base[0];
+                    sm.rsel.rank[0][1] = t1 - below - base[0];
+                }
             }
-            // the first round's buckets follow the key: ratio outliers would
-            // squeeze the bulk into a few value-linear buckets
-            select_ranks<1>(sm.rsel, false, [&](auto&& f) { visit_pairs(sm.pu, c, f); });
+            if (!inside && tid == 0) {
+                sm.rsel.rank[0][0] = t0;
+                sm.rsel.rank[0][1] = t1;
+            }
+            __syncthreads();
+            for (int e = tid; e < BOX_NB; e += BOX_THREADS) hist[e] = 0u;
+            uint32_t bl = 0u, bh = 0u, nbd = 0u;
+            if (inside) {
+                // pass two: the keys of the target buckets
+                bl = sm.rsel.klo[0];
+                bh = sm.rsel.khi[0];
+                visit_pairs(sm.pu, c, [&](uint32_t key) {
+                    const bool in = key >= bl && key <= bh;
+                    const uint32_t slot = wave_append(in, &sm.nband);
+                    if (in && slot < (uint32_t)SCALE_BAND) sm.band[slot] = key;
+                });
+            }
+            __syncthreads();
+            nbd = sm.nband;
+            // key-linear first rounds: ratio outliers would squeeze the bulk
+            // into a few value-linear buckets
+            if (inside && nbd <= (uint32_t)SCALE_BAND) {
+                select_ranks<1>(sm.rsel, false, [&](auto&& f) {
+                    for (uint32_t t = tid; t < nbd; t += BOX_THREADS) {
+                        const float v[1] = {key2f(sm.band[t])};
+                        f(v);
+                    }
+                });
+            } else {
+                // all pairs, restricted to the range in rsel (the target
+                // buckets, or every key)
+                select_ranks<1>(sm.rsel, false, [&](auto&& f) {
+                    visit_pairs(sm.pu, c, [&](uint32_t key) {
+                        const float v[1] = {key2f(key)};
+                        f(v);
+                    });
+                });
+            }
             s = 0.5f * (__builtin_sqrtf(key2f(sm.rsel.res[0][0])) + __builtin_sqrtf(key2f(sm.rsel.res[0][1])));
         }
     }
