@@ -347,8 +347,7 @@ def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS,
 def bench_dense(ops, wl, f0, f1, boxes, cs):
     """The dense variant on the same frame pair: TV-L1 flow with the default
     parameters (both frames' structure-texture split, 5 levels, 5 warps x 30
-    iterations) and the mean-flow box prediction, one graph replay; the
-    iteration kernel's time at level 0 from a graph of 30 iterations."""
+    iterations) and the mean-flow box prediction, one graph replay."""
     import torch
     p = ops.tvl1_params()
     H, W = wl.frame0.shape
@@ -370,13 +369,12 @@ def bench_dense(ops, wl, f0, f1, boxes, cs):
     with torch.cuda.graph(g, stream=cs):
         step()
     ms = _graph_ms(torch, g, cs, 10)
-    launches = p.levels * (2 * (p.iters_s + 1) + 1 + 1 + p.warps * (1 + p.iters)) + 1
     px = W * H
     # one iteration kernel at level 0: read u 8 B, p 16 B, data 16 B; write u 8 B, p 16 B
     it_bytes = px * 64
     return {"ms_per_step": ms, "frames_per_s": 1e3 / ms, "pixels_per_s": px / (ms * 1e-3),
             "levels": p.levels, "warps": p.warps, "iters": p.iters, "iters_s": p.iters_s,
-            "kernel_launches": launches, "iter_bytes_level0": it_bytes,
+            "iter_bytes_level0": it_bytes,
             "step": "TV-L1 flow (structure-texture of both frames, all levels) + box mean"}
 
 
