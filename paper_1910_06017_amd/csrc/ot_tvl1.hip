@@ -133,7 +133,16 @@ struct TileGeom {
 // Large tiles for large levels; small ones where large tiles would leave
 // most compute units idle (each workgroup's critical path is its region).
 constexpr int TBL_X = 64, TBL_Y = 16, TBL_T = 1024;
-constexpr int TBS_X = 16, TBS_Y = 8, TBS_T = 256;
+#ifndef OT_TVS_T
+#define OT_TVS_T 512
+#endif
+#ifndef OT_TVS_Y
+#define OT_TVS_Y 8
+#endif
+#ifndef OT_TVS_X
+#define OT_TVS_X 16
+#endif
+constexpr int TBS_X = OT_TVS_X, TBS_Y = OT_TVS_Y, TBS_T = OT_TVS_T;
 
 // n (<= K) TV-L1 iterations: v = data step of u, u = v + theta div p (both
 // flow components), p = projection onto the unit ball of (p + (tau/theta)
