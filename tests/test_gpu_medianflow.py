@@ -280,3 +280,17 @@ def test_median_flow_pipeline_sd_boxes(ops):
     # median box still follows its true scale
     assert np.median(np.abs(gs - s_true)) < 0.01
     assert st_h.mean() > 0.5
+
+
+def test_box_scaled_many_equal_ratios(ops):
+    """An exact translation of integer grids: nearly every pair has the same
+    ratio key, so the keys around the median do not fit on chip and the
+    selection runs over all pairs; the scale is 1 to rounding."""
+    g = np.stack(np.meshgrid(np.arange(20.0), np.arange(15.0)), -1).reshape(-1, 2) * 3 + 40
+    P = np.concatenate([g, g + 200]).astype(np.float32)
+    Q = (P + np.array([5.0, -3.0])).astype(np.float32)
+    ids = np.repeat(np.arange(2, dtype=np.int32), len(g))
+    boxes = np.array([[40, 40, 97, 82], [240, 240, 297, 282]], np.float32)
+    st = np.ones(len(P), np.uint8)
+    g_, o = check_scaled(ops, boxes, ids, P, Q, st)
+    assert np.all(np.abs(g_[2] - 1.0) <= 1e-6) and np.all(o[2] == 1.0)

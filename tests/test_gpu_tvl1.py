@@ -127,3 +127,27 @@ def test_box_mean_flow_matches_oracle(ops):
     # small boxes moving up to 20 px in front of a static background: the
     # regularised field follows most boxes only partly (see DESIGN)
     assert np.median(err) < 0.6 * np.median(still)
+
+
+def test_tvl1_pitched_frames(ops):
+    """Level 0 read through a row pitch larger than the width gives the same
+    flow, bit for bit, as the packed frame."""
+    import ctypes as C
+    f0, f1, _ = synth.shifted_pair(731, W=150, H=100, shift=(0.8, 1.1))
+    p = ops.tvl1_params(levels=3, warps=2, iters=10, iters_s=10)
+
+    def pitched(img):
+        big = np.zeros((img.shape[0], 173), np.uint8)
+        big[:, 11:11 + img.shape[1]] = img
+        t = dev(big)[:, 11:11 + img.shape[1]]
+        ws = ops.alloc_workspace(img.shape[1], img.shape[0], 3)
+        d = ops.OtPyr()
+        ops.check(ops.lib().ot_pyramid_build(t.data_ptr(), img.shape[1], img.shape[0], 173, 3,
+                                             ws.data_ptr(), ws.numel(), 0, C.byref(d),
+                                             torch.cuda.current_stream().cuda_stream), "build")
+        return ops.Pyramid(t, ws, d)
+
+    a = ops.tvl1_flow(pitched(f0), pitched(f1), p)
+    b = ops.tvl1_flow(ops.pyramid_build(dev(f0), 3), ops.pyramid_build(dev(f1), 3), p)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
