@@ -609,11 +609,12 @@ __device__ __forceinline__ void box_scaled(const float* __restrict__ boxes, int 
         // pairs gives two sample quantiles A <= B around its median, 14
         // standard deviations of the sample median's rank away on each
         // side.  (2) Pass one counts all pairs, those below A and above B,
-        // and histograms the keys in [A, B] into BOX_NB buckets.  (3) The histogram names
-        // the bucket(s) holding both middle ranks; pass two keeps the keys
-        // of those buckets and the exact selection runs on them alone (on
-        // all pairs of that key range if they do not fit).  If a middle rank
-        // lies outside [A, B], the exact selection runs on all pairs.
+        // and histograms the keys in [A, B] into BOX_NB buckets.  (3) The
+        // histogram names the bucket(s) holding both middle ranks; pass two
+        // keeps the keys of those buckets and the exact selection runs on
+        // them alone (on all pairs of that key range if they do not fit).
+        // If a middle rank lies outside [A, B], the exact selection runs on
+        // all pairs.
         const uint32_t uc = (uint32_t)c;
         const uint32_t total = uc * ((uc - 1u) / 2u) + ((uc & 1u) ? 0u : uc / 2u);
         // pairs drawn by a hashed index: neighbouring pairs of the walk
