@@ -7,8 +7,8 @@ stream into one batched launch (new pyramid, tracking, box update; see
 `batch.py`).  Frames that arrive while a tick runs join the next tick.  A
 stream's previous pyramid, points and boxes stay resident between frames:
 each frame builds one pyramid and the two pyramid workspaces swap roles.
-Every `reseed_every`-th frame replaces the stream's boxes and points with
-synthetic "detections".  Streams silent for `evict_after` seconds are evicted
+A frame may carry synthetic "detections" (the benchmark attaches them to
+every 10th frame of a stream) that replace the stream's boxes and points.  Streams silent for `evict_after` seconds are evicted
 and their memory returned to the budget.
 
 `Scheduler` is pure Python (no GPU) so admission, batching order and
