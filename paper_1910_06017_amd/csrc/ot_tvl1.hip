@@ -40,13 +40,21 @@ __device__ __forceinline__ float div_at(int x, int y, int W, int H, GetX&& px, G
 }
 
 // ---------------------------------------------------------------- structure
-// texture = f - alpha * (f - theta div p)
-__global__ __launch_bounds__(TV_BX* TV_BY) void k_texture(const uint8_t* __restrict__ img, int pitch,
-                                                          int W, int H, const float2* __restrict__ p,
-                                                          float* __restrict__ tex, float theta,
+// texture = f - alpha * (f - theta div p), both frames (blockIdx.z).
+__global__ __launch_bounds__(TV_BX* TV_BY) void k_texture(const uint8_t* __restrict__ img0, int pitch0,
+                                                          const uint8_t* __restrict__ img1, int pitch1,
+                                                          int W, int H, const float2* __restrict__ p0,
+                                                          const float2* __restrict__ p1,
+                                                          float* __restrict__ tex0,
+                                                          float* __restrict__ tex1, float theta,
                                                           float alpha) {
     const int x = blockIdx.x * TV_BX + threadIdx.x, y = blockIdx.y * TV_BY + threadIdx.y;
     if (x >= W || y >= H) return;
+    const bool second = blockIdx.z != 0;
+    const uint8_t* __restrict__ img = second ? img1 : img0;
+    const int pitch = second ? pitch1 : pitch0;
+    const float2* __restrict__ p = second ? p1 : p0;
+    float* __restrict__ tex = second ? tex1 : tex0;
     const float f = (float)img[(size_t)y * pitch + x] * (1.0f / 255.0f);
     auto pxf = [&](int xx, int yy) { return p[(size_t)yy * W + xx].x; };
     auto pyf = [&](int xx, int yy) { return p[(size_t)yy * W + xx].y; };
@@ -243,12 +251,22 @@ __global__ __launch_bounds__(NT) void k_tvl1_block(const float4* __restrict__ da
 // n (<= K) dual steps of the structure (ROF) problem on f = img / 255:
 // w = div p - f / theta, p <- (p + tau grad w) / (1 + tau |grad w|); p taken
 // as 0 when `first`.
+// The two frames of a pair, one per blockIdx.z.
+struct FramePair {
+    const uint8_t* img[2];
+    int pitch[2];
+    const float2* p_in[2];
+    float2* p_out[2];
+};
+
 template <int K, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_rof_block(const uint8_t* __restrict__ img, int pitch,
-                                                          int W, int H, const float2* __restrict__ p_in,
-                                                          float2* __restrict__ p_out, float inv_theta,
-                                                          float tau, int first, int n) {
+__global__ __launch_bounds__(NT) void k_rof_block(FramePair fp, int W, int H, float inv_theta,
+                                                  float tau, int first, int n) {
     using G = TileGeom<K, TX, TY, NT>;
+    const uint8_t* __restrict__ img = fp.img[blockIdx.z];
+    const int pitch = fp.pitch[blockIdx.z];
+    const float2* __restrict__ p_in = fp.p_in[blockIdx.z];
+    float2* __restrict__ p_out = fp.p_out[blockIdx.z];
     __shared__ float2 sp[G::RN];
     __shared__ float sw[G::RN];
     const int tid = threadIdx.x;
@@ -385,11 +403,11 @@ inline dim3 grid2(int W, int H) { return dim3((W + TV_BX - 1) / TV_BX, (H + TV_B
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace: textures T0, T1 (float), structure duals (2 x float2), image
+// Workspace: textures T0, T1 (float), structure duals (2 x 2 x float2), image
 // gradient (float2), data (float4), flow (2 x float2), dual (2 x float4),
 // each sized for level 0 and reused by the coarser levels.
 struct TvLayout {
-    size_t t0, t1, r0, r1, g, d, u0, u1, p0, p1, bytes;
+    size_t t0, t1, r0, r1, r2, r3, g, d, u0, u1, p0, p1, bytes;
     static TvLayout make(int W, int H) {
         const size_t n = (size_t)W * H;
         TvLayout L;
@@ -403,6 +421,8 @@ struct TvLayout {
         L.t1 = take(n * 4);
         L.r0 = take(n * 8);
         L.r1 = take(n * 8);
+        L.r2 = take(n * 8);
+        L.r3 = take(n * 8);
         L.g = take(n * 8);
         L.d = take(n * 16);
         L.u0 = take(n * 8);
@@ -472,7 +492,9 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
     uint8_t* base = static_cast<uint8_t*>(ws);
     float* T0 = reinterpret_cast<float*>(base + T.t0);
     float* T1 = reinterpret_cast<float*>(base + T.t1);
-    float2* R[2] = {reinterpret_cast<float2*>(base + T.r0), reinterpret_cast<float2*>(base + T.r1)};
+    // structure duals: frame f ping-pongs between R[f][0] and R[f][1]
+    float2* R[2][2] = {{reinterpret_cast<float2*>(base + T.r0), reinterpret_cast<float2*>(base + T.r1)},
+                       {reinterpret_cast<float2*>(base + T.r2), reinterpret_cast<float2*>(base + T.r3)}};
     float2* G = reinterpret_cast<float2*>(base + T.g);
     float4* D = reinterpret_cast<float4*>(base + T.d);
     float2* U[2] = {reinterpret_cast<float2*>(base + T.u0), reinterpret_cast<float2*>(base + T.u1)};
@@ -486,32 +508,35 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
         const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
         const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
         const bool large = gbl.x * gbl.y >= 256;
-        // textures of both frames
-        for (int f = 0; f < 2; ++f) {
-            const ot_pyr* py = f == 0 ? prev_pyr : next_pyr;
-            const uint8_t* img = py->level[l];
-            const int pitch = py->pitch[l];
-            int cr = 0;
-            for (int it = 0; it < prm->iters_s; it += TV_K) {
-                const int nb = prm->iters_s - it < TV_K ? prm->iters_s - it : TV_K;
-                if (large)
-                    hipLaunchKernelGGL((k_rof_block<TV_K, TBL_X, TBL_Y, TBL_T>), gbl, dim3(TBL_T), 0, s, img,
-                                       pitch, W, H, R[cr], R[cr ^ 1], 1.0f / prm->theta_s, prm->tau_s,
-                                       it == 0 ? 1 : 0, nb);
-                else
-                    hipLaunchKernelGGL((k_rof_block<TV_K, TBS_X, TBS_Y, TBS_T>), gbs, dim3(TBS_T), 0, s, img,
-                                       pitch, W, H, R[cr], R[cr ^ 1], 1.0f / prm->theta_s, prm->tau_s,
-                                       it == 0 ? 1 : 0, nb);
-                cr ^= 1;
+        // textures of both frames, the two frames side by side in every launch
+        int cr = 0;
+        for (int it = 0; it < prm->iters_s; it += TV_K) {
+            const int nb = prm->iters_s - it < TV_K ? prm->iters_s - it : TV_K;
+            FramePair fp;
+            for (int f = 0; f < 2; ++f) {
+                const ot_pyr* py = f == 0 ? prev_pyr : next_pyr;
+                fp.img[f] = py->level[l];
+                fp.pitch[f] = py->pitch[l];
+                fp.p_in[f] = R[f][cr];
+                fp.p_out[f] = R[f][cr ^ 1];
             }
-            if (prm->iters_s == 0) {
-                // no structure iterations: p = 0
-                hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0,
-                                   s, R[cr], (size_t)W * H);
-            }
-            hipLaunchKernelGGL(k_texture, gr, bl, 0, s, img, pitch, W, H, R[cr], f == 0 ? T0 : T1,
-                               prm->theta_s, prm->alpha);
+            if (large)
+                hipLaunchKernelGGL((k_rof_block<TV_K, TBL_X, TBL_Y, TBL_T>), dim3(gbl.x, gbl.y, 2), dim3(TBL_T), 0,
+                                   s, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+            else
+                hipLaunchKernelGGL((k_rof_block<TV_K, TBS_X, TBS_Y, TBS_T>), dim3(gbs.x, gbs.y, 2), dim3(TBS_T), 0,
+                                   s, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+            cr ^= 1;
         }
+        if (prm->iters_s == 0) {
+            // no structure iterations: p = 0
+            for (int f = 0; f < 2; ++f)
+                hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0, s,
+                                   R[f][cr], (size_t)W * H);
+        }
+        hipLaunchKernelGGL(k_texture, dim3(gr.x, gr.y, 2), bl, 0, s, prev_pyr->level[l], prev_pyr->pitch[l],
+                           next_pyr->level[l], next_pyr->pitch[l], W, H, R[0][cr], R[1][cr], T0, T1,
+                           prm->theta_s, prm->alpha);
         hipLaunchKernelGGL(k_central_grad, gr, bl, 0, s, T1, W, H, G);
         // initial flow: zero at the coarsest level, else the coarser flow doubled
         if (l == L - 1) {

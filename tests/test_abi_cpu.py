@@ -275,7 +275,7 @@ def test_tvl1_validation(L):
     assert (p.levels, p.warps, p.iters, p.iters_s) == (5, 5, 30, 50)
     n = 720 * 576
     al = lambda v: (v + 255) // 256 * 256
-    assert L.ot_tvl1_bytes(720, 576) == 2 * al(4 * n) + 3 * al(8 * n) + al(16 * n) + 2 * al(8 * n) + 2 * al(16 * n)
+    assert L.ot_tvl1_bytes(720, 576) == 2 * al(4 * n) + 5 * al(8 * n) + al(16 * n) + 2 * al(8 * n) + 2 * al(16 * n)
     assert L.ot_tvl1_bytes(0, 5) == 0
     _, P = layout(L, levels=5)
     need = L.ot_tvl1_bytes(720, 576)
