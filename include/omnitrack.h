@@ -15,6 +15,13 @@
  * The Lucas-Kanade steps follow Bouguet (2000), "Pyramidal implementation
  * of the Lucas-Kanade feature tracker"; gradients are 3x3 Scharr (2000);
  * the point gate is the Shi-Tomasi (1994) minimum eigenvalue.
+ * Around that path: many streams in one batched, graph-capturable tick
+ * (ot_batch_*); the working level of the preprocessing phase
+ * (ot_working_level, ot_lk_opts.base_level); Median Flow's forward-backward
+ * gate and scaled boxes (ot_fb_gate, ot_box_update_scaled); the matching and
+ * update phases (ot_iou_matrix, ot_assign, ot_track_update); and the
+ * paper's own dense engine, TV-L1 flow with the mean-flow box prediction
+ * (ot_tvl1_flow, ot_box_mean_flow).
  *
  * Conventions shared by every call
  *   - Pointers are DEVICE pointers unless marked (host).
