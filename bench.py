@@ -61,7 +61,7 @@ def parse():
                    help="skip the Median-Flow step (forward-backward tracking, scaled boxes)")
     p.add_argument("--served-seconds", type=float, default=3.0,
                    help="length of the 64-stream arrival trace for served and plain")
-    p.add_argument("--served-rates", default="1,2,4",
+    p.add_argument("--served-rates", default="1,2,3,4",
                    help="arrival-rate multipliers on 25 fps per stream (comma list)")
     return p.parse_args()
 
@@ -556,7 +556,14 @@ def bench_served(a):
                 ex.evict(sid)
             ex.ticks = 0
         runs.append(rec)
-    return {"streams": len(streams), "trace_s": a.served_seconds, "runs": runs}
+    # saturation: the largest offered load each path serves with p99 <= 40 ms
+    # (one 25 fps frame interval)
+    sat = {}
+    for name in executors:
+        ok = [r["offered_points_per_s"] for r in runs if r[name]["p99_ms"] <= 40.0]
+        sat[name] = max(ok) if ok else None
+    return {"streams": len(streams), "trace_s": a.served_seconds, "runs": runs,
+            "max_offered_points_per_s_with_p99_le_40ms": sat}
 
 
 def _pin(frame):
