@@ -151,3 +151,29 @@ def test_tvl1_pitched_frames(ops):
     b = ops.tvl1_flow(ops.pyramid_build(dev(f0), 3), ops.pyramid_build(dev(f1), 3), p)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("H,W,levels", [(1, 1, 1), (2, 3, 2), (5, 1, 3), (7, 9, 4)])
+def test_tvl1_tiny_frames(ops, H, W, levels):
+    """Degenerate sizes: every stencil edge rule at once, coarsest levels of
+    one pixel."""
+    rng = np.random.default_rng(H * 31 + W)
+    f0 = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    f1 = np.roll(f0, 1, axis=1)
+    _, _, d = run_both(ops, f0, f1, levels=levels, warps=2, iters=7, iters_s=6)
+    assert d.max() <= FLOW_TOL
+
+
+def test_box_mean_flow_edges(ops):
+    flow = torch.zeros((4, 5, 2), dtype=torch.float32, device="cuda")
+    flow[..., 0] = 1.5
+    flow[..., 1] = -2.0
+    boxes = np.array([[0, 0, 4, 3], [10, 10, 20, 20], [np.nan, 0, 2, 2], [-1e30, -1e30, 1e30, 1e30]],
+                     np.float32)
+    ob, oc = ops.box_mean_flow(flow, dev(boxes))
+    ob, oc = ob.cpu().numpy(), oc.cpu().numpy()
+    assert oc.tolist() == [20, 0, 0, 20]
+    assert np.array_equal(ob[0], [1.5, -2.0, 5.5, 1.0]) and np.array_equal(ob[1], boxes[1])
+    e = torch.zeros((0, 4), dtype=torch.float32, device="cuda")
+    ob, oc = ops.box_mean_flow(flow, e)
+    assert ob.shape == (0, 4)
