@@ -30,7 +30,7 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published (packed issue)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, one FP32 op per lane
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP32 work of the tracker per point and level:
+# Algorithmic FP32 work of the tracker per point and level (the method's per-pixel formulation):
 FLOP_TEMPLATE = 441 * 27     # 3 bilinear samples (7 flop) + 3 tensor FMAs (6 flop) per window pixel
 FLOP_SCHARR = 22 * 22 * 20   # 2 fused Scharr responses (10 flop) per bilinear tap
 FLOP_ITER = 441 * 12         # bilinear (7) + mismatch (1) + two FMAs (4) per window pixel
@@ -103,7 +103,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(streams shard across GPUs by placement, see DESIGN.md)"}))
+                          "(independent streams would be placed on GPUs whole, by HBM budget and load)"}))
         sys.exit(2)
     import torch
     from paper_1910_06017_amd import ops, synth

@@ -172,7 +172,7 @@ def tvl1_flow(pyr0: list, pyr1: list, prm: TvL1Params, perturb: float = 0.0):
     at least prm.levels each).  perturb > 0 adds a fixed pattern of that
     amplitude to every texture: a probe of how far the result moves under
     input changes the size of float32 rounding (the conditioning of the
-    problem, against which a float32 run is judged)."""
+    problem, the yardstick for comparing a float32 run)."""
     L = prm.levels
     u1 = u2 = None
     for l in range(L - 1, -1, -1):
