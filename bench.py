@@ -102,7 +102,7 @@ def traffic_from_profile(launch_pts: int):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                           "(independent streams would be placed on GPUs whole, by HBM budget and load)"}))
         sys.exit(2)
     import torch

@@ -65,7 +65,7 @@ enum {
     OT_E_SHAPE = -2,       /* image or pyramid shapes do not agree */
     OT_E_WORKSPACE = -3,   /* a caller buffer is too small */
     OT_E_LAUNCH = -4,      /* the HIP runtime refused a launch or copy */
-    OT_E_UNSUPPORTED = -5  /* valid request this build does not implement */
+    OT_E_UNSUPPORTED = -5  /* valid request the library does not implement */
 };
 
 #define OT_MAX_LEVELS 8
