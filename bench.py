@@ -298,6 +298,7 @@ def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS,
     ob = torch.empty((m, 4), dtype=torch.float32, device=dev)
     oc = torch.empty(m, dtype=torch.int32, device=dev)
     osc = torch.empty(m, dtype=torch.float32, device=dev)
+    wsc = ops.box_scaled_workspace(m, dev)
     kw = dict(win=WIN, levels=L, iters=ITERS, eps=EPS, margin=MARGIN)
     Q = ops.pyramid_build(f1, L, ws=ws1)
 
@@ -306,13 +307,13 @@ def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS,
         ops.lk_track(prev, Q, pts, out=(nxt, sf, None), **kw)
         ops.lk_track(Q, prev, nxt, out=(back, sb, None), **kw)
         ops.fb_gate(pts, back, sf, sb, 1.0, out=(st, fe))
-        ops.box_update_scaled(boxes, bid, pts, nxt, st, out=(ob, oc, osc))
+        ops.box_update_scaled(boxes, bid, pts, nxt, st, out=(ob, oc, osc), ws=wsc)
 
     def gate():
         ops.fb_gate(pts, back, sf, sb, 1.0, out=(st, fe))
 
     def scaled():
-        ops.box_update_scaled(boxes, bid, pts, nxt, st, out=(ob, oc, osc))
+        ops.box_update_scaled(boxes, bid, pts, nxt, st, out=(ob, oc, osc), ws=wsc)
 
     # the step is one replay; each kernel alone is KREP launches per replay so
     # that the graph's own launch cost is amortised

@@ -226,13 +226,19 @@ OT_API ot_err ot_fb_gate(const float* pts, const float* back_pts, const uint8_t*
  * box with c > OT_SCALE_MAX_POINTS gets NaN in out_boxes[b] and out_scale[b]
  * (its count is still written).  Ratios are formed in float32; pairs whose
  * squared first-frame distance is zero in float32 are skipped.  Layouts as in
- * ot_box_update; out_scale m float32.  Work per box grows with c^2.
+ * ot_box_update; out_scale m float32.  Work per box grows with c^2; the
+ * pairs of one box are spread over several workgroups.  ws:
+ * ot_box_scaled_bytes(m) bytes, 256-byte aligned, owned by the caller (no
+ * state is kept in it between calls).
  * Errors: OT_E_INVAL (negative counts, null pointers with m > 0,
- * misalignment), OT_E_LAUNCH. */
+ * misalignment), OT_E_WORKSPACE, OT_E_LAUNCH. */
 OT_API ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t* box_id,
                             const float* pts, const float* next_pts, const uint8_t* status,
                             int32_t n, float* out_boxes, int32_t* out_count, float* out_scale,
-                            void* stream);
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of ot_box_update_scaled for m boxes (0 if invalid). */
+OT_API size_t ot_box_scaled_bytes(int32_t m);
 
 /* ------------------------------------------------------------------------
  * Matching and update phases (Sec. V-A): the predicted scene objects S_t

@@ -229,17 +229,23 @@ ot_err ot_fb_gate(const float* pts, const float* back_pts, const uint8_t* st_fwd
     return OT_OK;
 }
 
+size_t ot_box_scaled_bytes(int32_t m) {
+    if (m < 0 || m > (1 << 24)) return 0;
+    return box_scaled_ws_bytes(m);
+}
+
 ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t* box_id,
                             const float* pts, const float* next_pts, const uint8_t* status,
                             int32_t n, float* out_boxes, int32_t* out_count, float* out_scale,
-                            void* stream) {
-    if (m < 0 || n < 0) return OT_E_INVAL;
+                            void* ws, size_t ws_bytes, void* stream) {
+    if (m < 0 || n < 0 || m > (1 << 24)) return OT_E_INVAL;
     if (m == 0) return OT_OK;
     if (!boxes || !out_boxes || !out_count || !out_scale) return OT_E_INVAL;
     if (n > 0 && (!box_id || !pts || !next_pts || !status)) return OT_E_INVAL;
     if (((uintptr_t)pts | (uintptr_t)next_pts) & 7) return OT_E_INVAL;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < box_scaled_ws_bytes(m)) return OT_E_WORKSPACE;
     if (launch_box_scaled(boxes, m, box_id, pts, next_pts, status, n, out_boxes, out_count,
-                          out_scale, static_cast<hipStream_t>(stream)) != hipSuccess)
+                          out_scale, ws, static_cast<hipStream_t>(stream)) != hipSuccess)
         return OT_E_LAUNCH;
     return OT_OK;
 }

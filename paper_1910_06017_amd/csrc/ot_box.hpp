@@ -474,11 +474,10 @@ __device__ __forceinline__ void box_median(const float* __restrict__ boxes, int 
 // centre moves by the component-wise median displacement of its tracked
 // points and its half-extents scale by the median, over all unordered pairs
 // of those points at distinct first-frame positions, of the ratio of the
-// pair's distance in the second frame to its distance in the first.  One
-// BOX_THREADS workgroup per box; up to SCALE_CAP points are gathered into
-// LDS.  The pair ratios are never stored: the selection visits every pair
-// once per pass, keyed by the squared ratio (monotone in the ratio), and the
-// two middle squared ratios are square-rooted at the end.
+// pair's distance in the second frame to its distance in the first.  Up to
+// SCALE_CAP points per box are gathered.  The pair ratios are never stored:
+// every pass walks the pairs, keyed by the squared ratio (monotone in the
+// ratio), and the two middle squared ratios are square-rooted at the end.
 // ---------------------------------------------------------------------------
 constexpr int SCALE_BAND = 6144;    // keys around the median held for the final selection
 constexpr int SCALE_SAMPLE = 4096;  // sampled pairs (in the band's storage, used first)
@@ -486,10 +485,10 @@ constexpr int SCALE_SAMPLE = 4096;  // sampled pairs (in the band's storage, use
 struct ScaleSmem {
     float4 pu[SCALE_CAP];      // (x, y) in the first frame, (x, y) in the second
     uint32_t band[SCALE_BAND];  // sampled keys, then the keys of the band
-    SelSmem<2> sel;            // displacement medians
+    SelSmem<2> sel;            // displacement medians, the bracket
     SelSmem<1> rsel;           // ratio median
     int32_t count;
-    uint32_t npairs, nbelow, nabove, nsample, nband;
+    uint32_t nsample;
 };
 
 // Key of the pair (a, e): the order-preserving key of the squared distance
@@ -515,8 +514,8 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     return x;
 }
 
-// Slot for each active lane with pred set, reserved with one LDS atomic per
-// wave on *counter (lanes may be inactive; slots follow lane order).
+// Slot for each active lane with pred set, reserved with one atomic per wave
+// on *counter (LDS or global; lanes may be inactive; slots follow lane order).
 __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
     const unsigned long long m = __ballot(pred);
     const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -534,14 +533,14 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
 // circular distance d below c/2 pairs all c points, and for even c the
 // distance c/2 pairs only the first half.  Each thread steps q by BOX_THREADS.
 template <class F>
-__device__ __forceinline__ void visit_pairs(const float4* __restrict__ pu, int c, F&& f) {
+__device__ __forceinline__ void visit_pairs_range(const float4* __restrict__ pu, int c, uint32_t q0,
+                                                  uint32_t q1, F&& f) {
     const uint32_t uc = (uint32_t)c;
-    const uint32_t total = uc * ((uc - 1u) / 2u) + ((uc & 1u) ? 0u : uc / 2u);
-    const uint32_t t = threadIdx.x;
-    if (t >= total) return;
+    const uint32_t t = q0 + threadIdx.x;
+    if (t >= q1) return;
     uint32_t d = t / uc, i = t - d * uc;
     const uint32_t sd = (uint32_t)BOX_THREADS / uc, si = (uint32_t)BOX_THREADS - sd * uc;
-    for (uint32_t q = t; q < total; q += BOX_THREADS) {
+    for (uint32_t q = t; q < q1; q += BOX_THREADS) {
         uint32_t j = i + d + 1u;
         if (j >= uc) j -= uc;
         uint32_t key;
@@ -555,272 +554,391 @@ __device__ __forceinline__ void visit_pairs(const float4* __restrict__ pu, int c
     }
 }
 
-__device__ __forceinline__ void box_scaled(const float* __restrict__ boxes, int b,
-                                           const int32_t* __restrict__ box_id,
-                                           const float* __restrict__ pts,
-                                           const float* __restrict__ next_pts,
-                                           const uint8_t* __restrict__ status, int n,
-                                           float* __restrict__ out_boxes,
-                                           int32_t* __restrict__ out_count,
-                                           float* __restrict__ out_scale, ScaleSmem& sm) {
+__device__ __forceinline__ uint32_t pair_total(int c) {
+    const uint32_t uc = (uint32_t)c;
+    return uc * ((uc - 1u) / 2u) + ((uc & 1u) ? 0u : uc / 2u);
+}
+
+template <class F>
+__device__ __forceinline__ void visit_pairs(const float4* __restrict__ pu, int c, F&& f) {
+    visit_pairs_range(pu, c, 0u, pair_total(c), f);
+}
+
+// ---------------------------------------------------------------------------
+// The scaled update runs in four launches so that the pair passes of one box
+// spread over many compute units (a box of 5000 points has 12.5 M pairs):
+//   prep   (one workgroup per box): gather, displacement medians, the sample
+//          bracket [A, B]; the points, the state and a zero histogram go to
+//          the box's workspace block;
+//   hist   (S workgroups per box, each a slice of the pair walk): pass one,
+//          counts and the histogram of [A, B], merged with global atomics;
+//   band   (S per box): each workgroup reads the merged histogram, finds the
+//          bucket(s) of both middle ranks and appends its slice's keys there;
+//   final  (one per box): the exact selection on the band (or, if a middle
+//          rank fell outside [A, B] or the band overflowed, on all pairs),
+//          then the box.
+// ---------------------------------------------------------------------------
+struct ScaleState {
+    int32_t c;            // kept points; 0 or > SCALE_CAP: the box is done after prep
+    uint32_t A, B;        // bracket keys
+    uint32_t nsample;     // valid sampled pairs (0: no bracket)
+    float mx, my;         // displacement medians
+    uint32_t npairs, nbelow, nabove, kmin, kmax;  // pass one
+    uint32_t nband;       // pass two
+    uint32_t pad[4];
+};
+struct ScaleWs {
+    ScaleState st;
+    uint32_t hist[BOX_NB];
+    uint32_t band[SCALE_BAND];
+    float4 pu[SCALE_CAP];
+};
+
+__device__ __forceinline__ int bracket_shift(uint32_t A, uint32_t B) {
+    const uint32_t span = B - A;
+    return max(0, (span == 0u ? 0 : 32 - __clz((int)span)) - 10);
+}
+
+__device__ __forceinline__ void scaled_write(const float* __restrict__ boxes, int b, int c, float mx,
+                                             float my, float s, float* __restrict__ out_boxes,
+                                             int32_t* __restrict__ out_count,
+                                             float* __restrict__ out_scale) {
+    const float x0 = boxes[4 * b + 0], y0 = boxes[4 * b + 1], x1 = boxes[4 * b + 2], y1 = boxes[4 * b + 3];
+    if (c > 0) {
+        const float cx = 0.5f * (x0 + x1) + mx, cy = 0.5f * (y0 + y1) + my;
+        const float hw = 0.5f * (x1 - x0), hh = 0.5f * (y1 - y0);
+        out_boxes[4 * b + 0] = cx - s * hw;
+        out_boxes[4 * b + 1] = cy - s * hh;
+        out_boxes[4 * b + 2] = cx + s * hw;
+        out_boxes[4 * b + 3] = cy + s * hh;
+    } else {
+        out_boxes[4 * b + 0] = x0;
+        out_boxes[4 * b + 1] = y0;
+        out_boxes[4 * b + 2] = x1;
+        out_boxes[4 * b + 3] = y1;
+    }
+    out_count[b] = c;
+    out_scale[b] = s;
+}
+
+// Phase 1.  The sample: at most SCALE_SAMPLE pairs drawn by a hashed index
+// (neighbouring pairs of the walk share their points, so an evenly strided
+// sample is far from random); A and B are its quantiles 14 standard
+// deviations of the sample median's rank either side of the median.
+__device__ __forceinline__ void scaled_prep(const float* __restrict__ boxes, int b,
+                                            const int32_t* __restrict__ box_id,
+                                            const float* __restrict__ pts,
+                                            const float* __restrict__ next_pts,
+                                            const uint8_t* __restrict__ status, int n,
+                                            float* __restrict__ out_boxes,
+                                            int32_t* __restrict__ out_count,
+                                            float* __restrict__ out_scale, ScaleWs* __restrict__ ws,
+                                            ScaleSmem& sm) {
     const int tid = threadIdx.x, lane = tid & 63;
     if (tid == 0) {
         sm.count = 0;
-        sm.npairs = 0u;
-        sm.nbelow = 0u;
-        sm.nabove = 0u;
         sm.nsample = 0u;
-        sm.nband = 0u;
     }
     sel_init(sm.sel);
-    sel_init(sm.rsel);
     __syncthreads();
     box_gather<SCALE_CAP>(b, box_id, pts, next_pts, status, n, sm.count, sm.sel,
                           [&](int k, float2 p, float2 q) { sm.pu[k] = make_float4(p.x, p.y, q.x, q.y); });
     __syncthreads();
     const int c = sm.count;
-    if (c > SCALE_CAP) {
-        // too many points for the pair pass: no result
+    ScaleState& st = ws->st;
+    for (int e = tid; e < BOX_NB; e += BOX_THREADS) ws->hist[e] = 0u;
+    if (c > SCALE_CAP || c == 0) {
+        // too many points for the pair passes (no result), or none
         if (tid == 0) {
-            const float nan = __builtin_nanf("");
-            for (int k = 0; k < 4; ++k) out_boxes[4 * b + k] = nan;
-            out_count[b] = c;
-            out_scale[b] = nan;
+            st.c = c;
+            if (c == 0) {
+                scaled_write(boxes, b, 0, 0.0f, 0.0f, 1.0f, out_boxes, out_count, out_scale);
+            } else {
+                const float nan = __builtin_nanf("");
+                for (int k = 0; k < 4; ++k) out_boxes[4 * b + k] = nan;
+                out_count[b] = c;
+                out_scale[b] = nan;
+            }
         }
         return;
     }
-    float mx = 0.0f, my = 0.0f, s = 1.0f;
-    if (c > 0) {
-        if (tid < 2) {
-            sm.sel.rank[tid][0] = (uint32_t)((c - 1) / 2);
-            sm.sel.rank[tid][1] = (uint32_t)(c / 2);
+    for (int i = tid; i < c; i += BOX_THREADS) ws->pu[i] = sm.pu[i];
+    if (tid < 2) {
+        sm.sel.rank[tid][0] = (uint32_t)((c - 1) / 2);
+        sm.sel.rank[tid][1] = (uint32_t)(c / 2);
+    }
+    select_ranks<2>(sm.sel, true, [&](auto&& f) {
+        for (int i = tid; i < c; i += BOX_THREADS) {
+            const float4 p = sm.pu[i];
+            const float v[2] = {p.z - p.x, p.w - p.y};
+            f(v);
         }
-        select_ranks<2>(sm.sel, true, [&](auto&& f) {
-            for (int i = tid; i < c; i += BOX_THREADS) {
-                const float4 p = sm.pu[i];
-                const float v[2] = {p.z - p.x, p.w - p.y};
+    });
+    const float mx = 0.5f * (key2f(sm.sel.res[0][0]) + key2f(sm.sel.res[0][1]));
+    const float my = 0.5f * (key2f(sm.sel.res[1][0]) + key2f(sm.sel.res[1][1]));
+    const uint32_t uc = (uint32_t)c, total = pair_total(c);
+    const uint32_t ns = min(total, (uint32_t)SCALE_SAMPLE);
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (uint32_t t = tid; t < ns; t += BOX_THREADS) {
+        const uint32_t q = (uint32_t)(((uint64_t)mix32(t) * total) >> 32), d = q / uc, i = q - d * uc;
+        uint32_t j = i + d + 1u;
+        if (j >= uc) j -= uc;
+        uint32_t key;
+        const bool ok = pair_key(sm.pu[i], sm.pu[j], key);
+        const uint32_t slot = wave_append(ok, &sm.nsample);
+        if (ok) {
+            sm.band[slot] = key;
+            lo = min(lo, key);
+            hi = max(hi, key);
+        }
+    }
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    // the two bracket ranks are far apart: each is its own (equal-rank)
+    // target, as two axes of one selection over the sample
+    if (tid < 2) {
+        sm.sel.klo[tid] = 0xFFFFFFFFu;
+        sm.sel.khi[tid] = 0u;
+    }
+    __syncthreads();
+    if (lane == 0 && lo <= hi) {
+        for (int a = 0; a < 2; ++a) {
+            atomicMin(&sm.sel.klo[a], lo);
+            atomicMax(&sm.sel.khi[a], hi);
+        }
+    }
+    __syncthreads();
+    const uint32_t msmp = sm.nsample;
+    uint32_t A = 0u, B = 0xFFFFFFFFu;
+    if (msmp > 0u) {
+        const uint32_t h = 2u + (uint32_t)ceilf(7.0f * sqrtf((float)msmp));
+        const uint32_t rc = (msmp - 1u) / 2u;
+        if (tid == 0) {
+            sm.sel.rank[0][0] = sm.sel.rank[0][1] = rc > h ? rc - h : 0u;
+            sm.sel.rank[1][0] = sm.sel.rank[1][1] = min(msmp - 1u, msmp / 2u + h);
+        }
+        __syncthreads();
+        select_ranks<2>(sm.sel, false, [&](auto&& f) {
+            for (uint32_t t = tid; t < msmp; t += BOX_THREADS) {
+                const float k = key2f(sm.band[t]);
+                const float v[2] = {k, k};
                 f(v);
             }
         });
-        mx = 0.5f * (key2f(sm.sel.res[0][0]) + key2f(sm.sel.res[0][1]));
-        my = 0.5f * (key2f(sm.sel.res[1][0]) + key2f(sm.sel.res[1][1]));
-        // Ratio median, exact, in two passes over the pairs in the common
-        // case.  (1) A fixed pseudo-random sample of at most SCALE_SAMPLE
-        // pairs gives two sample quantiles A <= B around its median, 14
-        // standard deviations of the sample median's rank away on each
-        // side.  (2) Pass one counts all pairs, those below A and above B,
-        // and histograms the keys in [A, B] into BOX_NB buckets.  (3) The
-        // histogram names the bucket(s) holding both middle ranks; pass two
-        // keeps the keys of those buckets and the exact selection runs on
-        // them alone (on all pairs of that key range if they do not fit).
-        // If a middle rank lies outside [A, B], the exact selection runs on
-        // all pairs.
-        const uint32_t uc = (uint32_t)c;
-        const uint32_t total = uc * ((uc - 1u) / 2u) + ((uc & 1u) ? 0u : uc / 2u);
-        // pairs drawn by a hashed index: neighbouring pairs of the walk
-        // share their points, so an evenly strided sample is far from random
-        const uint32_t ns = min(total, (uint32_t)SCALE_SAMPLE);
-        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-        for (uint32_t t = tid; t < ns; t += BOX_THREADS) {
-            const uint32_t q = (uint32_t)(((uint64_t)mix32(t) * total) >> 32), d = q / uc, i = q - d * uc;
-            uint32_t j = i + d + 1u;
-            if (j >= uc) j -= uc;
-            uint32_t key;
-            const bool ok = pair_key(sm.pu[i], sm.pu[j], key);
-            const uint32_t slot = wave_append(ok, &sm.nsample);
-            if (ok) {
-                sm.band[slot] = key;
-                lo = min(lo, key);
-                hi = max(hi, key);
+        A = sm.sel.res[0][0];
+        B = sm.sel.res[1][0];
+    }
+    if (tid == 0) {
+        st.c = c;
+        st.A = A;
+        st.B = B;
+        st.nsample = msmp;
+        st.mx = mx;
+        st.my = my;
+        st.npairs = st.nbelow = st.nabove = st.nband = 0u;
+        st.kmin = 0xFFFFFFFFu;
+        st.kmax = 0u;
+    }
+}
+
+// Loads the box's points into LDS (c <= SCALE_CAP).
+__device__ __forceinline__ void load_points(const ScaleWs* __restrict__ ws, int c, float4* pu) {
+    for (int i = threadIdx.x; i < c; i += BOX_THREADS) pu[i] = ws->pu[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void slice_range(int c, int slice, int S, uint32_t& q0, uint32_t& q1) {
+    const uint64_t total = pair_total(c);
+    q0 = (uint32_t)(total * (uint64_t)slice / (uint64_t)S);
+    q1 = (uint32_t)(total * (uint64_t)(slice + 1) / (uint64_t)S);
+}
+
+struct SliceSmem {
+    float4 pu[SCALE_CAP];
+    uint32_t hist[BOX_NB];
+    uint32_t dec[8];  // the band decision: inside, klo, khi
+};
+
+// Phase 2: pass one over a slice of the pairs.
+__device__ __forceinline__ void scaled_hist(ScaleWs* __restrict__ ws, int slice, int S, SliceSmem& sm) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    ScaleState& st = ws->st;
+    const int c = st.c;
+    if (c <= 0 || c > SCALE_CAP) return;
+    const uint32_t A = st.A, B = st.B;
+    const int sh = bracket_shift(A, B);
+    for (int e = tid; e < BOX_NB; e += BOX_THREADS) sm.hist[e] = 0u;
+    load_points(ws, c, sm.pu);
+    uint32_t q0, q1;
+    slice_range(c, slice, S, q0, q1);
+    uint32_t np = 0u, nbelow = 0u, nabove = 0u, lo = 0xFFFFFFFFu, hi = 0u, run = 0u;
+    int cur = 0;
+    visit_pairs_range(sm.pu, c, q0, q1, [&](uint32_t key) {
+        ++np;
+        lo = min(lo, key);
+        hi = max(hi, key);
+        if (key < A) {
+            ++nbelow;
+        } else if (key > B) {
+            ++nabove;
+        } else {
+            // runs of equal buckets are added once
+            const int bu = (int)((key - A) >> sh);
+            if (bu != cur) {
+                if (run) atomicAdd(&sm.hist[cur], run);
+                cur = bu;
+                run = 0u;
             }
+            ++run;
         }
-        lo = wave_min_u32(lo);
-        hi = wave_max_u32(hi);
-        // the two bracket ranks are far apart: each is its own (equal-rank)
-        // target, as two axes of one selection over the sample
-        if (tid < 2) {
-            sm.sel.klo[tid] = 0xFFFFFFFFu;
-            sm.sel.khi[tid] = 0u;
-        }
-        __syncthreads();
-        if (lane == 0 && lo <= hi) {
-            for (int a = 0; a < 2; ++a) {
-                atomicMin(&sm.sel.klo[a], lo);
-                atomicMax(&sm.sel.khi[a], hi);
+    });
+    if (run) atomicAdd(&sm.hist[cur], run);
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    np = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(np), 63);
+    nbelow = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nbelow), 63);
+    nabove = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nabove), 63);
+    if (lane == 0 && np > 0u) {
+        atomicAdd(&st.npairs, np);
+        atomicAdd(&st.nbelow, nbelow);
+        atomicAdd(&st.nabove, nabove);
+        atomicMin(&st.kmin, lo);
+        atomicMax(&st.kmax, hi);
+    }
+    __syncthreads();
+    for (int e = tid; e < BOX_NB; e += BOX_THREADS) {
+        const uint32_t v = sm.hist[e];
+        if (v) atomicAdd(&ws->hist[e], v);
+    }
+}
+
+// The bucket(s) of both middle ranks among the keys in [A, B], by wave 0:
+// dec = {inside, first key, last key of those buckets, keys below them}.
+__device__ __forceinline__ void scaled_decide(const ScaleWs* __restrict__ ws, uint32_t* dec) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const ScaleState& st = ws->st;
+    const uint32_t npairs = st.npairs, below = st.nbelow, above = st.nabove;
+    const uint32_t A = st.A, B = st.B;
+    const int sh = bracket_shift(A, B);
+    const uint32_t t0 = npairs > 0u ? (npairs - 1u) / 2u : 0u, t1 = npairs / 2u;
+    const bool inside = npairs > 0u && st.nsample > 0u && below <= t0 && t1 < npairs - above;
+    if (tid < 64) {
+        if (!inside) {
+            if (lane == 0) dec[0] = 0u;
+        } else {
+            uint32_t cnt[16];
+            uint32_t tot = 0u;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                cnt[j] = ws->hist[16 * lane + j];
+                tot += cnt[j];
             }
-        }
-        __syncthreads();
-        const uint32_t msmp = sm.nsample;
-        uint32_t A = 0u, B = 0xFFFFFFFFu;
-        if (msmp > 0u) {
-            const uint32_t h = 2u + (uint32_t)ceilf(7.0f * sqrtf((float)msmp));
-            const uint32_t rc = (msmp - 1u) / 2u;
-            if (tid == 0) {
-                sm.sel.rank[0][0] = sm.sel.rank[0][1] = rc > h ? rc - h : 0u;
-                sm.sel.rank[1][0] = sm.sel.rank[1][1] = min(msmp - 1u, msmp / 2u + h);
-            }
-            __syncthreads();
-            select_ranks<2>(sm.sel, false, [&](auto&& f) {
-                for (uint32_t t = tid; t < msmp; t += BOX_THREADS) {
-                    const float k = key2f(sm.band[t]);
-                    const float v[2] = {k, k};
-                    f(v);
-                }
-            });
-            A = sm.sel.res[0][0];
-            B = sm.sel.res[1][0];
-        }
-        // pass one: counts and the histogram of [A, B] (runs of equal
-        // buckets added once, as in the selection)
-        const uint32_t span = B - A;
-        const int sh = max(0, (span == 0u ? 0 : 32 - __clz((int)span)) - 10);
-        uint32_t np = 0u, nbelow = 0u, nabove = 0u;
-        int cur = 0;
-        uint32_t run = 0u;
-        lo = 0xFFFFFFFFu;
-        hi = 0u;
-        uint32_t* hist = sm.rsel.hist[0];
-        visit_pairs(sm.pu, c, [&](uint32_t key) {
-            ++np;
-            lo = min(lo, key);
-            hi = max(hi, key);
-            if (key < A) {
-                ++nbelow;
-            } else if (key > B) {
-                ++nabove;
-            } else {
-                const int bu = (int)((key - A) >> sh);
-                if (bu != cur) {
-                    if (run) atomicAdd(&hist[cur], run);
-                    cur = bu;
-                    run = 0u;
-                }
-                ++run;
-            }
-        });
-        if (run) atomicAdd(&hist[cur], run);
-        lo = wave_min_u32(lo);
-        hi = wave_max_u32(hi);
-        np = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(np), 63);
-        nbelow = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nbelow), 63);
-        nabove = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nabove), 63);
-        if (tid == 0) {
-            sm.rsel.klo[0] = 0xFFFFFFFFu;
-            sm.rsel.khi[0] = 0u;
-        }
-        __syncthreads();
-        if (lane == 0 && np > 0u) {
-            atomicMin(&sm.rsel.klo[0], lo);
-            atomicMax(&sm.rsel.khi[0], hi);
-            atomicAdd(&sm.npairs, np);
-            atomicAdd(&sm.nbelow, nbelow);
-            atomicAdd(&sm.nabove, nabove);
-        }
-        __syncthreads();
-        const uint32_t npairs = sm.npairs;
-        if (npairs > 0u) {
-            const uint32_t t0 = (npairs - 1u) / 2u, t1 = npairs / 2u;
-            const uint32_t below = sm.nbelow, above = sm.nabove;
-            const bool inside = msmp > 0u && below <= t0 && t1 < npairs - above;
-            // scan: the buckets of both middle ranks among the keys in [A, B]
-            if (inside && tid < 64) {
-                uint32_t cnt[16];
-                uint32_t tot = 0u;
+            const uint32_t incl = wave_incl_scan_u32(tot), excl = incl - tot;
+            int bk[2];
+            uint32_t base0 = 0u;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const uint32_t k = (t == 0 ? t0 : t1) - below;
+                const bool mine = k >= excl && k < incl;
+                int bin = 16 * lane;
+                uint32_t acc = excl, bse = excl;
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    cnt[j] = hist[16 * lane + j];
-                    tot += cnt[j];
-                }
-                const uint32_t incl = wave_incl_scan_u32(tot), excl = incl - tot;
-                int bk[2];
-                uint32_t base[2];
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const uint32_t k = (t == 0 ? t0 : t1) - below;
-                    const bool mine = k >= excl && k < incl;
-                    int bin = 16 * lane;
-                    uint32_t acc = excl, bse = excl;
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) {
-                        if (k >= acc + cnt[j]) {
-                            bin = 16 * lane + j + 1;
-                            bse = acc + cnt[j];
-                        }
-                        acc += cnt[j];
+                    if (k >= acc + cnt[j]) {
+                        bin = 16 * lane + j + 1;
+                        bse = acc + cnt[j];
                     }
-                    const int src = __ffsll((unsigned long long)__ballot(mine)) - 1;
-                    bk[t] = __builtin_amdgcn_readlane(bin, src);
-                    base[t] = (uint32_t)__builtin_amdgcn_readlane((int)bse, src);
+                    acc += cnt[j];
                 }
-                if (lane == 0) {
-                    // keys of buckets bk[0] .. bk[1] (at most two adjacent ones)
-                    const uint32_t klo = A + ((uint32_t)bk[0] << sh);
-                    const uint64_t khi64 = (uint64_t)A + ((uint64_t)(bk[1] + 1) << sh) - 1u;
-                    sm.rsel.klo[0] = klo;
-                    sm.rsel.khi[0] = (uint32_t)min(khi64, (uint64_t)B);
-                    sm.rsel.rank[0][0] = t0 - below - base[0];
-                    sm.rsel.rank[0][1] = t1 - below - base[0];
-                }
+                const int src = __ffsll((unsigned long long)__ballot(mine)) - 1;
+                bk[t] = __builtin_amdgcn_readlane(bin, src);
+                if (t == 0) base0 = (uint32_t)__builtin_amdgcn_readlane((int)bse, src);
             }
-            if (!inside && tid == 0) {
+            if (lane == 0) {
+                const uint64_t khi64 = (uint64_t)A + ((uint64_t)(bk[1] + 1) << sh) - 1u;
+                dec[0] = 1u;
+                dec[1] = A + ((uint32_t)bk[0] << sh);
+                dec[2] = (uint32_t)min(khi64, (uint64_t)B);
+                dec[3] = below + base0;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Phase 3: pass two over a slice: the keys of the target buckets.
+__device__ __forceinline__ void scaled_band(ScaleWs* __restrict__ ws, int slice, int S, SliceSmem& sm) {
+    ScaleState& st = ws->st;
+    const int c = st.c;
+    if (c <= 0 || c > SCALE_CAP) return;
+    scaled_decide(ws, sm.dec);
+    if (sm.dec[0] == 0u) return;
+    const uint32_t bl = sm.dec[1], bh = sm.dec[2];
+    load_points(ws, c, sm.pu);
+    uint32_t q0, q1;
+    slice_range(c, slice, S, q0, q1);
+    visit_pairs_range(sm.pu, c, q0, q1, [&](uint32_t key) {
+        const bool in = key >= bl && key <= bh;
+        const uint32_t slot = wave_append(in, &st.nband);
+        if (in && slot < (uint32_t)SCALE_BAND) ws->band[slot] = key;
+    });
+}
+
+// Phase 4: the ratio median and the box.
+__device__ __forceinline__ void scaled_final(const float* __restrict__ boxes, int b,
+                                             float* __restrict__ out_boxes,
+                                             int32_t* __restrict__ out_count,
+                                             float* __restrict__ out_scale,
+                                             const ScaleWs* __restrict__ ws, ScaleSmem& sm) {
+    const int tid = threadIdx.x;
+    const ScaleState& st = ws->st;
+    const int c = st.c;
+    if (c <= 0 || c > SCALE_CAP) return;
+    const uint32_t npairs = st.npairs;
+    float s = 1.0f;
+    if (npairs > 0u) {
+        sel_init(sm.rsel);
+        uint32_t* dec = reinterpret_cast<uint32_t*>(&sm.sel.res[0][0]);
+        scaled_decide(ws, dec);
+        const uint32_t t0 = (npairs - 1u) / 2u, t1 = npairs / 2u;
+        const uint32_t nband = st.nband;
+        const bool fast = dec[0] != 0u && nband <= (uint32_t)SCALE_BAND;
+        if (tid == 0) {
+            if (fast) {
+                sm.rsel.klo[0] = dec[1];
+                sm.rsel.khi[0] = dec[2];
+                sm.rsel.rank[0][0] = t0 - dec[3];
+                sm.rsel.rank[0][1] = t1 - dec[3];
+            } else {
+                sm.rsel.klo[0] = st.kmin;
+                sm.rsel.khi[0] = st.kmax;
                 sm.rsel.rank[0][0] = t0;
                 sm.rsel.rank[0][1] = t1;
             }
-            __syncthreads();
-            for (int e = tid; e < BOX_NB; e += BOX_THREADS) hist[e] = 0u;
-            uint32_t bl = 0u, bh = 0u, nbd = 0u;
-            if (inside) {
-                // pass two: the keys of the target buckets
-                bl = sm.rsel.klo[0];
-                bh = sm.rsel.khi[0];
-                visit_pairs(sm.pu, c, [&](uint32_t key) {
-                    const bool in = key >= bl && key <= bh;
-                    const uint32_t slot = wave_append(in, &sm.nband);
-                    if (in && slot < (uint32_t)SCALE_BAND) sm.band[slot] = key;
-                });
-            }
-            __syncthreads();
-            nbd = sm.nband;
-            // key-linear first rounds: ratio outliers would squeeze the bulk
-            // into a few value-linear buckets
-            if (inside && nbd <= (uint32_t)SCALE_BAND) {
-                select_ranks<1>(sm.rsel, false, [&](auto&& f) {
-                    for (uint32_t t = tid; t < nbd; t += BOX_THREADS) {
-                        const float v[1] = {key2f(sm.band[t])};
-                        f(v);
-                    }
-                });
-            } else {
-                // all pairs, restricted to the range in rsel (the target
-                // buckets, or every key)
-                select_ranks<1>(sm.rsel, false, [&](auto&& f) {
-                    visit_pairs(sm.pu, c, [&](uint32_t key) {
-                        const float v[1] = {key2f(key)};
-                        f(v);
-                    });
-                });
-            }
-            s = 0.5f * (__builtin_sqrtf(key2f(sm.rsel.res[0][0])) + __builtin_sqrtf(key2f(sm.rsel.res[0][1])));
         }
-    }
-    if (tid == 0) {
-        const float x0 = boxes[4 * b + 0], y0 = boxes[4 * b + 1], x1 = boxes[4 * b + 2], y1 = boxes[4 * b + 3];
-        if (c > 0) {
-            const float cx = 0.5f * (x0 + x1) + mx, cy = 0.5f * (y0 + y1) + my;
-            const float hw = 0.5f * (x1 - x0), hh = 0.5f * (y1 - y0);
-            out_boxes[4 * b + 0] = cx - s * hw;
-            out_boxes[4 * b + 1] = cy - s * hh;
-            out_boxes[4 * b + 2] = cx + s * hw;
-            out_boxes[4 * b + 3] = cy + s * hh;
+        // key-linear first rounds: ratio outliers would squeeze the bulk
+        // into a few value-linear buckets
+        if (fast) {
+            for (uint32_t t = tid; t < nband; t += BOX_THREADS) sm.band[t] = ws->band[t];
+            __syncthreads();
+            select_ranks<1>(sm.rsel, false, [&](auto&& f) {
+                for (uint32_t t = tid; t < nband; t += BOX_THREADS) {
+                    const float v[1] = {key2f(sm.band[t])};
+                    f(v);
+                }
+            });
         } else {
-            out_boxes[4 * b + 0] = x0;
-            out_boxes[4 * b + 1] = y0;
-            out_boxes[4 * b + 2] = x1;
-            out_boxes[4 * b + 3] = y1;
+            load_points(ws, c, sm.pu);
+            select_ranks<1>(sm.rsel, false, [&](auto&& f) {
+                visit_pairs(sm.pu, c, [&](uint32_t key) {
+                    const float v[1] = {key2f(key)};
+                    f(v);
+                });
+            });
         }
-        out_count[b] = c;
-        out_scale[b] = s;
+        s = 0.5f * (__builtin_sqrtf(key2f(sm.rsel.res[0][0])) + __builtin_sqrtf(key2f(sm.rsel.res[0][1])));
     }
+    if (tid == 0) scaled_write(boxes, b, c, st.mx, st.my, s, out_boxes, out_count, out_scale);
 }
 
 // Forward-backward gate (Kalal et al. 2010): a point keeps status 1 when it

@@ -102,23 +102,54 @@ hipError_t launch_box(const float* boxes, int m, const int32_t* box_id, const fl
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(BOX_THREADS) void k_box_scaled(const float* __restrict__ boxes,
-                                                            const int32_t* __restrict__ box_id,
-                                                            const float* __restrict__ pts,
-                                                            const float* __restrict__ next_pts,
-                                                            const uint8_t* __restrict__ status, int n,
-                                                            float* __restrict__ out_boxes,
-                                                            int32_t* __restrict__ out_count,
-                                                            float* __restrict__ out_scale) {
+__global__ __launch_bounds__(BOX_THREADS) void k_scaled_prep(const float* __restrict__ boxes,
+                                                             const int32_t* __restrict__ box_id,
+                                                             const float* __restrict__ pts,
+                                                             const float* __restrict__ next_pts,
+                                                             const uint8_t* __restrict__ status, int n,
+                                                             float* __restrict__ out_boxes,
+                                                             int32_t* __restrict__ out_count,
+                                                             float* __restrict__ out_scale,
+                                                             ScaleWs* __restrict__ ws) {
     __shared__ ScaleSmem sm;
-    box_scaled(boxes, blockIdx.x, box_id, pts, next_pts, status, n, out_boxes, out_count, out_scale, sm);
+    scaled_prep(boxes, blockIdx.x, box_id, pts, next_pts, status, n, out_boxes, out_count, out_scale,
+                ws + blockIdx.x, sm);
 }
+
+__global__ __launch_bounds__(BOX_THREADS) void k_scaled_hist(ScaleWs* __restrict__ ws, int S) {
+    __shared__ SliceSmem sm;
+    scaled_hist(ws + blockIdx.x / S, (int)(blockIdx.x % S), S, sm);
+}
+
+__global__ __launch_bounds__(BOX_THREADS) void k_scaled_band(ScaleWs* __restrict__ ws, int S) {
+    __shared__ SliceSmem sm;
+    scaled_band(ws + blockIdx.x / S, (int)(blockIdx.x % S), S, sm);
+}
+
+__global__ __launch_bounds__(BOX_THREADS) void k_scaled_final(const float* __restrict__ boxes,
+                                                              float* __restrict__ out_boxes,
+                                                              int32_t* __restrict__ out_count,
+                                                              float* __restrict__ out_scale,
+                                                              const ScaleWs* __restrict__ ws) {
+    __shared__ ScaleSmem sm;
+    scaled_final(boxes, blockIdx.x, out_boxes, out_count, out_scale, ws + blockIdx.x, sm);
+}
+
+size_t box_scaled_ws_bytes(int m) { return (size_t)m * sizeof(ScaleWs); }
+
+int box_scaled_slices(int m) { return m >= 256 ? 1 : min(64, 256 / m); }
 
 hipError_t launch_box_scaled(const float* boxes, int m, const int32_t* box_id, const float* pts,
                              const float* next_pts, const uint8_t* status, int n, float* out_boxes,
-                             int32_t* out_count, float* out_scale, hipStream_t stream) {
-    hipLaunchKernelGGL(k_box_scaled, dim3(m), dim3(BOX_THREADS), 0, stream, boxes, box_id, pts,
-                       next_pts, status, n, out_boxes, out_count, out_scale);
+                             int32_t* out_count, float* out_scale, void* ws, hipStream_t stream) {
+    ScaleWs* w = static_cast<ScaleWs*>(ws);
+    const int S = box_scaled_slices(m);
+    hipLaunchKernelGGL(k_scaled_prep, dim3(m), dim3(BOX_THREADS), 0, stream, boxes, box_id, pts,
+                       next_pts, status, n, out_boxes, out_count, out_scale, w);
+    hipLaunchKernelGGL(k_scaled_hist, dim3(m * S), dim3(BOX_THREADS), 0, stream, w, S);
+    hipLaunchKernelGGL(k_scaled_band, dim3(m * S), dim3(BOX_THREADS), 0, stream, w, S);
+    hipLaunchKernelGGL(k_scaled_final, dim3(m), dim3(BOX_THREADS), 0, stream, boxes, out_boxes,
+                       out_count, out_scale, w);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 
 # Every symbol the header declares.
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
-           "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled",
+           "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled", "ot_box_scaled_bytes",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
            "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_box_mean_flow",
            "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_strerror", "ot_version"]
@@ -104,8 +104,10 @@ def lib():
         L.ot_box_update.restype = i32
         L.ot_fb_gate.argtypes = [P, P, P, P, i32, f32, P, P, P]
         L.ot_fb_gate.restype = i32
-        L.ot_box_update_scaled.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P]
+        L.ot_box_update_scaled.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P, sz, P]
         L.ot_box_update_scaled.restype = i32
+        L.ot_box_scaled_bytes.argtypes = [i32]
+        L.ot_box_scaled_bytes.restype = sz
         L.ot_tvl1_default_params.argtypes = [C.POINTER(OtTvl1Params)]
         L.ot_tvl1_default_params.restype = None
         L.ot_tvl1_bytes.argtypes = [i32, i32]
@@ -311,7 +313,13 @@ def fb_gate(pts, back_pts, st_fwd, st_bwd, fb_max: float, want_err: bool = True,
     return st, fe
 
 
-def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, stream=None):
+def box_scaled_workspace(m: int, device="cuda"):
+    """Workspace for box_update_scaled on m boxes."""
+    torch = _torch()
+    return torch.empty(max(1, int(lib().ot_box_scaled_bytes(m))), dtype=torch.uint8, device=device)
+
+
+def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, ws=None, stream=None):
     """Median-Flow box update: the centre moves by the median displacement
     and the half-extents scale by the median pairwise distance ratio.
     Returns (out_boxes (m,4), out_count (m,), out_scale (m,))."""
@@ -331,9 +339,12 @@ def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, stream=Non
         os_ = torch.empty(m, dtype=torch.float32, device=boxes.device)
     else:
         ob, oc, os_ = out
+    if ws is None:
+        ws = box_scaled_workspace(m, boxes.device)
     check(lib().ot_box_update_scaled(_ptr(boxes), m, _ptr(box_id), _ptr(pts), _ptr(next_pts),
-                                     _ptr(status), n, _ptr(ob), _ptr(oc), _ptr(os_),
-                                     _stream_handle(stream)), "ot_box_update_scaled")
+                                     _ptr(status), n, _ptr(ob), _ptr(oc), _ptr(os_), _ptr(ws),
+                                     ws.numel() * ws.element_size(), _stream_handle(stream)),
+          "ot_box_update_scaled")
     return ob, oc, os_
 
 

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 21
+    assert len(syms) == 22
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -172,13 +172,20 @@ def test_fb_gate_validation(L):
 
 def test_box_scaled_validation(L):
     E = ops_err("OT_E_INVAL")
+    Wk = ops_err("OT_E_WORKSPACE")
     u = L.ot_box_update_scaled
-    assert u(FAKE, -1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None) == E
-    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, -5, FAKE, FAKE, FAKE, None) == E
-    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None, None) == E  # no scale output
-    assert u(FAKE, 3, None, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None) == E
-    assert u(FAKE, 3, FAKE, FAKE, FAKE + 4, FAKE, 5, FAKE, FAKE, FAKE, None) == E  # next_pts not 8-aligned
-    assert u(None, 0, None, None, None, None, 5, None, None, None, None) == 0
+    need = L.ot_box_scaled_bytes(3)
+    assert need > 0 and L.ot_box_scaled_bytes(6) == 2 * need and L.ot_box_scaled_bytes(-1) == 0
+    ws = FAKE + (1 << 20)
+    assert u(FAKE, -1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, ws, need, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, -5, FAKE, FAKE, FAKE, ws, need, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None, ws, need, None) == E  # no scale output
+    assert u(FAKE, 3, None, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, ws, need, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE + 4, FAKE, 5, FAKE, FAKE, FAKE, ws, need, None) == E  # misaligned
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, ws, need - 1, None) == Wk
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, ws + 16, need, None) == Wk
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None, need, None) == Wk
+    assert u(None, 0, None, None, None, None, 5, None, None, None, None, 0, None) == 0
 
 
 def test_scale_cap_matches_header():
