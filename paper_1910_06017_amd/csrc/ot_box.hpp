@@ -567,9 +567,9 @@ __device__ __forceinline__ void visit_pairs(const float4* __restrict__ pu, int c
 // ---------------------------------------------------------------------------
 // The scaled update runs in four launches so that the pair passes of one box
 // spread over many compute units (a box of 5000 points has 12.5 M pairs):
-//   prep   (one workgroup per box): gather, displacement medians, the sample
-//          bracket [A, B]; the points, the state and a zero histogram go to
-//          the box's workspace block;
+//   prep   (two workgroups per box): gather; one selects the displacement
+//          medians, the other draws the sample bracket [A, B] and writes the
+//          points, the state and a zero histogram to the box's workspace;
 //   hist   (S workgroups per box, each a slice of the pair walk): pass one,
 //          counts and the histogram of [A, B], merged with global atomics;
 //   band   (S per box): each workgroup reads the merged histogram, finds the
@@ -621,11 +621,13 @@ __device__ __forceinline__ void scaled_write(const float* __restrict__ boxes, in
     out_scale[b] = s;
 }
 
-// Phase 1.  The sample: at most SCALE_SAMPLE pairs drawn by a hashed index
-// (neighbouring pairs of the walk share their points, so an evenly strided
-// sample is far from random); A and B are its quantiles 14 standard
-// deviations of the sample median's rank either side of the median.
-__device__ __forceinline__ void scaled_prep(const float* __restrict__ boxes, int b,
+// Phase 1, two workgroups per box that both gather the box's points.  Role 0
+// keeps the points and draws the sample: at most SCALE_SAMPLE pairs drawn by
+// a hashed index (neighbouring pairs of the walk share their points, so an
+// evenly strided sample is far from random); A and B are its quantiles 14
+// standard deviations of the sample median's rank either side of the median.
+// Role 1 selects the displacement medians at the same time.
+__device__ __forceinline__ void scaled_prep(const float* __restrict__ boxes, int b, int role,
                                             const int32_t* __restrict__ box_id,
                                             const float* __restrict__ pts,
                                             const float* __restrict__ next_pts,
@@ -646,6 +648,25 @@ __device__ __forceinline__ void scaled_prep(const float* __restrict__ boxes, int
     __syncthreads();
     const int c = sm.count;
     ScaleState& st = ws->st;
+    if (role == 1) {
+        if (c > SCALE_CAP || c == 0) return;
+        if (tid < 2) {
+            sm.sel.rank[tid][0] = (uint32_t)((c - 1) / 2);
+            sm.sel.rank[tid][1] = (uint32_t)(c / 2);
+        }
+        select_ranks<2>(sm.sel, true, [&](auto&& f) {
+            for (int i = tid; i < c; i += BOX_THREADS) {
+                const float4 p = sm.pu[i];
+                const float v[2] = {p.z - p.x, p.w - p.y};
+                f(v);
+            }
+        });
+        if (tid == 0) {
+            st.mx = 0.5f * (key2f(sm.sel.res[0][0]) + key2f(sm.sel.res[0][1]));
+            st.my = 0.5f * (key2f(sm.sel.res[1][0]) + key2f(sm.sel.res[1][1]));
+        }
+        return;
+    }
     for (int e = tid; e < BOX_NB; e += BOX_THREADS) ws->hist[e] = 0u;
     if (c > SCALE_CAP || c == 0) {
         // too many points for the pair passes (no result), or none
@@ -663,19 +684,6 @@ __device__ __forceinline__ void scaled_prep(const float* __restrict__ boxes, int
         return;
     }
     for (int i = tid; i < c; i += BOX_THREADS) ws->pu[i] = sm.pu[i];
-    if (tid < 2) {
-        sm.sel.rank[tid][0] = (uint32_t)((c - 1) / 2);
-        sm.sel.rank[tid][1] = (uint32_t)(c / 2);
-    }
-    select_ranks<2>(sm.sel, true, [&](auto&& f) {
-        for (int i = tid; i < c; i += BOX_THREADS) {
-            const float4 p = sm.pu[i];
-            const float v[2] = {p.z - p.x, p.w - p.y};
-            f(v);
-        }
-    });
-    const float mx = 0.5f * (key2f(sm.sel.res[0][0]) + key2f(sm.sel.res[0][1]));
-    const float my = 0.5f * (key2f(sm.sel.res[1][0]) + key2f(sm.sel.res[1][1]));
     const uint32_t uc = (uint32_t)c, total = pair_total(c);
     const uint32_t ns = min(total, (uint32_t)SCALE_SAMPLE);
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
@@ -733,8 +741,6 @@ __device__ __forceinline__ void scaled_prep(const float* __restrict__ boxes, int
         st.A = A;
         st.B = B;
         st.nsample = msmp;
-        st.mx = mx;
-        st.my = my;
         st.npairs = st.nbelow = st.nabove = st.nband = 0u;
         st.kmin = 0xFFFFFFFFu;
         st.kmax = 0u;
@@ -756,7 +762,8 @@ __device__ __forceinline__ void slice_range(int c, int slice, int S, uint32_t& q
 struct SliceSmem {
     float4 pu[SCALE_CAP];
     uint32_t hist[BOX_NB];
-    uint32_t dec[8];  // the band decision: inside, klo, khi
+    uint32_t dec[8];   // the band decision: inside, klo, khi
+    uint32_t stat[5];  // the slice's pairs, below, above, smallest and largest key
 };
 
 // Phase 2: pass one over a slice of the pairs.
@@ -768,6 +775,10 @@ __device__ __forceinline__ void scaled_hist(ScaleWs* __restrict__ ws, int slice,
     const uint32_t A = st.A, B = st.B;
     const int sh = bracket_shift(A, B);
     for (int e = tid; e < BOX_NB; e += BOX_THREADS) sm.hist[e] = 0u;
+    if (tid == 0) {
+        sm.stat[0] = sm.stat[1] = sm.stat[2] = sm.stat[4] = 0u;
+        sm.stat[3] = 0xFFFFFFFFu;
+    }
     load_points(ws, c, sm.pu);
     uint32_t q0, q1;
     slice_range(c, slice, S, q0, q1);
@@ -798,14 +809,22 @@ __device__ __forceinline__ void scaled_hist(ScaleWs* __restrict__ ws, int slice,
     np = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(np), 63);
     nbelow = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nbelow), 63);
     nabove = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(nabove), 63);
+    // the waves' counts meet in LDS; the workgroup adds them to the box once
     if (lane == 0 && np > 0u) {
-        atomicAdd(&st.npairs, np);
-        atomicAdd(&st.nbelow, nbelow);
-        atomicAdd(&st.nabove, nabove);
-        atomicMin(&st.kmin, lo);
-        atomicMax(&st.kmax, hi);
+        atomicAdd(&sm.stat[0], np);
+        atomicAdd(&sm.stat[1], nbelow);
+        atomicAdd(&sm.stat[2], nabove);
+        atomicMin(&sm.stat[3], lo);
+        atomicMax(&sm.stat[4], hi);
     }
     __syncthreads();
+    if (tid == 0 && sm.stat[0] > 0u) {
+        atomicAdd(&st.npairs, sm.stat[0]);
+        atomicAdd(&st.nbelow, sm.stat[1]);
+        atomicAdd(&st.nabove, sm.stat[2]);
+        atomicMin(&st.kmin, sm.stat[3]);
+        atomicMax(&st.kmax, sm.stat[4]);
+    }
     for (int e = tid; e < BOX_NB; e += BOX_THREADS) {
         const uint32_t v = sm.hist[e];
         if (v) atomicAdd(&ws->hist[e], v);

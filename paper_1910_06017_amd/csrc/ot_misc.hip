@@ -112,8 +112,9 @@ __global__ __launch_bounds__(BOX_THREADS) void k_scaled_prep(const float* __rest
                                                              float* __restrict__ out_scale,
                                                              ScaleWs* __restrict__ ws) {
     __shared__ ScaleSmem sm;
-    scaled_prep(boxes, blockIdx.x, box_id, pts, next_pts, status, n, out_boxes, out_count, out_scale,
-                ws + blockIdx.x, sm);
+    const int b = blockIdx.x >> 1;
+    scaled_prep(boxes, b, (int)(blockIdx.x & 1), box_id, pts, next_pts, status, n, out_boxes, out_count,
+                out_scale, ws + b, sm);
 }
 
 __global__ __launch_bounds__(BOX_THREADS) void k_scaled_hist(ScaleWs* __restrict__ ws, int S) {
@@ -144,7 +145,7 @@ hipError_t launch_box_scaled(const float* boxes, int m, const int32_t* box_id, c
                              int32_t* out_count, float* out_scale, void* ws, hipStream_t stream) {
     ScaleWs* w = static_cast<ScaleWs*>(ws);
     const int S = box_scaled_slices(m);
-    hipLaunchKernelGGL(k_scaled_prep, dim3(m), dim3(BOX_THREADS), 0, stream, boxes, box_id, pts,
+    hipLaunchKernelGGL(k_scaled_prep, dim3(2 * m), dim3(BOX_THREADS), 0, stream, boxes, box_id, pts,
                        next_pts, status, n, out_boxes, out_count, out_scale, w);
     hipLaunchKernelGGL(k_scaled_hist, dim3(m * S), dim3(BOX_THREADS), 0, stream, w, S);
     hipLaunchKernelGGL(k_scaled_band, dim3(m * S), dim3(BOX_THREADS), 0, stream, w, S);
