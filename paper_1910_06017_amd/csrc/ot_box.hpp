@@ -481,6 +481,8 @@ __device__ __forceinline__ void box_median(const float* __restrict__ boxes, int 
 // ---------------------------------------------------------------------------
 constexpr int SCALE_BAND = 6144;    // keys around the median held for the final selection
 constexpr int SCALE_SAMPLE = 4096;  // sampled pairs (in the band's storage, used first)
+constexpr int SCALE_SHB_LOG2 = 14;  // buckets of the sample's histogram: 2^14
+constexpr int SCALE_SHB = 1 << SCALE_SHB_LOG2;
 
 struct ScaleSmem {
     float4 pu[SCALE_CAP];      // (x, y) in the first frame, (x, y) in the second
@@ -490,6 +492,8 @@ struct ScaleSmem {
     int32_t count;
     uint32_t nsample;
 };
+static_assert(SCALE_SHB * sizeof(uint32_t) <= sizeof(float4) * SCALE_CAP, "sample histogram in the points' LDS");
+static_assert(SCALE_SHB % BOX_THREADS == 0 && SCALE_SHB % 4 == 0, "sample histogram split over the threads");
 
 // Key of the pair (a, e): the order-preserving key of the squared distance
 // ratio; false when the squared first-frame distance is 0.  Every pass goes
@@ -621,6 +625,57 @@ __device__ __forceinline__ void scaled_write(const float* __restrict__ boxes, in
     out_scale[b] = s;
 }
 
+// Zero the sample histogram (SCALE_SHB buckets in LDS).
+__device__ __forceinline__ void shist_zero(uint32_t* hs) {
+    for (int e = threadIdx.x; e < SCALE_SHB / 4; e += BOX_THREADS)
+        reinterpret_cast<uint4*>(hs)[e] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The buckets of ranks r0 and r1 (both below the histogram's total) in the
+// SCALE_SHB-bucket histogram hs: out[t] = {bucket, keys before it, keys in
+// it}.  Thread i owns buckets PER*i .. PER*i+PER-1; wtot holds the waves'
+// totals.  All threads call; out is valid after the closing barrier.
+template <class Out>
+__device__ __forceinline__ void shist_find(const uint32_t* hs, uint32_t r0, uint32_t r1,
+                                           uint32_t* wtot, Out& out) {
+    constexpr int PER = SCALE_SHB / BOX_THREADS;
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint32_t cnt[PER];
+    uint32_t tot = 0u;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        cnt[j] = hs[PER * tid + j];
+        tot += cnt[j];
+    }
+    const uint32_t incl = wave_incl_scan_u32(tot);
+    if (lane == 63) wtot[tid >> 6] = incl;
+    __syncthreads();
+    uint32_t base = 0u;
+    for (int w = 0; w < (tid >> 6); ++w) base += wtot[w];
+    const uint32_t excl = base + incl - tot;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const uint32_t r = t == 0 ? r0 : r1;
+        if (r >= excl && r < excl + tot) {
+            uint32_t acc = excl, before = excl, in = cnt[0];
+            int bk = PER * tid;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (r >= acc + cnt[j]) {
+                    bk = PER * tid + j + 1;
+                    before = acc + cnt[j];
+                    in = j + 1 < PER ? cnt[j + 1] : 0u;
+                }
+                acc += cnt[j];
+            }
+            out[t][0] = (uint32_t)bk;
+            out[t][1] = before;
+            out[t][2] = in;
+        }
+    }
+    __syncthreads();
+}
+
 // Phase 1, two workgroups per box that both gather the box's points.  Role 0
 // keeps the points and draws the sample: at most SCALE_SAMPLE pairs drawn by
 // a hashed index (neighbouring pairs of the walk share their points, so an
@@ -702,39 +757,62 @@ __device__ __forceinline__ void scaled_prep(const float* __restrict__ boxes, int
     }
     lo = wave_min_u32(lo);
     hi = wave_max_u32(hi);
-    // the two bracket ranks are far apart: each is its own (equal-rank)
-    // target, as two axes of one selection over the sample
-    if (tid < 2) {
-        sm.sel.klo[tid] = 0xFFFFFFFFu;
-        sm.sel.khi[tid] = 0u;
+    // The bracket only has to contain the two sample quantiles (any A <= B
+    // gives the exact result; a wider one only widens the band), so two
+    // histogram rounds of the sample replace an exact selection: round one
+    // over the sample's key range in SCALE_SHB key-linear buckets, round two
+    // over the two buckets that hold the quantiles, SCALE_SHB / 2 finer
+    // buckets each.  A is the lower edge of the lower quantile's final
+    // bucket, B the upper edge of the upper one's.  The gathered points are
+    // no longer needed in LDS (they are in the workspace), so the histogram
+    // takes their place.
+    if (tid == 0) {
+        sm.sel.klo[0] = 0xFFFFFFFFu;
+        sm.sel.khi[0] = 0u;
     }
     __syncthreads();
+    uint32_t* hs = reinterpret_cast<uint32_t*>(sm.pu);
+    shist_zero(hs);
     if (lane == 0 && lo <= hi) {
-        for (int a = 0; a < 2; ++a) {
-            atomicMin(&sm.sel.klo[a], lo);
-            atomicMax(&sm.sel.khi[a], hi);
-        }
+        atomicMin(&sm.sel.klo[0], lo);
+        atomicMax(&sm.sel.khi[0], hi);
     }
     __syncthreads();
     const uint32_t msmp = sm.nsample;
     uint32_t A = 0u, B = 0xFFFFFFFFu;
     if (msmp > 0u) {
+        const uint32_t klo = sm.sel.klo[0], khi = sm.sel.khi[0];
+        const uint32_t span = khi - klo;
+        const int sh = max(0, (span == 0u ? 0 : 32 - __clz((int)span)) - SCALE_SHB_LOG2);
+        for (uint32_t t = tid; t < msmp; t += BOX_THREADS) atomicAdd(&hs[(sm.band[t] - klo) >> sh], 1u);
+        __syncthreads();
         const uint32_t h = 2u + (uint32_t)ceilf(7.0f * sqrtf((float)msmp));
         const uint32_t rc = (msmp - 1u) / 2u;
-        if (tid == 0) {
-            sm.sel.rank[0][0] = sm.sel.rank[0][1] = rc > h ? rc - h : 0u;
-            sm.sel.rank[1][0] = sm.sel.rank[1][1] = min(msmp - 1u, msmp / 2u + h);
-        }
-        __syncthreads();
-        select_ranks<2>(sm.sel, false, [&](auto&& f) {
+        const uint32_t r0 = rc > h ? rc - h : 0u, r1 = min(msmp - 1u, msmp / 2u + h);
+        shist_find(hs, r0, r1, sm.sel.hist[0], sm.sel.red);
+        const uint32_t bk0 = sm.sel.red[0][0], base0 = sm.sel.red[0][1], n0 = sm.sel.red[0][2];
+        const uint32_t bk1 = sm.sel.red[1][0], base1 = sm.sel.red[1][1];
+        const uint32_t lo0 = klo + (bk0 << sh), lo1 = klo + (bk1 << sh);
+        uint32_t s0 = 0u, s1 = 0u;
+        int sh2 = 0;
+        if (sh > 0) {
+            sh2 = max(0, sh - (SCALE_SHB_LOG2 - 1));
+            __syncthreads();  // every thread has read round one's result
+            shist_zero(hs);
+            __syncthreads();
             for (uint32_t t = tid; t < msmp; t += BOX_THREADS) {
-                const float k = key2f(sm.band[t]);
-                const float v[2] = {k, k};
-                f(v);
+                const uint32_t key = sm.band[t], bk = (key - klo) >> sh;
+                if (bk == bk0) atomicAdd(&hs[(key - lo0) >> sh2], 1u);
+                if (bk == bk1) atomicAdd(&hs[SCALE_SHB / 2 + ((key - lo1) >> sh2)], 1u);
             }
-        });
-        A = sm.sel.res[0][0];
-        B = sm.sel.res[1][0];
+            __syncthreads();
+            shist_find(hs, r0 - base0, n0 + (r1 - base1), sm.sel.hist[0], sm.sel.red);
+            s0 = sm.sel.red[0][0];
+            s1 = sm.sel.red[1][0] - (uint32_t)(SCALE_SHB / 2);
+        }
+        A = lo0 + (s0 << sh2);
+        const uint64_t b1 = (uint64_t)lo1 + ((uint64_t)(s1 + 1u) << sh2) - 1u;
+        B = (uint32_t)min(b1, (uint64_t)khi);
     }
     if (tid == 0) {
         st.c = c;
