@@ -227,11 +227,14 @@ OT_API ot_err ot_fb_gate(const float* pts, const float* back_pts, const uint8_t*
  * (its count is still written).  Ratios are formed in float32; pairs whose
  * squared first-frame distance is zero in float32 are skipped.  Layouts as in
  * ot_box_update; out_scale m float32.  Work per box grows with c^2; the
- * pairs of one box are spread over several workgroups.  ws:
- * ot_box_scaled_bytes(m) bytes, 256-byte aligned, owned by the caller (no
- * state is kept in it between calls).
- * Errors: OT_E_INVAL (negative counts, null pointers with m > 0,
- * misalignment), OT_E_WORKSPACE, OT_E_LAUNCH. */
+ * pairs of one box are spread over several workgroups.  ws: device scratch
+ * of at least ot_box_scaled_bytes(m) bytes, 256-byte aligned, owned by the
+ * caller; every call rewrites it from scratch and keeps nothing in it, but
+ * two calls whose work overlaps in time (different streams) must not share
+ * one.  m == 0 is a no-op.
+ * Errors: OT_E_INVAL (negative counts, m > 2^24, null pointers with m > 0,
+ * misalignment), OT_E_WORKSPACE (ws NULL, not 256-byte aligned or smaller
+ * than ot_box_scaled_bytes(m)), OT_E_LAUNCH. */
 OT_API ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t* box_id,
                             const float* pts, const float* next_pts, const uint8_t* status,
                             int32_t n, float* out_boxes, int32_t* out_count, float* out_scale,
