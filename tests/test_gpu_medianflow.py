@@ -162,6 +162,13 @@ def check_scaled(ops, boxes, ids, P, Q, st):
     ([400] * 20, 12),
     ([1023, 1024, 1025, 2049], 13),
     ([3000, 7], 14),
+    # one box: 64 slices per pass, most of them empty for so few pairs
+    ([10], 15),
+    ([2], 16),
+    # 300 boxes: one slice per box
+    ([(7 * i) % 41 for i in range(300)], 17),
+    # 128 boxes: two slices per box
+    ([(5 * i) % 97 for i in range(128)], 18),
 ])
 def test_box_scaled_matches_oracle(ops, counts, seed):
     check_scaled(ops, *box_scene(seed, counts))
