@@ -530,9 +530,11 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
     return base + below;
 }
 
-// Visit every unordered pair {i, j} of the c gathered points once as f(key),
-// key that of the squared distance ratio (pair_key), skipping pairs whose
-// squared first-frame distance is zero.  Pair q of the c * floor((c-1)/2) + (c even ? c/2 : 0)
+// Visit every unordered pair {i, j} of the c gathered points once as
+// f(key, ok), key that of the squared distance ratio (pair_key) and ok false
+// for a pair whose squared first-frame distance is zero (its key is then
+// meaningless and the pair is skipped).  The callback runs for every pair so
+// that it can be branch-free.  Pair q of the c * floor((c-1)/2) + (c even ? c/2 : 0)
 // pairs is (i, (i + d) mod c) with i = q mod c and d = q / c + 1: every
 // circular distance d below c/2 pairs all c points, and for even c the
 // distance c/2 pairs only the first half.  Each thread steps q by BOX_THREADS.
@@ -548,7 +550,8 @@ __device__ __forceinline__ void visit_pairs_range(const float4* __restrict__ pu,
         uint32_t j = i + d + 1u;
         if (j >= uc) j -= uc;
         uint32_t key;
-        if (pair_key(pu[i], pu[j], key)) f(key);
+        const bool ok = pair_key(pu[i], pu[j], key);
+        f(key, ok);
         i += si;
         d += sd;
         if (i >= uc) {
@@ -862,24 +865,20 @@ __device__ __forceinline__ void scaled_hist(ScaleWs* __restrict__ ws, int slice,
     slice_range(c, slice, S, q0, q1);
     uint32_t np = 0u, nbelow = 0u, nabove = 0u, lo = 0xFFFFFFFFu, hi = 0u, run = 0u;
     int cur = 0;
-    visit_pairs_range(sm.pu, c, q0, q1, [&](uint32_t key) {
-        ++np;
-        lo = min(lo, key);
-        hi = max(hi, key);
-        if (key < A) {
-            ++nbelow;
-        } else if (key > B) {
-            ++nabove;
-        } else {
-            // runs of equal buckets are added once
-            const int bu = (int)((key - A) >> sh);
-            if (bu != cur) {
-                if (run) atomicAdd(&sm.hist[cur], run);
-                cur = bu;
-                run = 0u;
-            }
-            ++run;
-        }
+    visit_pairs_range(sm.pu, c, q0, q1, [&](uint32_t key, bool ok) {
+        // selects instead of branches; runs of equal buckets are added once
+        np += ok ? 1u : 0u;
+        lo = ok ? min(lo, key) : lo;
+        hi = ok ? max(hi, key) : hi;
+        const bool below = ok && key < A, above = ok && key > B;
+        nbelow += below ? 1u : 0u;
+        nabove += above ? 1u : 0u;
+        const bool in = ok && !below && !above;
+        const int bu = (int)((key - A) >> sh);
+        const bool fresh = in && bu != cur;
+        if (fresh && run) atomicAdd(&sm.hist[cur], run);
+        cur = fresh ? bu : cur;
+        run = fresh ? 1u : run + (in ? 1u : 0u);
     });
     if (run) atomicAdd(&sm.hist[cur], run);
     lo = wave_min_u32(lo);
@@ -974,10 +973,12 @@ __device__ __forceinline__ void scaled_band(ScaleWs* __restrict__ ws, int slice,
     load_points(ws, c, sm.pu);
     uint32_t q0, q1;
     slice_range(c, slice, S, q0, q1);
-    visit_pairs_range(sm.pu, c, q0, q1, [&](uint32_t key) {
-        const bool in = key >= bl && key <= bh;
-        const uint32_t slot = wave_append(in, &st.nband);
-        if (in && slot < (uint32_t)SCALE_BAND) ws->band[slot] = key;
+    visit_pairs_range(sm.pu, c, q0, q1, [&](uint32_t key, bool ok) {
+        const bool in = ok && key >= bl && key <= bh;
+        if (__ballot(in)) {  // band keys are rare: most waves skip the append
+            const uint32_t slot = wave_append(in, &st.nband);
+            if (in && slot < (uint32_t)SCALE_BAND) ws->band[slot] = key;
+        }
     });
 }
 
@@ -1027,9 +1028,11 @@ __device__ __forceinline__ void scaled_final(const float* __restrict__ boxes, in
         } else {
             load_points(ws, c, sm.pu);
             select_ranks<1>(sm.rsel, false, [&](auto&& f) {
-                visit_pairs(sm.pu, c, [&](uint32_t key) {
-                    const float v[1] = {key2f(key)};
-                    f(v);
+                visit_pairs(sm.pu, c, [&](uint32_t key, bool ok) {
+                    if (ok) {
+                        const float v[1] = {key2f(key)};
+                        f(v);
+                    }
                 });
             });
         }
