@@ -107,6 +107,16 @@ __device__ __forceinline__ float blend_pair(uint32_t e, float bx) {
     return fmaf(bx, (float)h.y, (float)h.x);
 }
 
+// Bilinear blend of window sums at fractional offset (fx, fy), bb = fx * fy:
+// (1-fy) (S_J0 + fx S_D0) + fy (S_J1 + fx S_D1) expanded as
+// S_J0 + fx S_D0 + fy (S_J1 - S_J0) + fx fy (S_D1 - S_D0).  The template and
+// target terms both go through this one function, so equal inputs give
+// equal results (identical frames give b == 0 exactly).
+__device__ __forceinline__ float blend_sums(float j0, float d0, float jd, float dd, float fx,
+                                            float fy, float bb) {
+    return fmaf(bb, dd, fmaf(fy, jd, fmaf(fx, d0, j0)));
+}
+
 __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int w, int h, int jp,
                                              int sx0, int sy0, int SR, int SC, int SP,
                                              uint32_t* __restrict__ jr, int lane) {
@@ -468,10 +478,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             float tj0x, td0x, tj1x, td1x, tj0y, td0y, tj1y, td1y;
             wave_sum4(p0, p1, p2, p3, tj0x, td0x, tj1x, td1x);
             wave_sum4(q0, q1, q2, q3, tj0y, td0y, tj1y, td1y);
-            const float r0x = fmaf(ax, td0x, tj0x), r1x = fmaf(ax, td1x, tj1x);
-            const float r0y = fmaf(ax, td0y, tj0y), r1y = fmaf(ax, td1y, tj1y);
-            cax = fmaf(ay, r1x - r0x, r0x);
-            cay = fmaf(ay, r1y - r0y, r0y);
+            cax = blend_sums(tj0x, td0x, tj1x - tj0x, td1x - td0x, ax, ay, ax * ay);
+            cay = blend_sums(tj0y, td0y, tj1y - tj0y, td1y - td0y, ax, ay, ax * ay);
         }
         // the sums are 1024x the tensor of the true gradients (exactly)
         const float hm = 0.5f * (gxx + gyy), hd = 0.5f * (gxx - gyy);
@@ -512,13 +520,16 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         // and S_J1, S_D1 the same one row down.  These eight window sums are
         // recomputed only when the floor position changes; an iteration that
         // stays on the same pixel costs a handful of wave-uniform operations.
+        // The sums are kept as (S_J0, S_D0, S_J1 - S_J0, S_D1 - S_D0), the form
+        // blend_sums takes, which the template term above uses as well.
         int sfx = INT32_MIN, sfy = INT32_MIN;  // floor position of the sums
-        float sj0x = 0.0f, sd0x = 0.0f, sj1x = 0.0f, sd1x = 0.0f;
-        float sj0y = 0.0f, sd0y = 0.0f, sj1y = 0.0f, sd1y = 0.0f;
+        float sj0x = 0.0f, sd0x = 0.0f, sjdx = 0.0f, sddx = 0.0f;
+        float sj0y = 0.0f, sd0y = 0.0f, sjdy = 0.0f, sddy = 0.0f;
+        const float c0x = cx + gx, c0y = cy + gy;
         int it = 0;
         while (it < iters) {
-            const float qx = fminf(fmaxf(cx + gx + nux, lo), hix);
-            const float qy = fminf(fmaxf(cy + gy + nuy, lo), hiy);
+            const float qx = __builtin_amdgcn_fmed3f(c0x + nux, lo, hix);
+            const float qy = __builtin_amdgcn_fmed3f(c0y + nuy, lo, hiy);
             const float fqx = floorf(qx), fqy = floorf(qy);
             const float bxw = qx - fqx, byw = qy - fqy;
             int ox = (int)fqx - g.r - sx0, oy = (int)fqy - g.r - sy0;
@@ -551,15 +562,19 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                     q3 = fmaf((float)en.y, Y[k], q3);
                     e = en;
                 }
+                float sj1x, sd1x, sj1y, sd1y;
                 wave_sum4(p0, p1, p2, p3, sj0x, sd0x, sj1x, sd1x);
                 wave_sum4(q0, q1, q2, q3, sj0y, sd0y, sj1y, sd1y);
+                sjdx = sj1x - sj0x;
+                sddx = sd1x - sd0x;
+                sjdy = sj1y - sj0y;
+                sddy = sd1y - sd0y;
                 sfx = ifx;
                 sfy = ify;
             }
-            const float r0x = fmaf(bxw, sd0x, sj0x), r1x = fmaf(bxw, sd1x, sj1x);
-            const float r0y = fmaf(bxw, sd0y, sj0y), r1y = fmaf(bxw, sd1y, sj1y);
-            const float bx = cax - fmaf(byw, r1x - r0x, r0x);
-            const float by = cay - fmaf(byw, r1y - r0y, r0y);
+            const float bb = bxw * byw;
+            const float bx = cax - blend_sums(sj0x, sd0x, sjdx, sddx, bxw, byw, bb);
+            const float by = cay - blend_sums(sj0y, sd0y, sjdy, sddy, bxw, byw, bb);
             const float ex = (gyy * bx - gxy * by) * idet;
             const float ey = (gxx * by - gxy * bx) * idet;
             nux += ex;
