@@ -530,45 +530,78 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
     return base + below;
 }
 
-// Visit every unordered pair {i, j} of the c gathered points once as
-// f(key, ok), key that of the squared distance ratio (pair_key) and ok false
-// for a pair whose squared first-frame distance is zero (its key is then
-// meaningless and the pair is skipped).  The callback runs for every pair so
-// that it can be branch-free.  Pair q of the c * floor((c-1)/2) + (c even ? c/2 : 0)
-// pairs is (i, (i + d) mod c) with i = q mod c and d = q / c + 1: every
-// circular distance d below c/2 pairs all c points, and for even c the
-// distance c/2 pairs only the first half.  Each thread steps q by BOX_THREADS.
-template <class F>
-__device__ __forceinline__ void visit_pairs_range(const float4* __restrict__ pu, int c, uint32_t q0,
-                                                  uint32_t q1, F&& f) {
-    const uint32_t uc = (uint32_t)c;
-    const uint32_t t = q0 + threadIdx.x;
-    if (t >= q1) return;
-    uint32_t d = t / uc, i = t - d * uc;
-    const uint32_t sd = (uint32_t)BOX_THREADS / uc, si = (uint32_t)BOX_THREADS - sd * uc;
-    for (uint32_t q = t; q < q1; q += BOX_THREADS) {
-        uint32_t j = i + d + 1u;
-        if (j >= uc) j -= uc;
-        uint32_t key;
-        const bool ok = pair_key(pu[i], pu[j], key);
-        f(key, ok);
-        i += si;
-        d += sd;
-        if (i >= uc) {
-            i -= uc;
-            ++d;
-        }
-    }
-}
-
+// Pair q of the c * floor((c-1)/2) + (c even ? c/2 : 0) unordered pairs is
+// (i, (i + d) mod c) with i = q mod c and d = q / c + 1: every circular
+// distance d below c/2 pairs all c points, and for even c the distance c/2
+// pairs only the first half.  The sample draws pairs through this numbering.
 __device__ __forceinline__ uint32_t pair_total(int c) {
     const uint32_t uc = (uint32_t)c;
     return uc * ((uc - 1u) / 2u) + ((uc & 1u) ? 0u : uc / 2u);
 }
 
+// The passes walk the same pairs as items that share their first point: item
+// t < G*c (G = ceil(floor((c-1)/2) / PAIR_K)) is point i = t mod c with the
+// distances 1 + PAIR_K*g .. PAIR_K*(g+1) below c/2, g = t / c (the last
+// group may hold fewer); for even c, item G*c + i (i < c/2) is the pair
+// (i, i + c/2).  One load of point i serves PAIR_K pairs.
+constexpr uint32_t PAIR_K = 4;
+
+__device__ __forceinline__ uint32_t pair_items(int c) {
+    if (c < 2) return 0u;
+    const uint32_t uc = (uint32_t)c, df = (uc - 1u) / 2u;
+    return ((df + PAIR_K - 1u) / PAIR_K) * uc + ((uc & 1u) ? 0u : uc / 2u);
+}
+
+// Visit every unordered pair {i, j} of the c gathered points in the items
+// [t0, t1) once as f(key, ok), key that of the squared distance ratio
+// (pair_key) and ok false for a pair whose squared first-frame distance is
+// zero (its key is then meaningless and the pair is skipped).  The callback
+// runs for every pair so that it can be branch-free.  Each thread steps its
+// item by BOX_THREADS with an incremental (g, i) update.
+template <class F>
+__device__ __forceinline__ void visit_pairs_range(const float4* __restrict__ pu, int c, uint32_t t0,
+                                                  uint32_t t1, F&& f) {
+    if (c < 2) return;
+    const uint32_t uc = (uint32_t)c, df = (uc - 1u) / 2u;
+    const uint32_t gc = ((df + PAIR_K - 1u) / PAIR_K) * uc, half = uc / 2u;
+    uint32_t t = t0 + threadIdx.x;
+    if (t >= t1) return;
+    uint32_t g = t / uc, i = t - g * uc;
+    const uint32_t sg = (uint32_t)BOX_THREADS / uc, si = (uint32_t)BOX_THREADS - sg * uc;
+    for (; t < t1; t += BOX_THREADS) {
+        if (t < gc) {
+            const float4 a = pu[i];
+            const uint32_t d0 = g * PAIR_K;
+            uint32_t j = i + d0 + 1u;
+            if (j >= uc) j -= uc;
+#pragma unroll
+            for (uint32_t k = 0; k < PAIR_K; ++k) {
+                if (d0 + k < df) {
+                    uint32_t key;
+                    const bool ok = pair_key(a, pu[j], key);
+                    f(key, ok);
+                }
+                ++j;
+                if (j >= uc) j -= uc;
+            }
+        } else {
+            const uint32_t ih = t - gc;  // < c/2, even c only
+            uint32_t key;
+            const bool ok = pair_key(pu[ih], pu[ih + half], key);
+            f(key, ok);
+        }
+        i += si;
+        g += sg;
+        if (i >= uc) {
+            i -= uc;
+            ++g;
+        }
+    }
+}
+
 template <class F>
 __device__ __forceinline__ void visit_pairs(const float4* __restrict__ pu, int c, F&& f) {
-    visit_pairs_range(pu, c, 0u, pair_total(c), f);
+    visit_pairs_range(pu, c, 0u, pair_items(c), f);
 }
 
 // ---------------------------------------------------------------------------
@@ -835,7 +868,7 @@ __device__ __forceinline__ void load_points(const ScaleWs* __restrict__ ws, int 
 }
 
 __device__ __forceinline__ void slice_range(int c, int slice, int S, uint32_t& q0, uint32_t& q1) {
-    const uint64_t total = pair_total(c);
+    const uint64_t total = pair_items(c);
     q0 = (uint32_t)(total * (uint64_t)slice / (uint64_t)S);
     q1 = (uint32_t)(total * (uint64_t)(slice + 1) / (uint64_t)S);
 }
