@@ -186,7 +186,8 @@ def main():
         return
     if a.profile_extra:
         print(json.dumps({"median_flow": bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid,
-                                                           WIN, L, ITERS, EPS, MARGIN, cs),
+                                                           WIN, L, ITERS, EPS, MARGIN, cs,
+                                                           scenes=False),
                           "matching": bench_matching(ops, wl, ob, cs)}))
         return
 
@@ -281,11 +282,12 @@ def _graph_ms(torch, g, cs, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS, EPS, MARGIN, cs):
+def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS, EPS, MARGIN, cs,
+                      scenes=True):
     """The Median-Flow step on the same frame pair: next pyramid, forward and
     backward tracking, the forward-backward gate (1 px) and the scaled box
     update, one graph replay; the gate and the scaled update are also timed
-    alone."""
+    alone, and (scenes) the scaled update on a few large boxes."""
     import torch
     dev = pts.device
     n, m = pts.shape[0], boxes.shape[0]
@@ -342,7 +344,43 @@ def bench_median_flow(a, ops, wl, prev, f1, ws1, pts, boxes, bid, WIN, L, ITERS,
             "fb_gate_us": gate_ms * 1e3,
             "fb_gate_hbm_frac": gate_bytes / (gate_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "box_scaled_us": sc_ms * 1e3, "box_pairs": pairs,
-            "box_pairs_per_s": pairs / (sc_ms * 1e-3)}
+            "box_pairs_per_s": pairs / (sc_ms * 1e-3),
+            "box_scaled_scenes": bench_scaled_scenes(ops, dev, cs, reps, KREP) if scenes else None}
+
+
+def bench_scaled_scenes(ops, dev, cs, reps, krep):
+    """The scaled box update alone on seeded point sets of few large boxes
+    (similarity motion, 10 % outliers, 5 % lost points): 20 boxes of 400
+    points, 16 of 1000, 4 of 5000; krep launches per graph replay."""
+    import torch
+    from paper_1910_06017_amd import synth
+    out = {}
+    for name, counts, seed in (("20x400", [400] * 20, 1), ("16x1000", [1000] * 16, 2),
+                               ("4x5000", [5000] * 4, 3)):
+        arrs = [torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+                for x in synth.similarity_box_points(seed, counts)]
+        mm = arrs[0].shape[0]
+        o = (torch.empty((mm, 4), dtype=torch.float32, device=dev),
+             torch.empty(mm, dtype=torch.int32, device=dev),
+             torch.empty(mm, dtype=torch.float32, device=dev))
+        w2 = ops.box_scaled_workspace(mm, dev)
+
+        def fn():
+            ops.box_update_scaled(*arrs, out=o, ws=w2)
+
+        with torch.cuda.stream(cs):
+            fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(krep):
+                fn()
+        torch.cuda.synchronize()
+        us = _graph_ms(torch, g, cs, reps) / krep * 1e3
+        c = o[1].cpu().numpy().astype(np.int64)
+        pairs = int((c * (c - 1) // 2).sum())
+        out[name] = {"us": us, "pairs": pairs, "pairs_per_s": pairs / (us * 1e-6)}
+    return out
 
 
 def bench_dense(ops, wl, f0, f1, boxes, cs):

@@ -500,3 +500,45 @@ def served_streams(seed: int = 505, nstreams: int = 64, nframes: int = 20,
         boxes = np.array([[r.bbox(k) for r in scene.rects] for k in range(nframes)])
         out.append(Stream(s, W, H, prm["levels"], frames, boxes, per))
     return out
+
+
+def similarity_box_points(seed: int, counts, outlier_frac: float = 0.1, lost_frac: float = 0.05,
+                          dup: bool = False, extra_ids: bool = True):
+    """Point sets for the scaled box update: box b gets counts[b] points drawn
+    uniformly in a random box, moved by a random similarity (scale 0.9-1.1
+    about the box centre, shift up to 30 px) plus 0.05 px noise, with a
+    fraction of outliers (25 px noise) and of lost points (status 0); ids are
+    interleaved in random order, and a few points carry ids of no box.  With
+    dup every point of a box has a coincident twin.  Returns (boxes (m, 4),
+    box_id (n,), pts (n, 2), next_pts (n, 2), status (n,))."""
+    rng = np.random.default_rng(seed)
+    m = len(counts)
+    boxes, P, Q, ids = [], [], [], []
+    for b, c in enumerate(counts):
+        w, h = rng.uniform(20, 400, 2)
+        x0, y0 = rng.uniform(0, 1500), rng.uniform(0, 700)
+        boxes.append([x0, y0, x0 + w, y0 + h])
+        s = rng.uniform(0.9, 1.1)
+        t = rng.uniform(-30, 30, 2)
+        p = rng.uniform([x0, y0], [x0 + w, y0 + h], (c, 2))
+        if dup and c > 4:
+            p[c // 2:] = p[: c - c // 2]
+        cen = np.array([x0 + w / 2, y0 + h / 2])
+        q = cen + t + s * (p - cen) + rng.normal(0, 0.05, (c, 2))
+        bad = rng.random(c) < outlier_frac
+        q[bad] += rng.normal(0, 25, (bad.sum(), 2))
+        P.append(p)
+        Q.append(q)
+        ids.append(np.full(c, b, np.int32))
+    P = np.concatenate(P) if P else np.zeros((0, 2))
+    Q = np.concatenate(Q) if Q else np.zeros((0, 2))
+    ids = np.concatenate(ids) if ids else np.zeros(0, np.int32)
+    if extra_ids:
+        k = max(1, len(ids) // 50)
+        P = np.concatenate([P, rng.uniform(0, 1000, (k, 2))])
+        Q = np.concatenate([Q, rng.uniform(0, 1000, (k, 2))])
+        ids = np.concatenate([ids, rng.choice([-1, m, m + 7], k).astype(np.int32)])
+    st = (rng.random(len(ids)) >= lost_frac).astype(np.uint8)
+    perm = rng.permutation(len(ids))
+    return (np.asarray(boxes, np.float32), ids[perm].astype(np.int32), P[perm].astype(np.float32),
+            Q[perm].astype(np.float32), st[perm])

@@ -109,37 +109,7 @@ def test_fb_gate_in_place_and_empty(ops):
 def box_scene(seed, counts, outlier_frac=0.1, lost_frac=0.05, dup=False, extra_ids=True):
     """Boxes with `counts[b]` points each, moving by a similarity plus noise,
     some outliers and lost points, ids interleaved in random order."""
-    rng = np.random.default_rng(seed)
-    m = len(counts)
-    boxes, P, Q, ids = [], [], [], []
-    for b, c in enumerate(counts):
-        w, h = rng.uniform(20, 400, 2)
-        x0, y0 = rng.uniform(0, 1500), rng.uniform(0, 700)
-        boxes.append([x0, y0, x0 + w, y0 + h])
-        s = rng.uniform(0.9, 1.1)
-        t = rng.uniform(-30, 30, 2)
-        p = rng.uniform([x0, y0], [x0 + w, y0 + h], (c, 2))
-        if dup and c > 4:
-            p[c // 2:] = p[: c - c // 2]   # every point has a coincident twin
-        cen = np.array([x0 + w / 2, y0 + h / 2])
-        q = cen + t + s * (p - cen) + rng.normal(0, 0.05, (c, 2))
-        bad = rng.random(c) < outlier_frac
-        q[bad] += rng.normal(0, 25, (bad.sum(), 2))
-        P.append(p)
-        Q.append(q)
-        ids.append(np.full(c, b, np.int32))
-    P = np.concatenate(P) if P else np.zeros((0, 2))
-    Q = np.concatenate(Q) if Q else np.zeros((0, 2))
-    ids = np.concatenate(ids) if ids else np.zeros(0, np.int32)
-    if extra_ids:
-        k = max(1, len(ids) // 50)
-        P = np.concatenate([P, rng.uniform(0, 1000, (k, 2))])
-        Q = np.concatenate([Q, rng.uniform(0, 1000, (k, 2))])
-        ids = np.concatenate([ids, rng.choice([-1, m, m + 7], k).astype(np.int32)])
-    st = (rng.random(len(ids)) >= lost_frac).astype(np.uint8)
-    perm = rng.permutation(len(ids))
-    return (np.asarray(boxes, np.float32), ids[perm].astype(np.int32), P[perm].astype(np.float32),
-            Q[perm].astype(np.float32), st[perm])
+    return synth.similarity_box_points(seed, counts, outlier_frac, lost_frac, dup, extra_ids)
 
 
 def run_scaled(ops, boxes, ids, P, Q, st):
