@@ -18,6 +18,7 @@ the same frames one at a time with the per-stream calls for comparison.
 """
 from __future__ import annotations
 
+import gc
 import heapq
 import math
 import time
@@ -488,6 +489,21 @@ def run_trace(trace, frame_fn, specs, scheduler: Scheduler, executor, clock=None
     sleep = sleep or (lambda dt: time.sleep(max(0.0, dt)))
     for sp in specs:
         scheduler.register(sp)
+    # Python's cycle collector stops the loop for tens of milliseconds once
+    # thousands of results are alive, and every frame queued meanwhile waits
+    # that long: it stays off while the loop runs (reference counting still
+    # frees everything that is not in a cycle) and runs once afterwards.
+    gc_on = gc.isenabled()
+    gc.disable()
+    try:
+        return _run_trace(trace, frame_fn, scheduler, executor, clock, sleep, max_wall, batched)
+    finally:
+        if gc_on:
+            gc.enable()
+        gc.collect()
+
+
+def _run_trace(trace, frame_fn, scheduler, executor, clock, sleep, max_wall, batched):
     t0 = clock()
     i, results = 0, []
     n = len(trace)
