@@ -775,6 +775,33 @@ def check_tvl1_global_shift():
     assert np.median(e) < 0.02 and np.percentile(e, 90) < 0.05, (np.median(e), np.percentile(e, 90))
 
 
+def check_central_gradient_closed_forms():
+    """The warp gradient is the central difference (I(x+1) - I(x-1)) / 2 at
+    clamped indices: a ramp a x + b y gives exactly (a, b) in the interior,
+    x^2 gives exactly 2x (the central difference of a quadratic is its
+    derivative), a sinusoid A sin(w x) gives A sin(w) cos(w x), and the
+    clamped first and last columns / rows give the one-sided half
+    differences (I(1) - I(0)) / 2 and (I(W-1) - I(W-2)) / 2."""
+    T = oracle.tvl1
+    H, W = 9, 13
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    gx, gy = T.central_gradient(0.75 * xs - 1.5 * ys + 3.0)
+    assert np.array_equal(gx[:, 1:-1], np.full((H, W - 2), 0.75))
+    assert np.array_equal(gy[1:-1, :], np.full((H - 2, W), -1.5))
+    img = xs ** 2 + 0.5 * ys ** 2
+    gx, gy = T.central_gradient(img)
+    assert np.array_equal(gx[:, 1:-1], 2.0 * xs[:, 1:-1])
+    assert np.array_equal(gy[1:-1, :], ys[1:-1, :])
+    assert np.array_equal(gx[:, 0], (img[:, 1] - img[:, 0]) / 2)
+    assert np.array_equal(gx[:, -1], (img[:, -1] - img[:, -2]) / 2)
+    assert np.array_equal(gy[0], (img[1] - img[0]) / 2)
+    assert np.array_equal(gy[-1], (img[-1] - img[-2]) / 2)
+    w = 0.37
+    gx, gy = T.central_gradient(2.5 * np.sin(w * xs))
+    assert np.allclose(gx[:, 1:-1], 2.5 * np.sin(w) * np.cos(w * xs[:, 1:-1]), atol=1e-14)
+    assert np.array_equal(gy[1:-1], np.zeros((H - 2, W)))
+
+
 def check_tv_upsample():
     """A constant coarse flow doubles; a linear one keeps its slope in fine
     pixels (away from the clamped last column)."""
@@ -804,7 +831,7 @@ def check_box_mean_flow():
 
 TVL1 = [check_tv_div_adjoint, check_rof_closed_forms, check_tv_data_step_bruteforce,
         check_tvl1_zero_motion_and_dual, check_tvl1_global_shift, check_tv_upsample,
-        check_box_mean_flow]
+        check_box_mean_flow, check_central_gradient_closed_forms]
 
 MATCHING = [check_iou_closed_forms, check_iou_raster, check_iou_matrix_invariants,
             check_assign_bruteforce, check_assign_not_greedy_and_threshold, check_track_update,

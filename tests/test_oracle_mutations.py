@@ -178,6 +178,11 @@ TVL1_MUTATIONS = {
     "upsample_no_doubling": ("return 2.0 * bilinear_clamped", "return bilinear_clamped"),
     "primal_sign": ("u1 = v1 + prm.theta * div(p[0], p[1])", "u1 = v1 - prm.theta * div(p[0], p[1])"),
     "linearisation_sign": ("rho0 = I1w - gx * u1 - gy * u2 - I0", "rho0 = I1w + gx * u1 + gy * u2 - I0"),
+    "central_gradient_no_half": ("return 0.5 * (xp - xm), 0.5 * (yp - ym)", "return (xp - xm), (yp - ym)"),
+    "central_gradient_x_no_half": ("return 0.5 * (xp - xm), 0.5 * (yp - ym)", "return (xp - xm), 0.5 * (yp - ym)"),
+    "central_gradient_forward": ("return 0.5 * (xp - xm), 0.5 * (yp - ym)", "return (xp - img), (yp - img)"),
+    "central_gradient_axes_swapped": ("return 0.5 * (xp - xm), 0.5 * (yp - ym)", "return 0.5 * (yp - ym), 0.5 * (xp - xm)"),
+    "central_gradient_wraps": ("xp = np.concatenate([img[:, 1:], img[:, -1:]], axis=1)", "xp = np.roll(img, -1, axis=1)"),
     "box_excludes_right_edge": ("min(W - 1, int(np.floor(x1)))", "min(W - 1, int(np.floor(x1)) - 1)"),
 }
 
