@@ -267,6 +267,36 @@ struct LkResult {
     int status;
 };
 
+// Positions are carried as an exact integer anchor plus a small float
+// offset: a level coordinate of ~2000 px held in one float has a spacing of
+// 1.2e-4 px, which a non-contracting iterate amplifies, while an offset of a
+// few pixels keeps ~1e-7 px.  split_pos gives the integer floor and the
+// fraction of anchor + t, the position clamped to [lo, hi] (a clamped
+// position has fraction 0; past the bounds every tap reads the level's edge).
+__device__ __forceinline__ void split_pos(int anchor, float t, int lo, int hi, int& ip, float& f) {
+    t = __builtin_amdgcn_fmed3f(t, -1048576.0f, 1048576.0f);
+    const float ft = floorf(t);
+    ip = anchor + (int)ft;
+    f = t - ft;
+    if (ip < lo) {
+        ip = lo;
+        f = 0.0f;
+    }
+    if (ip >= hi) {
+        ip = hi;
+        f = 0.0f;
+    }
+}
+
+// g <- 2 (g + nu) on the split form g = gi + gf, gf in [0, 1): the doubling
+// and the floor are exact, only gf + nu rounds (at the magnitude of nu).
+__device__ __forceinline__ void carry_level(int& gi, float& gf, float nu) {
+    const float t = 2.0f * __builtin_amdgcn_fmed3f(gf + nu, -1048576.0f, 1048576.0f);
+    const float ft = floorf(t);
+    gi = 2 * gi + (int)ft;
+    gf = t - ft;
+}
+
 // FIXED: the geometry g is a compile-time constant (the caller's window and
 // margin are template arguments), so fixed-count loops are unrolled.
 // GRADS: the template pyramid carries materialized Scharr sums, which are
@@ -302,7 +332,9 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
 
     float X[R], Y[R];
     float* __restrict__ aA = reinterpret_cast<float*>(smem + g.AO);  // [R][64], level 0 only
-    float gx = 0.0f, gy = 0.0f;
+    // guess g = (gix + gfx, giy + gfy) in the current level's pixels
+    int gix = 0, giy = 0;
+    float gfx = 0.0f, gfy = 0.0f;
     float nux = 0.0f, nuy = 0.0f;
     uint32_t* jr = reinterpret_cast<uint32_t*>(smem);
     uint8_t* patch = smem;
@@ -491,9 +523,9 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                     if (iters_out) iters_out[k] = 0;
                     if (lam_out && k < l) lam_out[k] = 0.0f;
                 }
-            const float s = __builtin_ldexpf(1.0f, l);
-            res.nx = ux + gx * s;
-            res.ny = uy + gy * s;
+            const double s = __builtin_ldexp(1.0, l);
+            res.nx = (float)((double)ux + ((double)gix + (double)gfx) * s);
+            res.ny = (float)((double)uy + ((double)giy + (double)gfy) * s);
             return res;
         }
         // b comes out 32x and the tensor 1024x: 32 / det(1024 G) gives eta
@@ -502,13 +534,19 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
 
         // Positions are clamped before the integer conversion; past the bounds
         // every tap already reads the level's edge, so the samples are unchanged.
-        const float lo = -(float)(g.win + 8), hix = (float)(w + g.win + 8), hiy = (float)(h + g.win + 8);
+        const int lo = -(g.win + 8), hix = w + g.win + 8, hiy = h + g.win + 8;
+        // target position c + g + nu = (floor(c) + gi) + (frac(c) + gf + nu)
+        const int ancx = (int)flx + gix, ancy = (int)fly + giy;
+        const float f0x = ax + gfx, f0y = ay + gfy;
         nux = 0.0f;
         nuy = 0.0f;
         {
-            const float qx = fminf(fmaxf(cx + gx, lo), hix), qy = fminf(fmaxf(cy + gy, lo), hiy);
-            sx0 = (int)floorf(qx) - g.r - g.M;
-            sy0 = (int)floorf(qy) - g.r - g.M;
+            int qx, qy;
+            float unusedx, unusedy;
+            split_pos(ancx, f0x, lo, hix, qx, unusedx);
+            split_pos(ancy, f0y, lo, hiy, qy, unusedy);
+            sx0 = qx - g.r - g.M;
+            sy0 = qy - g.r - g.M;
             stage_target(Jl, w, h, jp, sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
             soff = sx0 & 3;
             __syncthreads();
@@ -525,14 +563,13 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         int sfx = INT32_MIN, sfy = INT32_MIN;  // floor position of the sums
         float sj0x = 0.0f, sd0x = 0.0f, sjdx = 0.0f, sddx = 0.0f;
         float sj0y = 0.0f, sd0y = 0.0f, sjdy = 0.0f, sddy = 0.0f;
-        const float c0x = cx + gx, c0y = cy + gy;
         int it = 0;
         while (it < iters) {
-            const float qx = __builtin_amdgcn_fmed3f(c0x + nux, lo, hix);
-            const float qy = __builtin_amdgcn_fmed3f(c0y + nuy, lo, hiy);
-            const float fqx = floorf(qx), fqy = floorf(qy);
-            const float bxw = qx - fqx, byw = qy - fqy;
-            int ox = (int)fqx - g.r - sx0, oy = (int)fqy - g.r - sy0;
+            int ifx, ify;
+            float bxw, byw;
+            split_pos(ancx, f0x + nux, lo, hix, ifx, bxw);
+            split_pos(ancy, f0y + nuy, lo, hiy, ify, byw);
+            int ox = ifx - g.r - sx0, oy = ify - g.r - sy0;
             if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
                 __syncthreads();
                 sx0 += ox - g.M;
@@ -543,7 +580,6 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                 ox = g.M;
                 oy = g.M;
             }
-            const int ifx = (int)fqx, ify = (int)fqy;
             if (ifx != sfx || ify != sfy) {
                 const uint32_t* __restrict__ jb = jr + (oy + row0) * g.SP + soff + ox + col;
                 float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
@@ -584,22 +620,27 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         }
         if (lane == 0 && iters_out) iters_out[l] = (uint8_t)min(it, 255);
         if (l > 0) {
-            gx = 2.0f * (gx + nux);
-            gy = 2.0f * (gy + nuy);
+            carry_level(gix, gfx, nux);
+            carry_level(giy, gfy, nuy);
         }
     }
-    // level 0: flow = g + nu
-    const float fx = gx + nux, fy = gy + nuy;
-    const float nx = ux + fx, ny = uy + fy;
+    // level 0: next = u + g + nu = floor(u) + gi + (frac(u) + gf + nu), one rounding
+    const float fu0x = floorf(ux), fu0y = floorf(uy);
+    const int fix0 = (int)fu0x + gix, fiy0 = (int)fu0y + giy;
+    const float ffx0 = ((ux - fu0x) + gfx) + nux, ffy0 = ((uy - fu0y) + gfy) + nuy;
+    const float nx = (float)((double)fix0 + (double)ffx0);
+    const float ny = (float)((double)fiy0 + (double)ffy0);
     res.nx = nx;
     res.ny = ny;
     if (!(nx >= 0.0f && ny >= 0.0f && nx <= (float)(W0 - 1) && ny <= (float)(H0 - 1))) return res;
 
     // ---- err: mean |I - J| over the level-0 window at the final position
     {
-        const float fqx = floorf(nx), fqy = floorf(ny);
-        const float bxw = nx - fqx, byw = ny - fqy;
-        int ox = (int)fqx - g.r - sx0, oy = (int)fqy - g.r - sy0;
+        int qx, qy;
+        float bxw, byw;
+        split_pos(fix0, ffx0, INT32_MIN / 2, INT32_MAX / 2, qx, bxw);
+        split_pos(fiy0, ffy0, INT32_MIN / 2, INT32_MAX / 2, qy, byw);
+        int ox = qx - g.r - sx0, oy = qy - g.r - sy0;
         if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
             __syncthreads();
             sx0 += ox - g.M;

@@ -20,3 +20,11 @@ def orc():
     import oracle
     oracle.build(force=not os.path.exists(oracle.LIB_PATH))
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    import parity_log
+    if parity_log.LINES:
+        terminalreporter.section("parity against the oracle")
+        for line in parity_log.LINES:
+            terminalreporter.write_line(line)

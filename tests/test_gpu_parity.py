@@ -2,12 +2,13 @@
 
 Pyramids must match bit for bit.  Lucas-Kanade (FP32 on the GPU, FP64 in the
 oracle) must agree on status for >= 99.9 % of the points, and every point
-both call tracked must lie within 0.01 px of the oracle when the two took
-the same stopping decisions (equal iteration counts at every level).  Where
-an eps test fell on different sides of the threshold in FP32 and FP64 (a
-"decision flip", <= 1 % of the points), the two runs stop one iteration
-apart and may differ by up to one more step below eps: 0.01 + eps.  Box
-updates must match within 0.01 px.
+both calls tracked must lie within 0.01 px of the oracle, whatever its
+class: converged with the same stopping decisions, a decision flip (an eps
+test on the other side of the threshold, so the runs stop one iteration
+apart), or capped (a level ran all `iters` iterations without converging).
+The classes are reported for every comparison (sizes and maxima, also in
+the session's terminal summary).  err is compared on the converged class.
+Box updates must match within 0.01 px.
 """
 import math
 
@@ -15,14 +16,16 @@ import numpy as np
 import pytest
 
 import oracle
+import parity_log
 from paper_1910_06017_amd import synth
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-FLOW_TOL = 0.01      # px, per point tracked by both
+FLOW_TOL = 0.01      # px, every point tracked by both
 STATUS_AGREE = 0.999
+ERR_TOL = 0.01       # gray levels, converged points
 
 
 @pytest.fixture(scope="module")
@@ -52,18 +55,18 @@ def run_oracle(f0, f1, pts, win, levels, iters, eps):
                            eps=float(np.float32(eps)))
 
 
-def compare(g, o, tag, flow_tol=FLOW_TOL, agree=STATUS_AGREE, err_tol=None, eps=0.01,
-            iters=30, max_flip_frac=0.01, capped_within=0.99, o_conv=None):
+def compare(g, o, tag, flow_tol=FLOW_TOL, agree=STATUS_AGREE, err_tol=ERR_TOL, eps=0.01,
+            iters=30, max_flip_frac=0.01, o_conv=None):
     """g = (next_pts, status, err[, iters, lam]) from the GPU; o = oracle result.
 
-    Points tracked by both fall in three classes: converged with the same
-    stopping decisions (every level stopped by the eps test at the same
-    iteration) -> within flow_tol; decision flips (an eps test on the other
-    side of the threshold) -> within flow_tol + eps; capped (a level ran all
-    `iters` iterations without converging: a non-contracting, chaotic
-    trajectory) -> at least `capped_within` of them within flow_tol.  With
-    eps = 0 every level runs `iters`; `o_conv` (oracle run with eps 0.01 did
-    not hit the cap) then marks the converged points."""
+    Every point tracked by both must lie within flow_tol.  The points fall in
+    three reported classes: converged with the same stopping decisions
+    (every level stopped by the eps test at the same iteration), decision
+    flips (an eps test on the other side of the threshold; at most
+    max_flip_frac of the points) and capped (a level ran all `iters`
+    iterations).  With eps = 0 every level runs `iters`; `o_conv` (the
+    oracle run with eps 0.01 did not hit the cap) then marks the converged
+    points.  err must agree within err_tol on the converged class."""
     gn, gs, ge = g[0], g[1], g[2]
     n = len(gs)
     ag = (gs == o.status).mean() if n else 1.0
@@ -80,19 +83,18 @@ def compare(g, o, tag, flow_tol=FLOW_TOL, agree=STATUS_AGREE, err_tol=None, eps=
     flip = both & ~capped & ~same
     cap = both & capped
     mx = lambda m: d[m].max() if m.any() else 0.0
-    cap_ok = (d[cap] <= flow_tol).mean() if cap.any() else 1.0
-    msg = (f"{tag}: n={n} status agree={ag:.5f} tracked={both.sum()} converged={conv.sum()} "
-           f"max|d|={mx(conv):.3e}; flips={flip.sum()} max={mx(flip):.3e}; "
-           f"capped={cap.sum()} within {flow_tol}: {cap_ok:.4f} max={mx(cap):.3e}")
-    print(msg)
+    de = np.abs(ge.astype(np.float64) - o.err)
+    emx = lambda m: de[m].max() if m.any() else 0.0
+    msg = (f"{tag}: n={n} status agree={ag:.5f} tracked={both.sum()} | converged={conv.sum()} "
+           f"max={mx(conv):.2e} px | flips={flip.sum()} max={mx(flip):.2e} px | "
+           f"capped={cap.sum()} max={mx(cap):.2e} px | all max={mx(both):.2e} px (bar "
+           f"{flow_tol}) | err max converged={emx(conv):.2e} capped={emx(cap):.2e} gray")
+    parity_log.record(msg)
     assert ag >= agree, msg
-    assert mx(conv) <= flow_tol, msg
-    assert mx(flip) <= flow_tol + eps, msg
+    assert mx(both) <= flow_tol, msg
     assert flip.sum() <= max_flip_frac * max(1, both.sum()), msg
-    assert cap_ok >= capped_within, msg
-    if err_tol is not None and conv.any():
-        de = np.abs(ge[conv].astype(np.float64) - o.err[conv])
-        assert de.max() <= err_tol, f"{tag}: err max diff {de.max()}"
+    if err_tol is not None:
+        assert emx(conv) <= err_tol, msg
     assert np.all(ge[gs == 0] == -1.0)
     return d
 
@@ -148,8 +150,7 @@ def test_parity_sd_shift(ops, eps):
     w = synth.sd_shift_workload()
     g = run_gpu(ops, w.frame0, w.frame1, w.pts, w.win, w.levels, w.iters, eps)
     o = run_oracle(w.frame0, w.frame1, w.pts, w.win, w.levels, w.iters, eps)
-    compare(g, o, f"sd_shift eps={eps}", err_tol=0.01 if eps == 0 else None, eps=eps,
-            o_conv=conv_mask(w) if eps == 0 else None)
+    compare(g, o, f"sd_shift eps={eps}", eps=eps, o_conv=conv_mask(w) if eps == 0 else None)
 
 
 @pytest.mark.parametrize("eps", [0.01, 0.0])
@@ -176,8 +177,7 @@ def test_parity_window_sizes(ops, win):
     gg = run_gpu(ops, f0, f1, pts, win, 3, 20, 0.0)
     o = run_oracle(f0, f1, pts, win, 3, 20, 0.0)
     oc = run_oracle(f0, f1, pts, win, 3, 20, 0.01)
-    compare(gg, o, f"win={win}", err_tol=0.01, eps=0.0, iters=20,
-            o_conv=~(oc.iters >= 20).any(1))
+    compare(gg, o, f"win={win}", eps=0.0, iters=20, o_conv=~(oc.iters >= 20).any(1))
 
 
 def test_parity_tiny_images_and_edges(ops):
@@ -190,8 +190,7 @@ def test_parity_tiny_images_and_edges(ops):
                        np.float32)
         g = run_gpu(ops, a, b, pts, 7, 2, 10, 0.0)
         o = run_oracle(a, b, pts, 7, 2, 10, 0.0)
-        compare(g, o, f"tiny {H}x{W}", agree=1.0, flow_tol=1e-3, eps=0.0, iters=10,
-                capped_within=1.0)
+        compare(g, o, f"tiny {H}x{W}", agree=1.0, flow_tol=1e-3, eps=0.0, iters=10)
 
 
 def test_invalid_points(ops):
@@ -285,8 +284,11 @@ def test_box_update_end_to_end(ops):
     o = run_oracle(w.frame0, w.frame1, w.pts, 21, 4, 30, 0.01)
     wb, wc = oracle.box_update(w.boxes, w.box_id, w.pts, o.next_pts, o.status)
     same = oc.cpu().numpy() == wc
-    assert same.mean() >= 0.9
+    # every box median is taken over points within 0.01 px of the oracle's
     d = np.abs(ob.cpu().numpy() - wb)[same]
+    parity_log.record(f"sd_boxes box update end to end: counts equal {same.mean():.4f}, "
+                      f"max corner difference {d.max():.2e} px")
+    assert same.mean() >= 0.99
     assert d.max() <= FLOW_TOL, d.max()
 
 

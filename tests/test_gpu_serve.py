@@ -1,9 +1,12 @@
 """Serving loop on the GPU: a stream's results are the same alone and in the
-mix, served (batched) and plain (per-stream calls) agree bit for bit, and a
-small HBM budget defers admission without losing frames."""
+mix, served (batched) and plain (per-stream calls) agree bit for bit, served
+boxes match the oracle's box update on the frames whose points were just
+re-seeded, and a small HBM budget defers admission without losing frames."""
 import numpy as np
 import pytest
 
+import oracle
+import parity_log
 from paper_1910_06017_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -80,3 +83,36 @@ def test_small_budget_defers_admission(env):
                           serve.GpuExecutor(max_jobs=16, max_points=1 << 20))
     assert len(res) == len(trace)
     assert sch.used <= budget and sch.evicted
+
+
+def test_served_boxes_match_oracle(env):
+    """Frames right after a re-seed (k % 10 == 1) track known points: the
+    seeded grid of frame k-1.  Their served boxes and counts must match the
+    oracle's tracker and box update on the same frame pair: counts equal and
+    every box within 0.01 px (the per-point bar carried through the median)."""
+    serve, streams = env
+    trace = serve.make_trace(len(streams), 0.5, 25.0, seed=5)
+    res, _ = run(serve, streams, trace, serve.GpuExecutor(max_jobs=16, max_points=1 << 20))
+    checked, worst, same_counts, boxes_n = 0, 0.0, 0, 0
+    for r in res:
+        if r.k % 10 != 1:
+            continue
+        s = streams[r.sid]
+        pts, bid, bx = s.seed_points(r.k - 1, np.random.default_rng(1000 * r.sid + r.k - 1))
+        f0 = s.frames[(r.k - 1) % len(s.frames)]
+        f1 = s.frames[r.k % len(s.frames)]
+        o = oracle.lk_track(f0, f1, pts, win=21, levels=s.levels, iters=30,
+                            eps=float(np.float32(0.01)))
+        ob, oc = oracle.box_update(bx, bid, pts, o.next_pts, o.status)
+        same = r.counts == oc
+        same_counts += same.sum()
+        boxes_n += len(oc)
+        if same.any():
+            worst = max(worst, float(np.abs(r.boxes[same] - ob[same]).max()))
+        checked += 1
+    parity_log.record(f"served vs oracle: {checked} frames after a re-seed, {boxes_n} boxes, "
+                      f"counts equal {same_counts / max(1, boxes_n):.4f}, max corner "
+                      f"difference {worst:.2e} px")
+    assert checked >= len(streams)
+    assert same_counts >= 0.99 * boxes_n
+    assert worst <= 0.01
