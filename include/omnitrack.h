@@ -38,7 +38,9 @@
  *   - The library allocates no device memory, keeps no pointer after a call
  *     returns and has no global stream, handle or mutable state: calls are
  *     thread-safe and may run concurrently on different streams (each
- *     caller thread owns its own stream, the lesson of Sec. III-B).
+ *     caller thread owns its own stream, the lesson of Sec. III-B).  The one
+ *     exception is ot_box_update_scaled_noalloc, whose scratch is a static
+ *     device array per GPU shared by all its calls (see there).
  *   - The caller owns every buffer and keeps it (and any frame a pyramid
  *     aliases as its level 0) alive until the enqueued work has finished.
  */
@@ -242,6 +244,28 @@ OT_API ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t*
 
 /* Workspace bytes of ot_box_update_scaled for m boxes (0 if invalid). */
 OT_API size_t ot_box_scaled_bytes(int32_t m);
+
+/* Largest box count of ot_box_update_scaled_noalloc. */
+#define OT_SCALED_NOALLOC_MAX_BOXES 64
+
+/* ot_box_update_scaled for callers that cannot allocate device memory (code
+ * under HIP graph capture, allocation-free serving loops): the same
+ * arguments, results and errors without ws/ws_bytes.  The per-box scratch is
+ * a static device array inside the library, OT_SCALED_NOALLOC_MAX_BOXES x
+ * ot_box_scaled_bytes(1) bytes (8.1 MB), of which each GPU the library runs
+ * on holds its own copy until the process ends; the call allocates nothing.
+ * Its device address is looked up once per device, on the first call that
+ * targets it (the device of `stream`, or the current device for NULL).
+ * Every call rewrites the scratch it uses from scratch, but all calls on one
+ * GPU share the one array: calls whose work overlaps in time on one GPU
+ * (different streams, several host threads) race and must be serialised by
+ * the caller.  Errors: as ot_box_update_scaled, plus OT_E_INVAL for m >
+ * OT_SCALED_NOALLOC_MAX_BOXES (nothing enqueued) and OT_E_LAUNCH when the
+ * scratch address cannot be obtained. */
+OT_API ot_err ot_box_update_scaled_noalloc(const float* boxes, int32_t m, const int32_t* box_id,
+                                           const float* pts, const float* next_pts,
+                                           const uint8_t* status, int32_t n, float* out_boxes,
+                                           int32_t* out_count, float* out_scale, void* stream);
 
 /* ------------------------------------------------------------------------
  * Matching and update phases (Sec. V-A): the predicted scene objects S_t

@@ -250,6 +250,22 @@ ot_err ot_box_update_scaled(const float* boxes, int32_t m, const int32_t* box_id
     return OT_OK;
 }
 
+ot_err ot_box_update_scaled_noalloc(const float* boxes, int32_t m, const int32_t* box_id,
+                                    const float* pts, const float* next_pts, const uint8_t* status,
+                                    int32_t n, float* out_boxes, int32_t* out_count,
+                                    float* out_scale, void* stream) {
+    if (m < 0 || n < 0 || m > OT_SCALED_NOALLOC_MAX_BOXES) return OT_E_INVAL;
+    if (m == 0) return OT_OK;
+    if (!boxes || !out_boxes || !out_count || !out_scale) return OT_E_INVAL;
+    if (n > 0 && (!box_id || !pts || !next_pts || !status)) return OT_E_INVAL;
+    if (((uintptr_t)pts | (uintptr_t)next_pts) & 7) return OT_E_INVAL;
+    if (launch_box_scaled_noalloc(boxes, m, box_id, pts, next_pts, status, n, out_boxes,
+                                  out_count, out_scale,
+                                  static_cast<hipStream_t>(stream)) != hipSuccess)
+        return OT_E_LAUNCH;
+    return OT_OK;
+}
+
 // ------------------------------------------------------------------ batched
 static bool cfg_valid(const ot_batch_cfg* c) {
     return c && c->max_jobs >= 1 && c->max_points >= 0 && c->max_boxes >= 0 &&

@@ -31,6 +31,12 @@ hipError_t launch_box_scaled(const float* boxes, int m, const int32_t* box_id, c
                              int32_t* out_count, float* out_scale, void* ws, hipStream_t stream);
 // Workspace of the scaled update for m boxes (one block per box).
 size_t box_scaled_ws_bytes(int m);
+// The scaled update on the library's static per-device scratch
+// (m <= OT_SCALED_NOALLOC_MAX_BOXES, checked by the caller).
+hipError_t launch_box_scaled_noalloc(const float* boxes, int m, const int32_t* box_id,
+                                     const float* pts, const float* next_pts,
+                                     const uint8_t* status, int n, float* out_boxes,
+                                     int32_t* out_count, float* out_scale, hipStream_t stream);
 hipError_t launch_fb_gate(const float* pts, const float* back_pts, const uint8_t* st_fwd,
                           const uint8_t* st_bwd, int n, float fb_max, float* fb_err,
                           uint8_t* status_out, hipStream_t stream);

@@ -1,5 +1,7 @@
 // ot_misc.hip -- pyramid reduce and box-median kernels for gfx950, single and
 // batched forms.
+#include <mutex>
+
 #include "ot_box.hpp"
 #include "ot_pyr.hpp"
 #include "ot_launch.hpp"
@@ -152,6 +154,56 @@ hipError_t launch_box_scaled(const float* boxes, int m, const int32_t* box_id, c
     hipLaunchKernelGGL(k_scaled_final, dim3(m), dim3(BOX_THREADS), 0, stream, boxes, out_boxes,
                        out_count, out_scale, w);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free scaled update: a static device array (one
+// copy per GPU).  Host code never passes `scratch` itself to a kernel -- on
+// the host that name is only a stand-in for the symbol -- but the device
+// address hipGetSymbolAddress returns for it, looked up once per device with
+// that device current.
+static __device__ __align__(256) ScaleWs scratch[OT_SCALED_NOALLOC_MAX_BOXES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_addr[SCRATCH_DEVICES] = {};
+
+hipError_t scratch_for_stream(hipStream_t stream, void** out) {
+    hipDevice_t dev = -1;
+    hipError_t e = hipStreamGetDevice(stream, &dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        int cur = -1;
+        if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_addr[dev] = p;
+    }
+    *out = scratch_addr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_box_scaled_noalloc(const float* boxes, int m, const int32_t* box_id,
+                                     const float* pts, const float* next_pts,
+                                     const uint8_t* status, int n, float* out_boxes,
+                                     int32_t* out_count, float* out_scale, hipStream_t stream) {
+    if (m < 1 || m > OT_SCALED_NOALLOC_MAX_BOXES) return hipErrorInvalidValue;
+    void* ws = nullptr;
+    const hipError_t e = scratch_for_stream(stream, &ws);
+    if (e != hipSuccess) return e;
+    // the kernels clear the per-box counters and histograms they use
+    return launch_box_scaled(boxes, m, box_id, pts, next_pts, status, n, out_boxes, out_count,
+                             out_scale, ws, stream);
 }
 
 constexpr int FB_THREADS = 256;

@@ -23,6 +23,7 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 # Every symbol the header declares.
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
            "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled", "ot_box_scaled_bytes",
+           "ot_box_update_scaled_noalloc",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
            "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_box_mean_flow",
            "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_strerror", "ot_version"]
@@ -108,6 +109,8 @@ def lib():
         L.ot_box_update_scaled.restype = i32
         L.ot_box_scaled_bytes.argtypes = [i32]
         L.ot_box_scaled_bytes.restype = sz
+        L.ot_box_update_scaled_noalloc.argtypes = [P, i32, P, P, P, P, i32, P, P, P, P]
+        L.ot_box_update_scaled_noalloc.restype = i32
         L.ot_tvl1_default_params.argtypes = [C.POINTER(OtTvl1Params)]
         L.ot_tvl1_default_params.restype = None
         L.ot_tvl1_bytes.argtypes = [i32, i32]
@@ -345,6 +348,32 @@ def box_update_scaled(boxes, box_id, pts, next_pts, status, out=None, ws=None, s
                                      _ptr(status), n, _ptr(ob), _ptr(oc), _ptr(os_), _ptr(ws),
                                      ws.numel() * ws.element_size(), _stream_handle(stream)),
           "ot_box_update_scaled")
+    return ob, oc, os_
+
+
+# Largest box count of the allocation-free scaled update.
+SCALED_NOALLOC_MAX_BOXES = 64
+
+
+def box_update_scaled_noalloc(boxes, box_id, pts, next_pts, status, out, stream=None):
+    """box_update_scaled on the library's static device scratch: nothing is
+    allocated, so the outputs (out_boxes m x 4, out_count m, out_scale m)
+    must be given.  Calls on one GPU share the scratch: serialise them."""
+    torch = _torch()
+    _need(boxes, torch.float32, 4, "boxes")
+    _need(pts, torch.float32, 2, "pts")
+    _need(next_pts, torch.float32, 2, "next_pts")
+    _need(box_id, torch.int32, None, "box_id")
+    _need(status, torch.uint8, None, "status")
+    m, n = boxes.shape[0], pts.shape[0]
+    if next_pts.shape[0] != n or box_id.numel() != n or status.numel() != n:
+        raise ValueError("box_update_scaled_noalloc: pts, next_pts, box_id and status must hold "
+                         "n points")
+    ob, oc, os_ = out
+    check(lib().ot_box_update_scaled_noalloc(_ptr(boxes), m, _ptr(box_id), _ptr(pts),
+                                             _ptr(next_pts), _ptr(status), n, _ptr(ob), _ptr(oc),
+                                             _ptr(os_), _stream_handle(stream)),
+          "ot_box_update_scaled_noalloc")
     return ob, oc, os_
 
 

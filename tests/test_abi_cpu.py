@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 22
+    assert len(syms) == 23
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -186,6 +186,24 @@ def test_box_scaled_validation(L):
     assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, ws + 16, need, None) == Wk
     assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None, need, None) == Wk
     assert u(None, 0, None, None, None, None, 5, None, None, None, None, 0, None) == 0
+
+
+def test_box_scaled_noalloc_validation(L):
+    """Argument errors of the allocation-free form return before any device
+    call: too many boxes for the static scratch, negative counts, nulls,
+    misalignment; m == 0 is a no-op."""
+    E = ops_err("OT_E_INVAL")
+    u = L.ot_box_update_scaled_noalloc
+    mx = ops.SCALED_NOALLOC_MAX_BOXES
+    txt = open(HEADER).read()
+    assert re.search(r"#define OT_SCALED_NOALLOC_MAX_BOXES (\d+)", txt).group(1) == str(mx)
+    assert u(FAKE, mx + 1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None) == E
+    assert u(FAKE, -1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, -5, FAKE, FAKE, FAKE, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None, None) == E
+    assert u(FAKE, 3, None, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None) == E
+    assert u(FAKE, 3, FAKE, FAKE, FAKE + 4, FAKE, 5, FAKE, FAKE, FAKE, None) == E
+    assert u(None, 0, None, None, None, None, 5, None, None, None, None) == 0
 
 
 def test_scale_cap_matches_header():
