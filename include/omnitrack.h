@@ -419,6 +419,10 @@ typedef struct {
     int32_t exact_grids;   /* nonzero: size every launch from the packed table's totals
                               (read from table_host) instead of the capacities -- for
                               eager ticks; a captured graph needs capacity-sized grids */
+    int32_t lk_wpg;        /* waves per workgroup of the tracking stage (0 or 1, 2, 4) */
+    int32_t lk_ppw;        /* points each wave tracks one after the other (0 or 1, 2, 4);
+                              wpg or ppw above 1 need the 21 x 21 window at margin 4 or 6
+                              and lk_waves == 0 (else OT_E_UNSUPPORTED) */
 } ot_batch_cfg;
 
 /* Bytes of the descriptor table for cfg's capacities (0 if invalid). */
@@ -438,6 +442,22 @@ OT_API ot_err ot_batch_pack(const ot_job* jobs, int32_t njobs, const ot_batch_cf
  * Errors: OT_E_INVAL, OT_E_WORKSPACE, OT_E_LAUNCH. */
 OT_API ot_err ot_batch_run(const void* table_host, void* table_dev, size_t table_bytes,
                     const ot_batch_cfg* cfg, void* stream);
+
+/* Stages of ot_batch_run_stages (bit mask). */
+#define OT_STAGE_PYRAMID 1 /* copy the table to table_dev, build every job's next pyramid */
+#define OT_STAGE_TRACK 2   /* track every job's points, update every job's boxes */
+
+/* ot_batch_run split in two stages, so that a caller can run one tick's
+ * preprocessing on one stream while an earlier tick is tracked on another
+ * (the prefetch of Sec. V-B).  stages = OT_STAGE_PYRAMID | OT_STAGE_TRACK is
+ * ot_batch_run.  OT_STAGE_TRACK alone reads the table that an earlier
+ * OT_STAGE_PYRAMID call copied into the same table_dev; the caller orders
+ * the two (e.g. an event recorded after the first and waited on the second
+ * stream) and keeps table_host and table_dev unchanged until both stages
+ * have run.  Arguments and errors as ot_batch_run, plus OT_E_INVAL for an
+ * empty or unknown stage mask. */
+OT_API ot_err ot_batch_run_stages(const void* table_host, void* table_dev, size_t table_bytes,
+                                  const ot_batch_cfg* cfg, int32_t stages, void* stream);
 
 /* Static text for an error code. */
 OT_API const char* ot_strerror(ot_err e);

@@ -61,6 +61,8 @@ class BatchConfig:
     margin: int = 0
     lk_waves: int = 0          # 0: one wave per point; >0: persistent grid of this many waves
     chunk: int = 1
+    lk_wpg: int = 1            # waves per workgroup of the tracking stage (1, 2, 4)
+    lk_ppw: int = 1            # points each wave tracks in turn (1, 2, 4)
     max_jobs: int = 64
     max_points: int = 1 << 20
     max_boxes: int = 4096
@@ -72,10 +74,11 @@ class BatchConfig:
         return ops.OtBatchCfg(self.win, self.iters, self.eps, self.min_eig, self.margin,
                               self.lk_waves, self.chunk, self.max_jobs, self.max_points,
                               self.max_boxes, self.max_tiles, self.max_levels,
-                              int(self.exact_grids))
+                              int(self.exact_grids), self.lk_wpg, self.lk_ppw)
 
     def schedule(self) -> dict:
-        return {"margin": self.margin, "lk_waves": self.lk_waves, "chunk": self.chunk}
+        return {"margin": self.margin, "lk_waves": self.lk_waves, "chunk": self.chunk,
+                "lk_wpg": self.lk_wpg, "lk_ppw": self.lk_ppw}
 
 
 def _ptr(t):
@@ -189,14 +192,26 @@ class BatchRunner:
 _DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
-def default_schedule(key: str) -> dict:
+def default_schedule(key: str, grads: bool | None = None) -> dict:
     """Tuned schedule for a shape bucket from the packaged cache (nearest
-    point bucket), else one wave per point with the default margin."""
+    point bucket), else one wave per point with the default margin.  For the
+    single-call tracker, `grads` False/True restricts the choice to gradients
+    computed in the tracker / read from materialized planes."""
     if os.path.exists(_DEFAULT_CACHE):
         with open(_DEFAULT_CACHE) as f:
             cache = json.load(f)
+
+        def pick(rec):
+            if grads is None or "all" not in rec:
+                return dict(rec["schedule"])
+            ok = [r for r in rec["all"] if bool(r.get("grads", False)) == grads]
+            if not ok:
+                return dict(rec["schedule"])
+            best = min(ok, key=lambda r: r["ms"])
+            return {k: v for k, v in best.items() if k != "ms"}
+
         if key in cache:
-            return dict(cache[key]["schedule"])
+            return pick(cache[key])
         single = key.startswith("single_")
         cands = [k for k in cache if k.startswith("single_") == single]
         if cands:
@@ -204,8 +219,9 @@ def default_schedule(key: str) -> dict:
                 return int(k.split("_")[-2][1:])
             want = pts(key)
             best = min(cands, key=lambda k: abs(math.log2(pts(k)) - math.log2(want)))
-            return dict(cache[best]["schedule"])
-    return {"margin": 0} if key.startswith("single_") else {"margin": 0, "lk_waves": 0, "chunk": 1}
+            return pick(cache[best])
+    return ({"margin": 0} if key.startswith("single_") else
+            {"margin": 0, "lk_waves": 0, "chunk": 1, "lk_wpg": 1, "lk_ppw": 1})
 
 
 def bucket_key(jobs: list) -> str:
@@ -215,16 +231,29 @@ def bucket_key(jobs: list) -> str:
     return f"p{1 << max(0, math.ceil(math.log2(max(pts, 1))))}_L{max(j.levels for j in jobs)}"
 
 
+def schedule_space() -> list:
+    """Tracking schedules of the batched tick: LDS margin x {waves per
+    workgroup x points per wave, one point per wave each, or a persistent
+    grid claiming chunks of points}.  Several waves or points per workgroup
+    exist for the 21 x 21 window at margins 4 and 6."""
+    out = []
+    for m in (2, 3, 4, 6):
+        shapes = [(1, 1)]
+        if m in (4, 6):
+            shapes = [(w, p) for w in (1, 2, 4) for p in (1, 2, 4)]
+        for (w, p) in shapes:
+            out.append({"margin": m, "lk_waves": 0, "chunk": 1, "lk_wpg": w, "lk_ppw": p})
+        for (w, c) in ((4096, 1), (4096, 4), (8192, 2)):
+            out.append({"margin": m, "lk_waves": w, "chunk": c, "lk_wpg": 1, "lk_ppw": 1})
+    return out
+
+
 @dataclass
 class Autotuner:
     """Times candidate tracking schedules on a tick and caches the best."""
 
     path: str | None = None
-    candidates: list = field(default_factory=lambda: [
-        {"margin": m, "lk_waves": w, "chunk": c}
-        for m in (2, 3, 4, 6)
-        for (w, c) in ((0, 1), (4096, 1), (4096, 4), (8192, 2))
-    ])
+    candidates: list = field(default_factory=schedule_space)
     cache: dict = field(default_factory=dict)
 
     def __post_init__(self):

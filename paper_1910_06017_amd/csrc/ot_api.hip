@@ -270,7 +270,7 @@ ot_err ot_box_update_scaled_noalloc(const float* boxes, int32_t m, const int32_t
 static bool cfg_valid(const ot_batch_cfg* c) {
     return c && c->max_jobs >= 1 && c->max_points >= 0 && c->max_boxes >= 0 &&
            c->max_tiles >= 0 && c->max_levels >= 1 && c->max_levels <= OT_MAX_LEVELS &&
-           c->lk_waves >= 0 && c->chunk >= 0;
+           c->lk_waves >= 0 && c->chunk >= 0 && c->lk_wpg >= 0 && c->lk_ppw >= 0;
 }
 
 size_t ot_batch_table_bytes(const ot_batch_cfg* cfg) {
@@ -386,37 +386,53 @@ ot_err ot_batch_pack(const ot_job* jobs, int32_t njobs, const ot_batch_cfg* cfg,
     return OT_OK;
 }
 
-ot_err ot_batch_run(const void* table_host, void* table_dev, size_t table_bytes,
-                    const ot_batch_cfg* cfg, void* stream) {
+ot_err ot_batch_run_stages(const void* table_host, void* table_dev, size_t table_bytes,
+                           const ot_batch_cfg* cfg, int32_t stages, void* stream) {
     if (!cfg_valid(cfg) || !table_host || !table_dev) return OT_E_INVAL;
+    if (stages < 1 || stages > (OT_STAGE_PYRAMID | OT_STAGE_TRACK)) return OT_E_INVAL;
     const TableLayout T = TableLayout::make(cfg->max_jobs);
     if (table_bytes < T.bytes || ((uintptr_t)table_dev & 255) != 0) return OT_E_WORKSPACE;
     LkParams prm;
     const ot_err e = lk_params(cfg->win, 1, cfg->iters, cfg->eps, cfg->min_eig, cfg->margin, &prm);
     if (e != OT_OK) return e;
+    const int wpg = cfg->lk_wpg > 0 ? cfg->lk_wpg : 1, ppw = cfg->lk_ppw > 0 ? cfg->lk_ppw : 1;
+    if (!batch_lk_shape_ok(prm.win, prm.margin, wpg, ppw) ||
+        (cfg->lk_waves > 0 && (wpg != 1 || ppw != 1)))
+        return OT_E_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (hipMemcpyAsync(table_dev, table_host, T.bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-        return OT_E_LAUNCH;
     const uint8_t* tdev = static_cast<const uint8_t*>(table_dev);
     // grid sizes: the capacities (graph-capturable), or the packed totals
     TableHdr hd;
     memcpy(&hd, table_host, sizeof(hd));
     const bool exact = cfg->exact_grids != 0;
-    for (int l0 = 0; l0 < cfg->max_levels - 1; l0 += PYR_FUSE) {
-        const int grid = exact ? hd.total_tiles[l0 + 1] : cfg->max_tiles;
-        if (grid > 0 && launch_batch_pyr(tdev, cfg->max_jobs, l0, grid, s) != hipSuccess)
+    if (stages & OT_STAGE_PYRAMID) {
+        if (hipMemcpyAsync(table_dev, table_host, T.bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return OT_E_LAUNCH;
+        for (int l0 = 0; l0 < cfg->max_levels - 1; l0 += PYR_FUSE) {
+            const int grid = exact ? hd.total_tiles[l0 + 1] : cfg->max_tiles;
+            if (grid > 0 && launch_batch_pyr(tdev, cfg->max_jobs, l0, grid, s) != hipSuccess)
+                return OT_E_LAUNCH;
+        }
+    }
+    if (stages & OT_STAGE_TRACK) {
+        const bool persistent = cfg->lk_waves > 0;
+        const int npts = exact ? hd.total_pts : cfg->max_points;
+        const int lk_waves = persistent && !(exact && hd.total_pts == 0) ? cfg->lk_waves : 0;
+        if ((persistent ? lk_waves : npts) > 0 &&
+            launch_batch_lk(tdev, cfg->max_jobs, prm.win, prm.margin, npts, lk_waves, wpg, ppw,
+                            s) != hipSuccess)
+            return OT_E_LAUNCH;
+        const int grid = exact ? hd.total_boxes : cfg->max_boxes;
+        if (grid > 0 && launch_batch_box(tdev, cfg->max_jobs, grid, s) != hipSuccess)
             return OT_E_LAUNCH;
     }
-    const bool persistent = cfg->lk_waves > 0;
-    int grid = persistent ? cfg->lk_waves : (exact ? hd.total_pts : cfg->max_points);
-    if (persistent && exact && hd.total_pts == 0) grid = 0;
-    if (grid > 0 &&
-        launch_batch_lk(tdev, cfg->max_jobs, prm.win, prm.margin, grid, persistent, s) != hipSuccess)
-        return OT_E_LAUNCH;
-    grid = exact ? hd.total_boxes : cfg->max_boxes;
-    if (grid > 0 && launch_batch_box(tdev, cfg->max_jobs, grid, s) != hipSuccess)
-        return OT_E_LAUNCH;
     return OT_OK;
+}
+
+ot_err ot_batch_run(const void* table_host, void* table_dev, size_t table_bytes,
+                    const ot_batch_cfg* cfg, void* stream) {
+    return ot_batch_run_stages(table_host, table_dev, table_bytes, cfg,
+                               OT_STAGE_PYRAMID | OT_STAGE_TRACK, stream);
 }
 
 const char* ot_strerror(ot_err e) {

@@ -129,11 +129,11 @@ struct TableLayout {
 
 // Rows per lane strip for a window: the wave's 64 lanes cover the window as
 // win columns x nseg row segments of `rows` rows.
-OT_HD inline int lk_nseg(int win) {
+OT_HD constexpr int lk_nseg(int win) {
     int s = 64 / win;
     return s < 1 ? 1 : (s > win ? win : s);
 }
-OT_HD inline int lk_rows_needed(int win) {
+OT_HD constexpr int lk_rows_needed(int win) {
     int s = lk_nseg(win);
     return (win + s - 1) / s;
 }
@@ -144,7 +144,7 @@ OT_HD inline int lk_rows_needed(int win) {
 // with a margin on every side, rows padded to whole 16-byte groups from the
 // 4-byte aligned column at or below the region), followed by the level-0
 // template samples (R floats per lane, kept for the residual).
-OT_HD inline size_t lk_lds_a_offset(int win, int R, int margin) {
+OT_HD constexpr size_t lk_lds_a_offset(int win, int R, int margin) {
     const int nseg = lk_nseg(win);
     const int RR = nseg * R + 1, TW = win + 1, PW = 4 * (((TW + 4) >> 2) + 1);
     const int ncg = 64 / TW, GR = (RR + ncg - 1) / ncg, GRR = ncg * GR;  // GRR >= RR
@@ -154,7 +154,7 @@ OT_HD inline size_t lk_lds_a_offset(int win, int R, int margin) {
     const size_t iter = (size_t)(RR + 2 * margin) * SP * 4;
     return ((setup > iter ? setup : iter) + 15) & ~(size_t)15;
 }
-OT_HD inline size_t lk_lds_bytes(int win, int R, int margin) {
+OT_HD constexpr size_t lk_lds_bytes(int win, int R, int margin) {
     return lk_lds_a_offset(win, R, margin) + (size_t)64 * R * 4;
 }
 

@@ -18,6 +18,22 @@ __device__ __forceinline__ int udiv_small(int a, int b) {
     return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
 }
 
+// Raw buffer view of a byte plane: loads take 32-bit byte offsets (no 64-bit
+// address arithmetic per lane) and return 0 past `bytes`.  `p` and `bytes`
+// must be wave-uniform (the descriptor lives in scalar registers).
+typedef __amdgpu_buffer_rsrc_t plane_t;
+
+__device__ __forceinline__ plane_t plane_rsrc(const uint8_t* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+__device__ __forceinline__ uint32_t plane_dword(plane_t r, uint32_t off) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+__device__ __forceinline__ uint32_t plane_byte(plane_t r, uint32_t off) {
+    return (uint32_t)(uint8_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+}
+
 __device__ __forceinline__ float uniform_f(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }

@@ -43,8 +43,13 @@ hipError_t launch_fb_gate(const float* pts, const float* back_pts, const uint8_t
 
 // Batched stages over a device table (layout TableLayout::make(cap)).
 hipError_t launch_batch_pyr(const uint8_t* table, int cap, int l0, int grid, hipStream_t stream);
-hipError_t launch_batch_lk(const uint8_t* table, int cap, int win, int margin, int grid,
-                           bool persistent, hipStream_t stream);
+// Tracking stage: a persistent grid of lk_waves waves (lk_waves > 0), else
+// npts points in workgroups of wpg waves tracking ppw points each.
+hipError_t launch_batch_lk(const uint8_t* table, int cap, int win, int margin, int npts,
+                           int lk_waves, int wpg, int ppw, hipStream_t stream);
+// 1 if the tracking stage has an instantiation for this window, margin and
+// (wpg, ppw) (1 x 1 always; 2 and 4 for the 21 x 21 window at margins 4, 6).
+int batch_lk_shape_ok(int win, int margin, int wpg, int ppw);
 hipError_t launch_batch_box(const uint8_t* table, int cap, int grid, hipStream_t stream);
 
 }  // namespace ot

@@ -8,6 +8,10 @@
 #ifndef OT_STAGE_BATCH
 #define OT_STAGE_BATCH 4
 #endif
+// Rows of the target region each lane loads per batch on the in-frame path.
+#ifndef OT_TARGET_BATCH
+#define OT_TARGET_BATCH 4
+#endif
 
 namespace ot {
 
@@ -120,6 +124,7 @@ __device__ __forceinline__ float blend_sums(float j0, float d0, float jd, float 
 __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int w, int h, int jp,
                                              int sx0, int sy0, int SR, int SC, int SP,
                                              uint32_t* __restrict__ jr, int lane) {
+    const plane_t J = plane_rsrc(Jl, (uint32_t)jp * (uint32_t)h);
     const int a0 = sx0 & ~3;
     const int nd = ((sx0 + SC - a0) >> 2) + 1;  // dwords covering columns a0 .. sx0+SC
     const bool fast = a0 >= 0 && sy0 >= 0 && a0 + 4 * nd <= w && sy0 + SR <= h &&
@@ -127,25 +132,24 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
     if (fast) {
         // one dword (4 pixels) per lane and row; the fifth pixel of the last
         // entry comes from the next lane (junk for the row's last dword, whose
-        // last entry lies past column SC - 1 and is never read)
+        // last entry lies past column SC - 1 and is never read).  Loads of rows
+        // past the region are not predicated: they stay inside the plane or
+        // read 0, and are never stored.
         const int rps = udiv_small(64, nd);
         const int lr = udiv_small(lane, nd), kk = lane - lr * nd;
         const bool lane_ok = lr < rps;
         const int steps = udiv_small(SR + rps - 1, rps);
-        const uint8_t* __restrict__ base = Jl + (size_t)sy0 * jp + a0 + 4 * kk;
+        const uint32_t dstep = (uint32_t)(rps * jp);
+        uint32_t off = (uint32_t)((sy0 + lr) * jp + a0 + 4 * kk);
         uint32_t* __restrict__ dst = jr + lr * SP + 4 * kk;
+constexpr int TB = OT_TARGET_BATCH;
 #pragma unroll 1
-        for (int s0 = 0; s0 < steps; s0 += 8) {
-            uint32_t v[8];
+        for (int s0 = 0; s0 < steps; s0 += TB) {
+            uint32_t v[TB];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int rr = lr + (s0 + s) * rps;
-                v[s] = (lane_ok && rr < SR)
-                           ? *reinterpret_cast<const uint32_t*>(base + (size_t)rr * jp)
-                           : 0u;
-            }
+            for (int s = 0; s < TB; ++s) v[s] = plane_dword(J, off + (uint32_t)s * dstep);
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
+            for (int s = 0; s < TB; ++s) {
                 const uint32_t nx = __shfl_down(v[s], 1, 64);
                 const int rr = lr + (s0 + s) * rps;
                 if (lane_ok && rr < SR) {
@@ -160,6 +164,7 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
                     *reinterpret_cast<uint4*>(dst + (s0 + s) * rps * SP) = q;
                 }
             }
+            off += (uint32_t)TB * dstep;
         }
     } else {
         const int off = sx0 - a0;
@@ -173,13 +178,11 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
 #pragma unroll
             for (int s = 0; s < OT_STAGE_BATCH; ++s) {
                 idx[s] = -1;
-                p0[s] = p1[s] = 0;
-                if (kb + s < nk && r < SR) {
-                    const uint8_t* row = Jl + (size_t)clampi(sy0 + r, 0, h - 1) * jp;
-                    p0[s] = row[clampi(sx0 + c, 0, w - 1)];
-                    p1[s] = row[clampi(sx0 + c + 1, 0, w - 1)];
-                    idx[s] = r * SP + off + c;
-                }
+                // clamped (always in-plane) offsets, loaded unpredicated
+                const uint32_t row = (uint32_t)(clampi(sy0 + r, 0, h - 1) * jp);
+                p0[s] = plane_byte(J, row + (uint32_t)clampi(sx0 + c, 0, w - 1));
+                p1[s] = plane_byte(J, row + (uint32_t)clampi(sx0 + c + 1, 0, w - 1));
+                if (kb + s < nk && r < SR) idx[s] = r * SP + off + c;
                 c += dc;
                 r += dr;
                 if (c >= SC) {
@@ -203,6 +206,7 @@ __device__ __forceinline__ void stage_target(const uint8_t* __restrict__ Jl, int
 __device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int w, int h, int ip,
                                             int x0, int y0, const LkGeom& g,
                                             uint8_t* __restrict__ patch, int lane) {
+    const plane_t I = plane_rsrc(Il, (uint32_t)ip * (uint32_t)h);
     const int xs = x0 - 1, ys = y0 - 1;
     const int a0 = xs & ~3;
     const int nd = ((x0 + g.TW - a0) >> 2) + 1;  // dwords covering a0 .. x0+TW
@@ -213,23 +217,20 @@ __device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int 
         const int lr = udiv_small(lane, nd), kk = lane - lr * nd;
         const bool lane_ok = lr < rps;
         const int steps = udiv_small(g.PR + rps - 1, rps);
-        const uint8_t* __restrict__ base = Il + (size_t)ys * ip + a0 + 4 * kk;
+        const uint32_t dstep = (uint32_t)(rps * ip);
+        uint32_t off = (uint32_t)((ys + lr) * ip + a0 + 4 * kk);
 #pragma unroll 1
-        for (int s0 = 0; s0 < steps; s0 += 8) {
-            uint32_t v[8];
+        for (int s0 = 0; s0 < steps; s0 += 4) {
+            uint32_t v[4];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int rr = lr + (s0 + s) * rps;
-                v[s] = (lane_ok && rr < g.PR)
-                           ? *reinterpret_cast<const uint32_t*>(base + (size_t)rr * ip)
-                           : 0u;
-            }
+            for (int s = 0; s < 4; ++s) v[s] = plane_dword(I, off + (uint32_t)s * dstep);
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
+            for (int s = 0; s < 4; ++s) {
                 const int rr = lr + (s0 + s) * rps;
                 if (lane_ok && rr < g.PR)
                     *reinterpret_cast<uint32_t*>(patch + rr * g.PW + 4 * kk) = v[s];
             }
+            off += 4u * dstep;
         }
     } else {
         const int cols = g.TW + 2, po = xs - a0;
@@ -243,11 +244,9 @@ __device__ __forceinline__ void stage_patch(const uint8_t* __restrict__ Il, int 
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 idx[s] = -1;
-                p[s] = 0;
-                if (kb + s < nk && r < g.PR) {
-                    p[s] = Il[(size_t)clampi(ys + r, 0, h - 1) * ip + clampi(xs + c, 0, w - 1)];
-                    idx[s] = r * g.PW + po + c;
-                }
+                p[s] = plane_byte(I, (uint32_t)(clampi(ys + r, 0, h - 1) * ip +
+                                                clampi(xs + c, 0, w - 1)));
+                if (kb + s < nk && r < g.PR) idx[s] = r * g.PW + po + c;
                 c += dc;
                 r += dr;
                 if (c >= cols) {
@@ -266,6 +265,22 @@ struct LkResult {
     float nx, ny, err;
     int status;
 };
+
+// Orders a wave's LDS writes before its later reads of them (the region a
+// wave stages is private to it).  With several waves per workgroup (WSYNC)
+// the order is kept within the wave only: the waves track different points
+// with different iteration counts and never wait on each other.  A
+// one-wave workgroup uses the workgroup barrier, which is the same thing.
+template <bool WSYNC>
+__device__ __forceinline__ void lk_sync() {
+    if constexpr (WSYNC) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
 
 // Positions are carried as an exact integer anchor plus a small float
 // offset: a level coordinate of ~2000 px held in one float has a spacing of
@@ -301,7 +316,7 @@ __device__ __forceinline__ void carry_level(int& gi, float& gf, float nu) {
 // margin are template arguments), so fixed-count loops are unrolled.
 // GRADS: the template pyramid carries materialized Scharr sums, which are
 // read (at clamped indices) instead of computed.
-template <int R, bool FIXED, bool GRADS, class PyrRef>
+template <int R, bool FIXED, bool GRADS, class PyrRef, bool WSYNC = false>
 __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, float ux, float uy,
                                              int L, int iters, float eps2, float min_eig,
                                              const LkGeom& g, unsigned char* __restrict__ smem,
@@ -355,7 +370,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
 
         // ---- template patch
         stage_patch(Il, w, h, ip, x0, y0, g, patch, lane);
-        __syncthreads();
+        lk_sync<WSYNC>();
         // ---- Scharr gradients at the tap grid: the gradient image is defined on
         // the level's pixels and read at clamped indices, so a tap outside the
         // level takes the gradient of the nearest edge pixel.  The responses are
@@ -448,7 +463,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
                 }
             }
         }
-        __syncthreads();
+        lk_sync<WSYNC>();
         // ---- bilinear template and gradients of this lane's strip
         {
             const int pcol = x0 + col - a0p;  // patch column of tap column `col`
@@ -530,7 +545,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         }
         // b comes out 32x and the tensor 1024x: 32 / det(1024 G) gives eta
         const float idet = 32.0f / (gxx * gyy - gxy * gxy);
-        __syncthreads();  // the set-up LDS is reused for the target region
+        lk_sync<WSYNC>();  // the set-up LDS is reused for the target region
 
         // Positions are clamped before the integer conversion; past the bounds
         // every tap already reads the level's edge, so the samples are unchanged.
@@ -549,7 +564,7 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             sy0 = qy - g.r - g.M;
             stage_target(Jl, w, h, jp, sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
             soff = sx0 & 3;
-            __syncthreads();
+            lk_sync<WSYNC>();
         }
         // The bilinear target at position floor + (fx, fy) blends four whole-
         // pixel samples with weights that depend only on (fx, fy), so
@@ -571,12 +586,12 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
             split_pos(ancy, f0y + nuy, lo, hiy, ify, byw);
             int ox = ifx - g.r - sx0, oy = ify - g.r - sy0;
             if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
-                __syncthreads();
+                lk_sync<WSYNC>();
                 sx0 += ox - g.M;
                 sy0 += oy - g.M;
                 stage_target(Jl, w, h, jp, sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
                 soff = sx0 & 3;
-                __syncthreads();
+                lk_sync<WSYNC>();
                 ox = g.M;
                 oy = g.M;
             }
@@ -642,12 +657,12 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         split_pos(fiy0, ffy0, INT32_MIN / 2, INT32_MAX / 2, qy, byw);
         int ox = qx - g.r - sx0, oy = qy - g.r - sy0;
         if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
-            __syncthreads();
+            lk_sync<WSYNC>();
             sx0 += ox - g.M;
             sy0 += oy - g.M;
             stage_target(Q.lvl[0], P.w[0], P.h[0], Q.pitch[0], sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
             soff = sx0 & 3;
-            __syncthreads();
+            lk_sync<WSYNC>();
             ox = g.M;
             oy = g.M;
         }

@@ -26,7 +26,8 @@ EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_t
            "ot_box_update_scaled_noalloc",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
            "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_box_mean_flow",
-           "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_strerror", "ot_version"]
+           "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_batch_run_stages",
+           "ot_strerror", "ot_version"]
 
 # Points per box the scaled box update takes (OT_SCALE_MAX_POINTS).
 SCALE_MAX_POINTS = 6144
@@ -74,7 +75,7 @@ class OtBatchCfg(C.Structure):
                 ("min_eig", C.c_float), ("margin", C.c_int32), ("lk_waves", C.c_int32),
                 ("chunk", C.c_int32), ("max_jobs", C.c_int32), ("max_points", C.c_int32),
                 ("max_boxes", C.c_int32), ("max_tiles", C.c_int32), ("max_levels", C.c_int32),
-                ("exact_grids", C.c_int32)]
+                ("exact_grids", C.c_int32), ("lk_wpg", C.c_int32), ("lk_ppw", C.c_int32)]
 
 
 _lib = None
@@ -133,6 +134,8 @@ def lib():
         L.ot_batch_pack.restype = i32
         L.ot_batch_run.argtypes = [P, P, sz, C.POINTER(OtBatchCfg), P]
         L.ot_batch_run.restype = i32
+        L.ot_batch_run_stages.argtypes = [P, P, sz, C.POINTER(OtBatchCfg), i32, P]
+        L.ot_batch_run_stages.restype = i32
         L.ot_strerror.argtypes = [i32]
         L.ot_strerror.restype = C.c_char_p
         L.ot_version.restype = i32

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 23
+    assert len(syms) == 24
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -278,6 +278,11 @@ def test_batch_run_validation(L):
     assert L.ot_batch_run(buf.ctypes.data, FAKE, nb - 256, C.byref(cfg), None) == ops_err("OT_E_WORKSPACE")
     assert L.ot_batch_run(None, FAKE, nb, C.byref(cfg), None) == ops_err("OT_E_INVAL")
     assert L.ot_batch_table_bytes(C.byref(make_cfg(max_jobs=0))) == 0
+    rs = L.ot_batch_run_stages
+    for bad in (0, 4, -1):
+        assert rs(buf.ctypes.data, FAKE, nb, C.byref(cfg), bad, None) == ops_err("OT_E_INVAL")
+    assert rs(buf.ctypes.data, FAKE + 16, nb, C.byref(cfg), 1, None) == ops_err("OT_E_WORKSPACE")
+    assert rs(None, FAKE, nb, C.byref(cfg), 2, None) == ops_err("OT_E_INVAL")
 
 
 def test_strerror(L):

@@ -60,7 +60,11 @@ def small_mix(seed=11, nstreams=7):
 
 @pytest.mark.parametrize("sched", [dict(lk_waves=0, chunk=1), dict(lk_waves=0, exact_grids=True),
                                    dict(lk_waves=600, chunk=1), dict(lk_waves=600, exact_grids=True),
-                                   dict(lk_waves=2048, chunk=3), dict(margin=2, lk_waves=0)])
+                                   dict(lk_waves=2048, chunk=3), dict(margin=2, lk_waves=0),
+                                   dict(margin=4, lk_wpg=2, lk_ppw=1),
+                                   dict(margin=4, lk_wpg=4, lk_ppw=2, exact_grids=True),
+                                   dict(margin=6, lk_wpg=1, lk_ppw=4),
+                                   dict(margin=6, lk_wpg=4, lk_ppw=4)])
 def test_batched_equals_per_stream(mods, sched):
     ops, batch = mods
     ws = small_mix()
@@ -193,3 +197,19 @@ def test_autotuner_picks_and_caches(mods, tmp_path):
     assert rec["schedule"] in tuner.candidates
     again = batch.Autotuner(path=str(tmp_path / "tune.json"))
     assert again.best(batch.bucket_key(jobs)) == rec["schedule"]
+
+
+def test_unsupported_shapes_are_rejected(mods):
+    """Several waves or points per workgroup exist for the 21 x 21 window at
+    margins 4 and 6 only, and not with the persistent grid."""
+    ops, batch = mods
+    ws = small_mix(seed=12, nstreams=2)
+    jobs = [make_job(ops, batch, w) for w in ws]
+    for sched in (dict(margin=3, lk_wpg=2), dict(margin=4, lk_wpg=3),
+                  dict(margin=4, lk_ppw=2, lk_waves=512)):
+        runner = batch.BatchRunner(batch.BatchConfig(max_jobs=16, max_points=40000,
+                                                     max_boxes=256, **sched))
+        runner.pack(jobs)
+        with pytest.raises(ops.OtError) as e:
+            runner.run()
+        assert e.value.code == -5
