@@ -80,6 +80,9 @@ def stream_footprint(spec: StreamSpec) -> int:
 class Scheduler:
     """Admission by HBM budget, continuous batching, eviction (no GPU)."""
 
+    # silence is checked at most this often (eviction waits `evict_after`, seconds)
+    EVICT_CHECK_S = 0.005
+
     def __init__(self, budget: int, max_jobs: int, max_points: int, evict_after: float = 2.0,
                  footprint=stream_footprint):
         self.budget, self.max_jobs, self.max_points = budget, max_jobs, max_points
@@ -89,10 +92,13 @@ class Scheduler:
         self.admitted: dict = {}     # sid -> bytes
         self.waiting: deque = deque()  # sids waiting for admission, FIFO
         self.queues: dict = {}       # sid -> deque of frames
+        self.nonempty: set = set()   # sids with queued frames
+        self.npending = 0
         self.last_seen: dict = {}
         self.used = 0
         self.evicted: list = []
         self.rejected: list = []
+        self._next_evict_check = -math.inf
 
     def register(self, spec: StreamSpec):
         self.specs[spec.sid] = spec
@@ -101,12 +107,16 @@ class Scheduler:
     def arrive(self, fr: Frame):
         q = self.queues[fr.sid]
         q.append(fr)
+        self.npending += 1
+        self.nonempty.add(fr.sid)
         self.last_seen[fr.sid] = fr.t_arrival
         if fr.sid not in self.admitted and fr.sid not in self.waiting:
             fp = self.footprint(self.specs[fr.sid])
             if fp > self.budget:
                 self.rejected.append(fr.sid)   # can never fit
+                self.npending -= len(q)
                 q.clear()
+                self.nonempty.discard(fr.sid)
                 return
             self.waiting.append(fr.sid)
 
@@ -125,6 +135,9 @@ class Scheduler:
         return new
 
     def evict_idle(self, now: float) -> list:
+        if now < self._next_evict_check:
+            return []
+        self._next_evict_check = now + self.EVICT_CHECK_S
         gone = []
         for sid in list(self.admitted):
             if not self.queues[sid] and now - self.last_seen.get(sid, now) > self.evict_after:
@@ -133,23 +146,40 @@ class Scheduler:
         self.evicted += gone
         return gone
 
+    def eviction_times(self, now: float) -> list:
+        """When each idle admitted stream becomes evictable (no earlier than
+        the next silence check)."""
+        return [max(self.last_seen.get(sid, now) + self.evict_after, self._next_evict_check)
+                for sid in self.admitted if not self.queues[sid]]
+
     def next_batch(self) -> list:
         """Oldest waiting frame of each admitted stream (oldest first), within
         the per-tick job and point capacities."""
-        cands = [(q[0].t_arrival, sid) for sid, q in self.queues.items()
-                 if q and sid in self.admitted]
+        cands = [(self.queues[sid][0].t_arrival, sid) for sid in self.nonempty
+                 if sid in self.admitted]
         cands.sort()
         batch, pts = [], 0
         for _, sid in cands:
             n = self.specs[sid].n_max
             if len(batch) >= self.max_jobs or pts + n > self.max_points:
                 break
-            batch.append(self.queues[sid].popleft())
+            q = self.queues[sid]
+            batch.append(q.popleft())
+            if not q:
+                self.nonempty.discard(sid)
             pts += n
+        self.npending -= len(batch)
         return batch
 
+    def requeue(self, frames: list):
+        """Put frames taken by next_batch back at the head of their queues."""
+        for fr in reversed(frames):
+            self.queues[fr.sid].appendleft(fr)
+            self.nonempty.add(fr.sid)
+            self.npending += 1
+
     def pending(self) -> int:
-        return sum(len(q) for q in self.queues.values())
+        return self.npending
 
 
 # ----------------------------------------------------------------------------- GPU side
@@ -171,6 +201,8 @@ def _hip():
 
 
 _H2D, _D2H = 1, 2
+# stages of ot_batch_run_stages
+OT_STAGE_PYRAMID, OT_STAGE_TRACK = 1, 2
 
 
 def _copy(dst: int, src: int, nbytes: int, kind: int, stream: int):
@@ -204,11 +236,16 @@ class _Arena:
 
 
 class _Slot:
-    """Resident device state of one stream: two frames, two pyramid
-    workspaces, two point buffers and two box chunks (one per frame parity),
-    plus the C job descriptors of both parities, built once."""
+    """Resident device state of one stream: three frames and pyramid
+    workspaces (frame f in buffer f % 3, so the next frame's upload and
+    pyramid can run while the current pair is tracked), two point buffers and
+    two box chunks (frame f in f % 2), and the C job descriptors of every
+    frame index mod 6, built once."""
 
-    def __init__(self, spec: StreamSpec, device, arena: _Arena):
+    NF = 3   # frame / pyramid buffers
+    NP = 2   # point / box buffers
+
+    def __init__(self, spec: StreamSpec, device, arena: _Arena, stream=None):
         import ctypes as C
 
         import torch
@@ -219,57 +256,68 @@ class _Slot:
             raise ValueError(f"stream {spec.sid}: {spec.m_max} boxes > {arena.m_chunk} per stream")
         self.spec = spec
         H, W, L = spec.H, spec.W, spec.levels
-        self.frames = [torch.empty((H, W), dtype=torch.uint8, device=device) for _ in range(2)]
-        self.ws = [ops.alloc_workspace(W, H, L, device) for _ in range(2)]
         n = max(1, spec.n_max)
-        self.pts = [torch.zeros((n, 2), dtype=torch.float32, device=device) for _ in range(2)]
-        self.status = torch.zeros(n, dtype=torch.uint8, device=device)
-        self.err = torch.zeros(n, dtype=torch.float32, device=device)
-        self.box_id = torch.full((n,), -1, dtype=torch.int32, device=device)
+        # allocated and initialised on the stream that will use them, so the
+        # fills are ordered before the first upload or re-seed
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            self.frames = [torch.empty((H, W), dtype=torch.uint8, device=device)
+                           for _ in range(self.NF)]
+            self.ws = [ops.alloc_workspace(W, H, L, device) for _ in range(self.NF)]
+            self.pts = [torch.zeros((n, 2), dtype=torch.float32, device=device)
+                        for _ in range(self.NP)]
+            self.status = torch.zeros(n, dtype=torch.uint8, device=device)
+            self.err = torch.zeros(n, dtype=torch.float32, device=device)
+            self.box_id = torch.full((n,), -1, dtype=torch.int32, device=device)
         self.arena = arena
         self.chunk = arena.take()
         c0 = self.chunk * arena.m_chunk
         self.c0 = c0
-        self.boxes = [arena.dev_boxes[p][c0:c0 + arena.m_chunk] for p in range(2)]
+        self.boxes = [arena.dev_boxes[p][c0:c0 + arena.m_chunk] for p in range(self.NP)]
         self.count = arena.dev_count[c0:c0 + arena.m_chunk]
-        self.pyr = [ops.pyramid_layout(self.frames[p], L, self.ws[p]) for p in range(2)]
-        # job[p]: the frame just uploaded is in parity p, the previous one in 1-p
+        self.pyr = [ops.pyramid_layout(self.frames[i], L, self.ws[i]) for i in range(self.NF)]
+        # job[f % 6]: frame f uploaded into buffer f % 3 (previous: (f-1) % 3),
+        # points and boxes from buffer (f-1) % 2 into f % 2
         self.job = []
-        for p in range(2):
+        for f in range(self.NF * self.NP):
             j = ops.OtJob()
-            q = 1 - p
-            j.prev = self.pyr[q].desc
-            j.next_frame = self.frames[p].data_ptr()
+            fi, fq = f % self.NF, (f - 1) % self.NF
+            p, q = f % self.NP, (f - 1) % self.NP
+            j.prev = self.pyr[fq].desc
+            j.next_frame = self.frames[fi].data_ptr()
             j.next_pitch = W
-            j.next_ws = self.ws[p].data_ptr()
-            j.next_ws_bytes = self.ws[p].numel()
+            j.next_ws = self.ws[fi].data_ptr()
+            j.next_ws_bytes = self.ws[fi].numel()
             j.levels = L
             j.pts, j.next_pts = self.pts[q].data_ptr(), self.pts[p].data_ptr()
             j.status, j.err = self.status.data_ptr(), self.err.data_ptr()
             j.boxes, j.out_boxes = self.boxes[q].data_ptr(), self.boxes[p].data_ptr()
             j.box_id, j.out_count = self.box_id.data_ptr(), self.count.data_ptr()
             self.job.append(j)
-        self.cur = 0        # parity of the last frame
-        self.started = False
+        self.f = -1         # index of the last frame submitted
         self.n = 0
         self.m = 0
         self.frames_done = 0
         self._c = C
 
+    @property
+    def started(self) -> bool:
+        return self.f >= 0
+
     def release(self):
         self.arena.give(self.chunk)
 
-    def upload(self, fr: Frame, p: int, stream: int):
+    def upload(self, fr: Frame, f: int, stream: int):
         px = fr.pixels
+        dst = self.frames[f % self.NF].data_ptr()
         if hasattr(px, "data_ptr"):
-            _copy(self.frames[p].data_ptr(), px.data_ptr(), px.numel(), _H2D, stream)
+            _copy(dst, px.data_ptr(), px.numel(), _H2D, stream)
         else:
             a = np.ascontiguousarray(px, np.uint8)
-            _copy(self.frames[p].data_ptr(), a.ctypes.data, a.nbytes, _H2D, stream)
+            _copy(dst, a.ctypes.data, a.nbytes, _H2D, stream)
 
-    def reseed(self, fr: Frame, p: int, stream: int):
-        """Detections at this frame replace the points and boxes tracked from
-        it, after the frame's own pair has been processed."""
+    def reseed(self, fr: Frame, f: int, stream: int):
+        """Detections at frame f replace the points and boxes tracked from it,
+        after the frame's own pair has been processed."""
         if fr.reseed is None:
             return
         pts, bid, bx = (np.ascontiguousarray(a) for a in fr.reseed)
@@ -279,37 +327,70 @@ class _Slot:
         pts = pts.astype(np.float32, copy=False)
         bid = bid.astype(np.int32, copy=False)
         bx = bx.astype(np.float32, copy=False)
+        p = f % self.NP
         # pageable sources: the runtime stages them before the call returns
         _copy(self.pts[p].data_ptr(), pts.ctypes.data, pts.nbytes, _H2D, stream)
         _copy(self.box_id.data_ptr(), bid.ctypes.data, bid.nbytes, _H2D, stream)
         _copy(self.boxes[p].data_ptr(), bx.ctypes.data, bx.nbytes, _H2D, stream)
         self.n, self.m = n, m
 
-    def job_for(self, p: int):
-        """C job for the frame in parity p (no points or boxes on the first frame)."""
-        j = self.job[p]
-        if not self.started:
-            j.prev = self.pyr[p].desc   # any valid descriptor: nothing is tracked
+    def job_for(self, f: int):
+        """C job for frame f (no points or boxes on the stream's first frame)."""
+        j = self.job[f % (self.NF * self.NP)]
+        if f == 0 or not self.started:
             j.n = j.m = 0
         else:
-            j.prev = self.pyr[1 - p].desc
             j.n, j.m = self.n, self.m
         return j
 
 
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
+class _Tick:
+    __slots__ = ("idx", "metas", "ev_pre", "ev_trk", "ring", "spans", "t_done")
+
+    def __init__(self, idx, metas, ev_pre, ev_trk, ring, spans):
+        self.idx, self.metas, self.ev_pre, self.ev_trk = idx, metas, ev_pre, ev_trk
+        self.ring, self.spans = ring, spans
+        self.t_done = None   # when the host saw the tick complete
+
+
 class GpuExecutor:
-    """Runs a tick of frames (at most one per stream) as one batched launch:
-    frame uploads, the table copy and the pyramid, tracking and box stages
-    (grids sized to the packed work), one copy back of every result, all on
-    one stream."""
+    """Runs ticks of frames (at most one per stream each) as batched launches,
+    with up to `depth` ticks in flight on the device.
+
+    A tick's preprocessing stage (frame uploads, the table copy, the pyramid
+    launches) runs on one HIP stream and its tracking stage (tracking, box
+    update, the copy back of the results, re-seeds) on a second one, after an
+    event of the first: tick k+1's uploads and pyramids overlap tick k's
+    tracking, and different streams' ticks overlap on the device.  Results
+    are collected by event queries (`poll`), not by blocking each tick.
+
+    Buffer reuse is ordered by events: tick k's preprocessing waits for the
+    tracking stage of tick k - depth (its device table and the frame buffers
+    it rewrites were last read there), and a stream's frame f reuses the frame
+    buffer of frame f - 3, whose last reader (the pair f-2, f-1) lies in an
+    earlier tick.  `depth=1` is the blocking loop: one tick at a time.
+
+    A tick of a single frame (most ticks at light load) goes through the
+    per-stream calls instead (`solo`): the same arithmetic without a table
+    to pack and copy, and, when nothing else is in flight, on one stream."""
 
     def __init__(self, win=21, iters=30, eps=0.01, max_jobs=64, max_points=1 << 21,
                  max_boxes=4096, max_levels=5, schedule=None, device="cuda", max_slots=128,
-                 m_chunk=64):
+                 m_chunk=64, depth=2, solo=True):
         import torch
 
-        from . import batch
+        from . import batch, ops
 
+        if depth < 1 or depth > 2:
+            raise ValueError("depth must be 1 or 2")
         self.torch = torch
         self.device = torch.device(device)
         sched = schedule or {}
@@ -317,78 +398,256 @@ class GpuExecutor:
                                      max_points=max_points, max_boxes=max_boxes,
                                      max_tiles=1 << 15, max_levels=max_levels, exact_grids=True,
                                      **sched)
-        self.runner = batch.BatchRunner(self.cfg, device=self.device, tables=1)
+        self.ccfg = self.cfg.to_c()
+        import ctypes as C
+        nb = int(ops.lib().ot_batch_table_bytes(C.byref(self.ccfg)))
+        if nb == 0:
+            raise ValueError("invalid batch configuration")
+        self.table_bytes = nb
+        self.depth = depth
+        self.solo = solo     # one-frame ticks through the per-stream calls
+        self.opts = ops.OtLkOpts(float(self.cfg.min_eig), None, None, self.cfg.margin, 0)
+        self.host_tab = [torch.empty(nb, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        self.dev_tab = [torch.empty(nb, dtype=torch.uint8, device=self.device) for _ in range(2)]
         self.arena = _Arena(torch, self.device, max_slots, m_chunk)
+        # host copies of the results of the ticks in flight (depth + 1 ring)
+        self.ring_boxes = [[torch.zeros((max_slots * m_chunk, 4), dtype=torch.float32,
+                                        pin_memory=True) for _ in range(2)]
+                           for _ in range(depth + 1)]
+        self.ring_count = [torch.zeros(max_slots * m_chunk, dtype=torch.int32, pin_memory=True)
+                           for _ in range(depth + 1)]
         self.slots: dict = {}
-        self.stream = torch.cuda.Stream(self.device)
-        self.sh = int(self.stream.cuda_stream)
+        # both streams at the default priority
+        self.s_pre = torch.cuda.Stream(self.device)
+        self.s_trk = torch.cuda.Stream(self.device)
+        self.h_pre = int(self.s_pre.cuda_stream)
+        self.h_trk = int(self.s_trk.cuda_stream)
+        self.inflight: deque = deque()
+        self.trk_events: dict = {}   # tick index -> tracking-stage event
+        self.ready: list = []        # results collected outside poll
         self.ticks = 0
+        torch.cuda.synchronize(self.device)  # the arena's fills precede both streams' work
 
+    # -------------------------------------------------------------- slots
     def admit(self, spec: StreamSpec):
-        self.slots[spec.sid] = _Slot(spec, self.device, self.arena)
+        self.slots[spec.sid] = _Slot(spec, self.device, self.arena, self.s_pre)
+        # the slot's fills (on the preprocessing stream) precede any tracking
+        self.s_trk.wait_stream(self.s_pre)
 
     def evict(self, sid: int):
         s = self.slots.pop(sid, None)
         if s is not None:
+            # results of the ticks drained here are handed out by the next poll
+            self.ready += self.drain()
             self.torch.cuda.synchronize(self.device)
             s.release()
 
-    def _launch(self, jobs):
+    # -------------------------------------------------------------- pipeline
+    def busy(self) -> bool:
+        return bool(self.inflight)
+
+    def can_submit(self) -> bool:
+        return len(self.inflight) < self.depth
+
+    def submit(self, frames: list):
+        """Enqueue one tick of frames (at most one per stream)."""
         import ctypes as C
 
         from . import ops
 
-        arr = (ops.OtJob * max(1, len(jobs)))()
-        for i, j in enumerate(jobs):
-            C.memmove(C.byref(arr, i * C.sizeof(ops.OtJob)), C.byref(j), C.sizeof(ops.OtJob))
-        ops.check(ops.lib().ot_batch_pack(arr, len(jobs), C.byref(self.runner.ccfg),
-                                          int(self.runner.host[0].data_ptr()),
-                                          self.runner.table_bytes, None), "ot_batch_pack")
-        # launches sized from the packed totals (a graph would need capacity grids)
-        ops.check(ops.lib().ot_batch_run(int(self.runner.host[0].data_ptr()),
-                                         int(self.runner.dev.data_ptr()), self.runner.table_bytes,
-                                         C.byref(self.runner.ccfg), self.sh), "ot_batch_run")
-
-    def run_tick(self, frames: list, now=time.perf_counter) -> list:
         torch = self.torch
+        if not self.can_submit():
+            raise RuntimeError("too many ticks in flight")
+        if len(frames) == 1 and self.solo:
+            self._submit_one(frames[0])
+            return
+        k = self.ticks
+        t = k % 2
+        L = ops.lib()
         metas, jobs = [], []
         for fr in frames:
             slot = self.slots[fr.sid]
-            p = 1 - slot.cur
-            slot.upload(fr, p, self.sh)
-            jobs.append(slot.job_for(p))
-            metas.append((fr, slot, p, slot.m if slot.started else 0))
-        self._launch(jobs)
+            f = slot.f + 1
+            jobs.append(slot.job_for(f))
+            metas.append((fr, slot, f, slot.m if slot.started else 0))
+        arr = (ops.OtJob * max(1, len(jobs)))()
+        for i, j in enumerate(jobs):
+            C.memmove(C.byref(arr, i * C.sizeof(ops.OtJob)), C.byref(j), C.sizeof(ops.OtJob))
+        # host table t was last copied by tick k-2, which has completed (depth <= 2)
+        ops.check(L.ot_batch_pack(arr, len(jobs), C.byref(self.ccfg),
+                                  int(self.host_tab[t].data_ptr()), self.table_bytes, None),
+                  "ot_batch_pack")
+        # ---- preprocessing stage
+        prior = self.trk_events.pop(k - self.depth, None)
+        if prior is not None:
+            self.s_pre.wait_event(prior)
+        for fr, slot, f, _ in metas:
+            slot.upload(fr, f, self.h_pre)
+        ops.check(L.ot_batch_run_stages(int(self.host_tab[t].data_ptr()),
+                                        int(self.dev_tab[t].data_ptr()), self.table_bytes,
+                                        C.byref(self.ccfg), OT_STAGE_PYRAMID, self.h_pre),
+                  "ot_batch_run_stages(pyramid)")
+        ev_pre = torch.cuda.Event()
+        ev_pre.record(self.s_pre)
+        # ---- tracking stage
+        self.s_trk.wait_event(ev_pre)
+        ops.check(L.ot_batch_run_stages(int(self.host_tab[t].data_ptr()),
+                                        int(self.dev_tab[t].data_ptr()), self.table_bytes,
+                                        C.byref(self.ccfg), OT_STAGE_TRACK, self.h_trk),
+                  "ot_batch_run_stages(track)")
+        r = k % (self.depth + 1)
         a = self.arena
-        for par in (0, 1):
-            if any(p == par for _, _, p, m in metas if m):
-                _copy(a.host_boxes[par].data_ptr(), a.dev_boxes[par].data_ptr(),
-                      a.dev_boxes[par].numel() * 4, _D2H, self.sh)
-        _copy(a.host_count.data_ptr(), a.dev_count.data_ptr(), a.dev_count.numel() * 4, _D2H,
-              self.sh)
-        for fr, slot, p, m in metas:
-            slot.reseed(fr, p, self.sh)
-        ev = torch.cuda.Event()
-        ev.record(self.stream)
-        ev.synchronize()
-        t = now()
-        out = []
-        hb = [b.numpy() for b in a.host_boxes]
-        hc = a.host_count.numpy()
-        for fr, slot, p, m in metas:
-            out.append(Result(fr.sid, fr.k, fr.t_arrival, t, hb[p][slot.c0:slot.c0 + m].copy(),
-                              hc[slot.c0:slot.c0 + m].copy(), self.ticks))
-            slot.cur = p
-            slot.started = True
-            slot.frames_done += 1
+        mc = a.m_chunk
+        spans = {}
+        for fr, slot, f, m in metas:
+            if m:
+                par = f % _Slot.NP
+                lo, hi = spans.get(par, (slot.c0, slot.c0 + mc))
+                spans[par] = (min(lo, slot.c0), max(hi, slot.c0 + mc))
+        clo = min((lo for lo, _ in spans.values()), default=0)
+        chi = max((hi for _, hi in spans.values()), default=0)
+        for par, (lo, hi) in spans.items():
+            _copy(self.ring_boxes[r][par][lo:].data_ptr(), a.dev_boxes[par][lo:].data_ptr(),
+                  (hi - lo) * 16, _D2H, self.h_trk)
+        if chi > clo:
+            _copy(self.ring_count[r][clo:].data_ptr(), a.dev_count[clo:].data_ptr(),
+                  (chi - clo) * 4, _D2H, self.h_trk)
+        for fr, slot, f, _ in metas:
+            slot.reseed(fr, f, self.h_trk)
+            slot.f = f
+        ev_trk = torch.cuda.Event()
+        ev_trk.record(self.s_trk)
+        self.trk_events[k] = ev_trk
+        self.inflight.append(_Tick(k, metas, ev_pre, ev_trk, r, spans))
         self.ticks += 1
+
+    def _submit_one(self, fr: Frame):
+        """A tick of one frame through the per-stream calls (the same kernels'
+        arithmetic, so the same results as a batched tick): no table to pack
+        and copy.  With nothing in flight every step goes on the tracking
+        stream; otherwise the upload and pyramid go on the preprocessing
+        stream, as in a batched tick."""
+        import ctypes as C
+
+        from . import ops
+
+        torch, L = self.torch, ops.lib()
+        k = self.ticks
+        slot = self.slots[fr.sid]
+        f = slot.f + 1
+        m = slot.m if slot.started else 0
+        NF, NP = _Slot.NF, _Slot.NP
+        fi, fq, p, q = f % NF, (f - 1) % NF, f % NP, (f - 1) % NP
+        sp = slot.spec
+        idle = not self.inflight
+        prior = self.trk_events.pop(k - self.depth, None)
+        s_pre, h_pre = (self.s_trk, self.h_trk) if idle else (self.s_pre, self.h_pre)
+        if prior is not None and not idle:
+            s_pre.wait_event(prior)
+        slot.upload(fr, f, h_pre)
+        d = ops.OtPyr()
+        ops.check(L.ot_pyramid_build(slot.frames[fi].data_ptr(), sp.W, sp.H, sp.W, sp.levels,
+                                     slot.ws[fi].data_ptr(), slot.ws[fi].numel(), 0, C.byref(d),
+                                     h_pre), "ot_pyramid_build")
+        ev_pre = None
+        if not idle:
+            ev_pre = torch.cuda.Event()
+            ev_pre.record(s_pre)
+            self.s_trk.wait_event(ev_pre)
+        r = k % (self.depth + 1)
+        spans = {}
+        if slot.started:
+            n = slot.n
+            ops.check(L.ot_lk_track_ex(C.byref(slot.pyr[fq].desc), C.byref(slot.pyr[fi].desc),
+                                       slot.pts[q].data_ptr(), n, self.cfg.win, sp.levels,
+                                       self.cfg.iters, self.cfg.eps, slot.pts[p].data_ptr(),
+                                       slot.status.data_ptr(), slot.err.data_ptr(),
+                                       C.byref(self.opts), self.h_trk), "ot_lk_track")
+            ops.check(L.ot_box_update(slot.boxes[q].data_ptr(), m, slot.box_id.data_ptr(),
+                                      slot.pts[q].data_ptr(), slot.pts[p].data_ptr(),
+                                      slot.status.data_ptr(), n, slot.boxes[p].data_ptr(),
+                                      slot.count.data_ptr(), self.h_trk), "ot_box_update")
+            if m:
+                _copy(self.ring_boxes[r][p][slot.c0:].data_ptr(), slot.boxes[p].data_ptr(),
+                      m * 16, _D2H, self.h_trk)
+                _copy(self.ring_count[r][slot.c0:].data_ptr(), slot.count.data_ptr(), m * 4,
+                      _D2H, self.h_trk)
+                spans[p] = (slot.c0, slot.c0 + m)
+        slot.reseed(fr, f, self.h_trk)
+        slot.f = f
+        ev_trk = torch.cuda.Event()
+        ev_trk.record(self.s_trk)
+        self.trk_events[k] = ev_trk
+        self.inflight.append(_Tick(k, [(fr, slot, f, m)], ev_pre, ev_trk, r, spans))
+        self.ticks += 1
+
+    def _collect(self, tk: _Tick, t_done: float) -> list:
+        out = []
+        hb = [b.numpy() for b in self.ring_boxes[tk.ring]]
+        hc = self.ring_count[tk.ring].numpy()
+        for fr, slot, f, m in tk.metas:
+            par = f % _Slot.NP
+            out.append(Result(fr.sid, fr.k, fr.t_arrival, t_done,
+                              hb[par][slot.c0:slot.c0 + m].copy(),
+                              hc[slot.c0:slot.c0 + m].copy(), tk.idx))
+            slot.frames_done += 1
         return out
+
+    def poll(self, now=time.perf_counter) -> list:
+        """Results of the ticks that have completed, oldest first (no wait)."""
+        out, self.ready = self.ready, []
+        while self.inflight:
+            tk = self.inflight[0]
+            if tk.t_done is None:
+                if not tk.ev_trk.query():
+                    break
+                tk.t_done = now()
+            out += self._collect(self.inflight.popleft(), tk.t_done)
+        return out
+
+    def wait_until(self, stop, now=time.perf_counter) -> None:
+        """Spin until the oldest tick in flight completes (its results are on
+        the host from that moment: the time is kept for them) or stop() is
+        true."""
+        if not self.inflight:
+            return
+        tk = self.inflight[0]
+        while tk.t_done is None:
+            if tk.ev_trk.query():
+                tk.t_done = now()
+                return
+            if stop():
+                return
+
+    def wait_oldest(self, now=time.perf_counter) -> list:
+        """Block until the oldest tick in flight completes; its results."""
+        if not self.inflight:
+            return []
+        tk = self.inflight.popleft()
+        if tk.t_done is None:
+            tk.ev_trk.synchronize()
+            tk.t_done = now()
+        return self._collect(tk, tk.t_done)
+
+    def drain(self, now=time.perf_counter) -> list:
+        out = []
+        while self.inflight:
+            out += self.wait_oldest(now)
+        return out
+
+    def run_tick(self, frames: list, now=time.perf_counter) -> list:
+        """One tick, blocking: submit and wait (results of any earlier ticks
+        in flight come first)."""
+        out = self.drain(now)
+        self.submit(frames)
+        return out + self.drain(now)
 
 
 class PlainExecutor:
     """The comparison path: each frame on its own with the per-stream calls
-    (ot_pyramid_build, ot_lk_track, ot_box_update), in arrival order, with the
-    same resident state and the same copies as the served path."""
+    (ot_pyramid_build, ot_lk_track, ot_box_update), in arrival order, on one
+    stream, waiting for each frame's boxes before the next frame starts, with
+    the same resident state and the same copies as the served path."""
 
     def __init__(self, win=21, iters=30, eps=0.01, device="cuda", max_slots=128, m_chunk=64):
         import torch
@@ -406,7 +665,7 @@ class PlainExecutor:
         self.ticks = 0
 
     def admit(self, spec: StreamSpec):
-        self.slots[spec.sid] = _Slot(spec, self.device, self.arena)
+        self.slots[spec.sid] = _Slot(spec, self.device, self.arena, self.stream)
 
     def evict(self, sid: int):
         s = self.slots.pop(sid, None)
@@ -422,19 +681,22 @@ class PlainExecutor:
         torch, L = self.torch, ops.lib()
         out = []
         a = self.arena
+        NF, NP = _Slot.NF, _Slot.NP
         for fr in frames:
             slot = self.slots[fr.sid]
-            p, q = 1 - slot.cur, slot.cur
+            f = slot.f + 1
+            fi, fq = f % NF, (f - 1) % NF
+            p, q = f % NP, (f - 1) % NP
             sp = slot.spec
-            slot.upload(fr, p, self.sh)
+            slot.upload(fr, f, self.sh)
             d = ops.OtPyr()
-            ops.check(L.ot_pyramid_build(slot.frames[p].data_ptr(), sp.W, sp.H, sp.W, sp.levels,
-                                         slot.ws[p].data_ptr(), slot.ws[p].numel(), 0,
+            ops.check(L.ot_pyramid_build(slot.frames[fi].data_ptr(), sp.W, sp.H, sp.W, sp.levels,
+                                         slot.ws[fi].data_ptr(), slot.ws[fi].numel(), 0,
                                          C.byref(d), self.sh), "ot_pyramid_build")
             m = 0
             if slot.started:
                 n, m = slot.n, slot.m
-                ops.check(L.ot_lk_track_ex(C.byref(slot.pyr[q].desc), C.byref(slot.pyr[p].desc),
+                ops.check(L.ot_lk_track_ex(C.byref(slot.pyr[fq].desc), C.byref(slot.pyr[fi].desc),
                                            slot.pts[q].data_ptr(), n, self.win, sp.levels,
                                            self.iters, self.eps, slot.pts[p].data_ptr(),
                                            slot.status.data_ptr(), slot.err.data_ptr(),
@@ -447,15 +709,16 @@ class PlainExecutor:
                       _D2H, self.sh)
                 _copy(a.host_count[slot.c0:].data_ptr(), slot.count.data_ptr(), m * 4, _D2H,
                       self.sh)
-            slot.reseed(fr, p, self.sh)
+            slot.reseed(fr, f, self.sh)
             ev = torch.cuda.Event()
             ev.record(self.stream)
-            ev.synchronize()
+            while not ev.query():   # the same host wait as the served path
+                pass
             out.append(Result(fr.sid, fr.k, fr.t_arrival, now(),
                               a.host_boxes[p].numpy()[slot.c0:slot.c0 + m].copy(),
                               a.host_count.numpy()[slot.c0:slot.c0 + m].copy(), self.ticks))
-            slot.cur = p
-            slot.started = True
+            slot.f = f
+            slot.frames_done += 1
             self.ticks += 1
         return out
 
@@ -496,6 +759,9 @@ def run_trace(trace, frame_fn, specs, scheduler: Scheduler, executor, clock=None
     gc_on = gc.isenabled()
     gc.disable()
     try:
+        if batched and hasattr(executor, "submit"):
+            return _run_trace_pipelined(trace, frame_fn, scheduler, executor, clock, sleep,
+                                        max_wall)
         return _run_trace(trace, frame_fn, scheduler, executor, clock, sleep, max_wall, batched)
     finally:
         if gc_on:
@@ -522,8 +788,7 @@ def _run_trace(trace, frame_fn, scheduler, executor, clock, sleep, max_wall, bat
         frames = scheduler.next_batch()
         if not batched:
             frames.sort(key=lambda f: f.t_arrival)
-            for f in frames[1:]:
-                scheduler.queues[f.sid].appendleft(f)
+            scheduler.requeue(frames[1:])
             frames = frames[:1]
         if frames:
             res = executor.run_tick(frames, now=lambda: clock() - t0)
@@ -533,11 +798,55 @@ def _run_trace(trace, frame_fn, scheduler, executor, clock, sleep, max_wall, bat
         # could free budget for a waiting stream
         wake = [trace[i][0]] if i < n else []
         if scheduler.waiting:
-            wake += [scheduler.last_seen.get(sid, now) + scheduler.evict_after
-                     for sid in scheduler.admitted if not scheduler.queues[sid]]
+            wake += scheduler.eviction_times(now)
         if not wake:
             break  # frames wait for streams that can never be admitted
         sleep(min(wake) - (clock() - t0) + 1e-4)
+    return results
+
+
+def _run_trace_pipelined(trace, frame_fn, scheduler, executor, clock, sleep, max_wall):
+    """The loop for an executor with ticks in flight (submit / poll / busy /
+    wait_until): frames that arrive while ticks run are admitted and
+    submitted as soon as the executor takes another tick, and results are
+    collected as their ticks complete."""
+    t0 = clock()
+    i, results = 0, []
+    n = len(trace)
+
+    def now():
+        return clock() - t0
+
+    while i < n or scheduler.pending() or executor.busy():
+        t = now()
+        if max_wall is not None and t > max_wall:
+            break
+        while i < n and trace[i][0] <= t:
+            ts, sid, k = trace[i]
+            scheduler.arrive(frame_fn(sid, k, ts))
+            i += 1
+        results += executor.poll(now)
+        for sid in scheduler.evict_idle(t):
+            executor.evict(sid)
+        for sid in scheduler.admit():
+            executor.admit(scheduler.specs[sid])
+        if executor.can_submit():
+            frames = scheduler.next_batch()
+            if frames:
+                executor.submit(frames)
+                continue
+        if executor.busy():
+            due = trace[i][0] if i < n else math.inf
+            executor.wait_until(lambda: now() >= due, now)
+            continue
+        wake = [trace[i][0]] if i < n else []
+        if scheduler.waiting:
+            wake += scheduler.eviction_times(t)
+        if not wake:
+            break
+        sleep(min(wake) - now() + 1e-4)
+    results += executor.poll(now)
+    results += executor.drain(now)
     return results
 
 

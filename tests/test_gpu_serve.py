@@ -50,10 +50,14 @@ def by_key(results):
     return {(r.sid, r.k): r for r in results}
 
 
-def test_alone_equals_mix_and_plain(env):
+@pytest.mark.parametrize("depth,solo", [(2, True), (2, False), (1, True)])
+def test_alone_equals_mix_and_plain(env, depth, solo):
+    """Two ticks in flight or one; one-frame ticks through the per-stream
+    calls or the batched launch: the same boxes and counts, bit for bit."""
     serve, streams = env
-    trace = serve.make_trace(len(streams), 0.5, 25.0, seed=5)
-    mix, _ = run(serve, streams, trace, serve.GpuExecutor(max_jobs=16, max_points=1 << 20))
+    trace = serve.make_trace(len(streams), 0.5, 25.0, seed=5, rate_scale=3.0)
+    mix, _ = run(serve, streams, trace, serve.GpuExecutor(max_jobs=16, max_points=1 << 20,
+                                                          depth=depth, solo=solo))
     alone_trace = [(t, s, k) for (t, s, k) in trace if s == 1]
     alone, _ = run(serve, streams, alone_trace, serve.GpuExecutor(max_jobs=16, max_points=1 << 20))
     plain, _ = run(serve, streams, trace, serve.PlainExecutor(), batched=False)

@@ -151,3 +151,98 @@ def test_latency_stats():
     rs = [serve.Result(0, k, 0.0, k * 1e-3, None, None) for k in range(101)]
     st = serve.latency_stats(rs)
     assert st["frames"] == 101 and abs(st["p50_ms"] - 50) < 1e-9 and abs(st["p99_ms"] - 99) < 1e-9
+
+
+class FakePipelinedExecutor:
+    """Ticks in flight on a fake device: a tick submitted at time t starts
+    when the previous tick's first stage has finished (stages of consecutive
+    ticks overlap) and completes `tick_s` after its start; at most `depth`
+    ticks are in flight.  Records the submit time of every tick and the
+    number of ticks in flight at each submit."""
+
+    def __init__(self, clock, tick_s=0.004, depth=2):
+        self.clock, self.tick_s, self.depth = clock, tick_s, depth
+        self.inflight = []          # (t_complete, frames)
+        self.ticks, self.submits, self.live = [], [], set()
+        self.ready = []
+
+    def admit(self, spec):
+        self.live.add(spec.sid)
+
+    def evict(self, sid):
+        self.ready += self.drain(lambda: self.clock.t)
+        self.live.discard(sid)
+
+    def busy(self):
+        return bool(self.inflight)
+
+    def can_submit(self):
+        return len(self.inflight) < self.depth
+
+    def submit(self, frames):
+        assert self.can_submit() and all(f.sid in self.live for f in frames)
+        t = self.clock.t
+        start = max(t, self.inflight[-1][2] if self.inflight else t)
+        self.submits.append((t, len(self.inflight)))
+        self.ticks.append([(f.sid, f.k) for f in frames])
+        # the next tick may start once this one's first half has run
+        self.inflight.append((start + self.tick_s, frames, start + self.tick_s / 2))
+        self.clock.t += 1e-5
+
+    def _results(self, frames, t):
+        return [serve.Result(f.sid, f.k, f.t_arrival, t, np.zeros((0, 4), np.float32),
+                             np.zeros(0, np.int32)) for f in frames]
+
+    def poll(self, now):
+        out, self.ready = self.ready, []
+        while self.inflight and self.inflight[0][0] <= self.clock.t:
+            _, frames, _ = self.inflight.pop(0)
+            out += self._results(frames, now())
+        return out
+
+    def wait_until(self, stop, now=None):
+        if self.inflight and not stop():
+            self.clock.t = max(self.clock.t, self.inflight[0][0])
+
+    def drain(self, now):
+        out = []
+        while self.inflight:
+            tc, frames, _ = self.inflight.pop(0)
+            self.clock.t = max(self.clock.t, tc)
+            out += self._results(frames, now())
+        return out
+
+
+def test_pipelined_loop_overlaps_ticks_and_keeps_order():
+    """Frames that arrive while a tick is in flight are submitted before it
+    completes (two ticks in flight), never more than `depth`; every frame
+    gets a result, each stream's frames in order, none before its tick is
+    done."""
+    clock = FakeClock()
+    ex = FakePipelinedExecutor(clock, tick_s=0.02, depth=2)
+    sch = serve.Scheduler(budget=10**9, max_jobs=64, max_points=10**6, footprint=fp_const(10))
+    trace = serve.make_trace(6, 1.0, 25.0, seed=3, rate_scale=3.0)
+    res = serve.run_trace(trace, frame_fn, [spec(s) for s in range(6)], sch, ex, clock=clock,
+                          sleep=clock.sleep)
+    assert len(res) == len(trace)
+    assert sorted((r.sid, r.k) for r in res) == sorted((s, k) for _, s, k in trace)
+    assert max(n for _, n in ex.submits) == 1          # submitted with one tick in flight
+    assert sum(1 for _, n in ex.submits if n == 1) > 0.2 * len(ex.submits)
+    last = {}
+    for tick in ex.ticks:
+        assert len({s for s, _ in tick}) == len(tick)
+        for s, k in tick:
+            assert k == last.get(s, -1) + 1
+            last[s] = k
+    assert all(r.latency >= 0.02 - 1e-9 for r in res)
+
+
+def test_pipelined_loop_depth_one_is_blocking():
+    clock = FakeClock()
+    ex = FakePipelinedExecutor(clock, tick_s=0.02, depth=1)
+    sch = serve.Scheduler(budget=10**9, max_jobs=64, max_points=10**6, footprint=fp_const(10))
+    trace = serve.make_trace(4, 0.5, 25.0, seed=4, rate_scale=2.0)
+    res = serve.run_trace(trace, frame_fn, [spec(s) for s in range(4)], sch, ex, clock=clock,
+                          sleep=clock.sleep)
+    assert len(res) == len(trace)
+    assert all(n == 0 for _, n in ex.submits)
