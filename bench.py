@@ -17,6 +17,7 @@ import hashlib
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -51,6 +52,8 @@ def parse():
                    help="run a plain 256 MiB device copy (scale for the HBM byte counters)")
     p.add_argument("--no-batched", action="store_true", help="skip the 32-stream batched tick")
     p.add_argument("--no-served", action="store_true", help="skip the served-vs-plain run")
+    p.add_argument("--no-video", action="store_true",
+                   help="skip the one-stream video run with and without prefetch")
     p.add_argument("--no-dense", action="store_true",
                    help="skip the dense TV-L1 flow + mean-flow box prediction step")
     p.add_argument("--no-working", action="store_true",
@@ -59,10 +62,13 @@ def parse():
                    help="skip the matching/update step (IoU on the GPU, assignment on the host)")
     p.add_argument("--no-mf", action="store_true",
                    help="skip the Median-Flow step (forward-backward tracking, scaled boxes)")
-    p.add_argument("--served-seconds", type=float, default=3.0,
-                   help="length of the 64-stream arrival trace for served and plain")
-    p.add_argument("--served-rates", default="1,2,3,4",
-                   help="arrival-rate multipliers on 25 fps per stream (comma list)")
+    p.add_argument("--served-seconds", type=float, default=60.0,
+                   help="length of the 64-stream arrival trace at 25 fps, served and plain")
+    p.add_argument("--served-rates", default="1,2,4,6,8,12,16,24,32",
+                   help="arrival-rate multipliers on 25 fps per stream for the saturation "
+                        "sweep (comma list; stops once the served p99 passes 40 ms)")
+    p.add_argument("--sweep-seconds", type=float, default=3.0,
+                   help="trace length of each saturation-sweep rate")
     return p.parse_args()
 
 
@@ -76,7 +82,7 @@ def lk_kernel_flops(iters: np.ndarray, lam: np.ndarray) -> float:
 
 def kernel_sha() -> str:
     h = hashlib.sha256()
-    for f in ("ot_device.hpp", "ot_lk_dev.hpp", "ot_lk.hip", "ot_common.hpp"):
+    for f in ("ot_device.hpp", "ot_lk_dev.hpp", "ot_lk_sched.hpp", "ot_lk.hip", "ot_common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1910_06017_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -133,8 +139,11 @@ def main():
     prev = ops.pyramid_build(f0, L)
     ws1 = ops.alloc_workspace(W, H, L)
     from paper_1910_06017_amd import batch
+    # the step builds the next pyramid, which is the next step's template
+    # pyramid: materialized gradients would have to be built every step, so
+    # the step takes the fastest schedule with gradients computed in the tracker
     MARGIN = batch.default_schedule("single_" + batch.bucket_key(
-        [type("J", (), {"n": n, "levels": L})()])).get("margin", 0)
+        [type("J", (), {"n": n, "levels": L})()]), grads=False).get("margin", 0)
     nxt = torch.empty((n, 2), dtype=torch.float32, device=dev)
     st = torch.empty(n, dtype=torch.uint8, device=dev)
     err = torch.empty(n, dtype=torch.float32, device=dev)
@@ -261,6 +270,8 @@ def main():
         out["dense_tvl1"] = bench_dense(ops, wl, f0, f1, boxes, cs)
     if not a.no_batched:
         out["batched"] = bench_batched(a)
+    if not a.no_video:
+        out["video_prefetch"] = bench_video(a)
     if not a.no_served:
         out["served_vs_plain"] = bench_served(a)
     if not a.no_cpu:
@@ -548,9 +559,11 @@ def bench_batched(a):
 
 
 def bench_served(a):
-    """64 streams with Poisson arrivals (25 fps each x rate), served with
-    continuous batching and, on the same trace, plain per-stream calls, for
-    each arrival-rate multiplier."""
+    """64 streams with Poisson arrivals at 25 fps each, served with continuous
+    batching (two ticks in flight: the next tick's uploads and pyramids
+    overlap the current tracking) and, on the same trace, plain per-stream
+    calls: the full-length trace at the configured rate, then short traces at
+    rising rates until the served p99 passes one frame interval (40 ms)."""
     from paper_1910_06017_amd import serve, synth
 
     streams = synth.served_streams(nframes=10)
@@ -571,42 +584,115 @@ def bench_served(a):
 
     pts_of = {s.sid: sum(s.pts_per_box) for s in streams}
     executors = {"served": (True, serve.GpuExecutor(max_jobs=64, max_points=1 << 21)),
+                 "served_blocking": (True, serve.GpuExecutor(max_jobs=64, max_points=1 << 21,
+                                                             depth=1)),
                  "plain": (False, serve.PlainExecutor())}
-    # warm both paths (allocation, graph capture) on a short trace
+    # warm every path (allocation, first launches) on a short trace
     warm = serve.make_trace(len(streams), 0.2, 25.0, seed=1)
     for name, (batched, ex) in executors.items():
         serve.run_trace(warm, frame_fn, specs, serve.Scheduler(1 << 40, 64, 1 << 21), ex,
                         batched=batched)
         for sid in list(ex.slots):
             ex.evict(sid)
-    runs = []
+
+    def run(name, seconds, rate):
+        batched, ex = executors[name]
+        trace = serve.make_trace(len(streams), seconds, 25.0, seed=505, rate_scale=rate)
+        sch = serve.Scheduler(budget=1 << 40, max_jobs=64, max_points=1 << 21)
+        ex.ticks = 0
+        t0 = time.perf_counter()
+        res = serve.run_trace(trace, frame_fn, specs, sch, ex, batched=batched,
+                              max_wall=seconds * 3)
+        wall = time.perf_counter() - t0
+        st = serve.latency_stats(res)
+        st["completed"] = len(res)
+        st["all_completed"] = len(res) == len(trace)
+        st["tracked_points_per_s"] = sum(pts_of[r.sid] for r in res if r.k > 0) / max(wall, 1e-9)
+        st["ticks"] = ex.ticks
+        st["frames_per_tick"] = len(res) / max(1, ex.ticks)
+        for sid in list(ex.slots):
+            ex.evict(sid)
+        offered = sum(pts_of[s] for _, s, _ in trace) / seconds
+        return len(trace), offered, st
+
+    full = {"rate": 1.0, "fps_per_stream": 25.0, "trace_s": a.served_seconds}
+    for name in ("served", "plain"):
+        nfr, offered, st = run(name, a.served_seconds, 1.0)
+        full["frames"], full["offered_points_per_s"] = nfr, offered
+        full[name] = st
+        print(f"served_vs_plain: {name} {a.served_seconds:.0f} s at 1x: p50 "
+              f"{st['p50_ms']:.3f} p99 {st['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
+    runs, live = [], {"served", "served_blocking", "plain"}
     for rate in [float(r) for r in a.served_rates.split(",")]:
-        trace = serve.make_trace(len(streams), a.served_seconds, 25.0, seed=505, rate_scale=rate)
-        rec = {"rate": rate, "fps_per_stream": 25.0 * rate, "frames": len(trace),
-               "offered_points_per_s": sum(pts_of[s] for _, s, _ in trace) / a.served_seconds}
-        for name, (batched, ex) in executors.items():
-            sch = serve.Scheduler(budget=1 << 40, max_jobs=64, max_points=1 << 21)
-            t0 = time.perf_counter()
-            res = serve.run_trace(trace, frame_fn, specs, sch, ex, batched=batched,
-                                  max_wall=a.served_seconds * 3)
-            wall = time.perf_counter() - t0
-            st = serve.latency_stats(res)
-            st["completed"] = len(res)
-            st["tracked_points_per_s"] = sum(pts_of[r.sid] for r in res if r.k > 0) / max(wall, 1e-9)
-            st["ticks"] = ex.ticks
+        rec = {"rate": rate, "fps_per_stream": 25.0 * rate, "trace_s": a.sweep_seconds}
+        for name in ("served", "served_blocking", "plain"):
+            if name not in live:
+                continue
+            nfr, offered, st = run(name, a.sweep_seconds, rate)
+            rec["frames"], rec["offered_points_per_s"] = nfr, offered
             rec[name] = st
-            for sid in list(ex.slots):
-                ex.evict(sid)
-            ex.ticks = 0
+            if not st["all_completed"] or st["p99_ms"] > 40.0:
+                live.discard(name)          # saturated: higher rates only queue more
         runs.append(rec)
-    # saturation: the largest offered load each path serves with p99 <= 40 ms
-    # (one 25 fps frame interval)
+        print(f"served_vs_plain: sweep rate {rate:g} done, still under 40 ms: {sorted(live)}",
+              file=sys.stderr, flush=True)
+        if "served" not in live:
+            break
+    # the largest offered load each path serves with p99 <= 40 ms (one 25 fps
+    # frame interval) and every frame completed
     sat = {}
-    for name in executors:
-        ok = [r["offered_points_per_s"] for r in runs if r[name]["p99_ms"] <= 40.0]
-        sat[name] = max(ok) if ok else None
-    return {"streams": len(streams), "trace_s": a.served_seconds, "runs": runs,
-            "max_offered_points_per_s_with_p99_le_40ms": sat}
+    for name in ("served", "served_blocking", "plain"):
+        ok = [r["offered_points_per_s"] for r in runs
+              if name in r and r[name]["all_completed"] and r[name]["p99_ms"] <= 40.0]
+        bad = [r["offered_points_per_s"] for r in runs
+               if name in r and not (r[name]["all_completed"] and r[name]["p99_ms"] <= 40.0)]
+        sat[name] = {"max_ok": max(ok) if ok else None, "first_over": min(bad) if bad else None}
+    return {"streams": len(streams), "full_trace": full, "sweep": runs,
+            "saturation_points_per_s": sat}
+
+
+def bench_video(a):
+    """One stream tracked frame by frame from pinned host frames, at the
+    working level of its resolution, with and without the prefetch of the
+    next frame's upload and pyramid on a second stream (Sec. V-B): the 2K
+    (2560x1280, level 1) and 4K (4096x2048, level 2) sizes of the paper's
+    runtime experiment, each a 12-frame cycle played 5 times (60 frames,
+    re-seeded every 10th)."""
+    import torch
+    from paper_1910_06017_amd import ops, synth, video
+
+    out = {}
+    for (W, H), npts, nbox in (((2560, 1280), 8000, 12), ((4096, 2048), 12000, 16)):
+        s = synth.served_streams(seed=606, nstreams=1, nframes=12, npts_range=(npts, npts),
+                                 nbox_range=(nbox, nbox), resolutions=((W, H),))[0]
+        cyc = [_pin(f) for f in s.frames]
+        frames = [cyc[k % len(cyc)] for k in range(60)]
+        seeds = {k: s.seed_points(k, np.random.default_rng(k)) for k in range(0, 60, 10)}
+        base = ops.working_level(W, H)
+        rec = {"frames": len(frames), "points": npts, "boxes": nbox, "working_level": base,
+               "levels": 4}
+        results = {}
+        for pf in (False, True):
+            trk = video.VideoTracker(W, H, levels=4, base_level=base, n_max=npts, m_max=nbox,
+                                     prefetch=pf)
+            trk.track(frames[:12], seeds)           # warm-up
+            torch.cuda.synchronize()
+            best = None
+            for _ in range(3):
+                t0 = time.perf_counter()
+                res = trk.track(frames, seeds)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            results[pf] = res
+            key = "prefetch" if pf else "one_stream"
+            rec[key] = {"ms_per_frame": 1e3 * best / (len(frames) - 1),
+                        "frames_per_s": (len(frames) - 1) / best,
+                        "tracked_points_per_s": npts * (len(frames) - 1) / best}
+        rec["identical"] = all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+                               for x, y in zip(results[False], results[True]))
+        rec["speedup"] = rec["one_stream"]["ms_per_frame"] / rec["prefetch"]["ms_per_frame"]
+        out[f"{W}x{H}"] = rec
+    return out
 
 
 def _pin(frame):
@@ -616,28 +702,83 @@ def _pin(frame):
     return t
 
 
-def cpu_baseline(wl, seconds: float):
-    """The FP64 oracle on the host cores: whole steps (next-frame pyramid,
-    tracking, box update) on the same frame pair, repeated for ~`seconds`."""
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu / /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def _oracle_steps(wl, seconds: float, nthreads: int, pts=None):
+    """Whole oracle steps (next-frame pyramid, tracking, box update) on one
+    frame pair until `seconds` have passed (at least one); returns (steps,
+    points per step, seconds)."""
     import oracle
 
-    oracle.build(force=not os.path.exists(oracle.LIB_PATH))
-    threads = oracle.max_threads()
+    pts = wl.pts if pts is None else pts
+    sel = None if pts is wl.pts else slice(0, len(pts))
     prev = oracle.pyramid(wl.frame0, wl.levels)
     steps, t0 = 0, time.perf_counter()
     while True:
         nxt = oracle.pyramid(wl.frame1, wl.levels)
-        r = oracle.lk_track_pyr(prev, nxt, wl.pts, wl.win, wl.levels, wl.iters,
-                                float(np.float32(wl.eps)))
-        oracle.box_update(wl.boxes, wl.box_id, wl.pts, r.next_pts, r.status)
+        r = oracle.lk_track_pyr(prev, nxt, pts, wl.win, wl.levels, wl.iters,
+                                float(np.float32(wl.eps)), nthreads=nthreads)
+        if sel is None:
+            oracle.box_update(wl.boxes, wl.box_id, wl.pts, r.next_pts, r.status)
         steps += 1
         dt = time.perf_counter() - t0
         if dt >= seconds:
-            break
-    return {"value": steps * wl.n / dt, "unit": "tracked points/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} whole steps of the same 720x576 box-scene frame pair "
-                      f"({wl.n} points), {dt:.1f} s, FP64, OpenMP over points"}
+            return steps, len(pts), dt
+
+
+def cpu_baseline(wl, seconds: float):
+    """The FP64 oracle on the host cores: whole steps (next-frame pyramid,
+    tracking, box update) on the 720x576 box scene, repeated for ~`seconds`,
+    with every host thread.  `detail` adds the shifted-texture, box-scene and
+    1080p pairs and one 32-stream tick, each with all threads and with one
+    (bounded samples: ~2 s per entry, the tick on every 8th point of each
+    stream at one thread)."""
+    import oracle
+    from paper_1910_06017_amd import synth
+
+    oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+    threads = oracle.max_threads()
+    steps, npts, dt = _oracle_steps(wl, seconds, 0)
+    out = {"value": steps * npts / dt, "unit": "tracked points/s", "cores": threads,
+           "kind": "oracle", "cpu": cpu_model(), "host_threads": os.cpu_count(),
+           "sample": f"{steps} whole steps of the same 720x576 box-scene frame pair "
+                     f"({npts} points), {dt:.1f} s, FP64, OpenMP over points"}
+    detail = {}
+    cases = {"720x576 shifted texture, 1024 points, 3 levels": synth.sd_shift_workload(),
+             "720x576 boxes, 8000 points, 4 levels": wl,
+             "1920x1080 boxes, 14400 points, 5 levels": synth.hd_boxes_workload()}
+    for name, w in cases.items():
+        rec = {}
+        for nt, key in ((threads, "all_threads"), (1, "one_thread")):
+            s_, n_, d_ = _oracle_steps(w, 2.0, nt)
+            rec[key] = {"points_per_s": s_ * n_ / d_, "ms_per_step": 1e3 * d_ / s_,
+                        "threads": nt, "steps": s_}
+        detail[name] = rec
+    ws = synth.batched_streams()
+    rec = {}
+    for nt, key, stride in ((threads, "all_threads", 1), (1, "one_thread", 8)):
+        t0, npts = time.perf_counter(), 0
+        for w in ws:
+            p = w.pts[::stride]
+            _oracle_steps(w, 0.0, nt, pts=p if stride > 1 else None)
+            npts += len(p)
+        d_ = time.perf_counter() - t0
+        rec[key] = {"points_per_s": npts / d_, "threads": nt, "points": npts,
+                    "seconds": d_,
+                    "sample": "every point" if stride == 1 else f"every {stride}th point"}
+    detail["32-stream tick (mixed 720x576/1280x720/1920x1080), 169567 points"] = rec
+    out["detail"] = detail
+    return out
 
 
 if __name__ == "__main__":
