@@ -554,8 +554,41 @@ def bench_batched(a):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     ok = float(np.mean([j.status.float().mean().item() for j in jobs if j.n]))
+    # the tracking stage alone (batched tracker + box median) on the packed
+    # table, events on its stream; its algorithmic flops from every point's
+    # per-level iteration counts (the per-stream call gives the same bits)
+    import ctypes as C
+    cs = torch.cuda.Stream()
+    h = int(cs.cuda_stream)
+    run = lambda st: ops.check(ops.lib().ot_batch_run_stages(
+        int(runner.host[0].data_ptr()), int(runner.dev.data_ptr()), runner.table_bytes,
+        C.byref(runner.ccfg), st, h), "ot_batch_run_stages")
+    with torch.cuda.stream(cs):
+        run(1)
+        for _ in range(3):
+            run(2)
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(cs)
+        for _ in range(reps):
+            run(2)
+        k1.record(cs)
+    torch.cuda.synchronize()
+    trk_ms = k0.elapsed_time(k1) / reps
+    flops = 0.0
+    for j, Qb in zip(jobs, runner.next_pyrs):
+        if j.n:
+            _, _, _, it, lam = ops.lk_track(j.prev, Qb, j.pts, win=cfg.win, levels=j.levels,
+                                            iters=cfg.iters, eps=cfg.eps, want_diag=True)
+            flops += lk_kernel_flops(it.cpu().numpy(), lam.cpu().numpy())
+    achieved = flops / (trk_ms * 1e-3) / 1e12
     return {"streams": len(ws), "points_per_tick": npts, "ms_per_tick": ms,
-            "tracked_points_per_s": npts / (ms * 1e-3), "schedule": sched, "ok_fraction": ok}
+            "tracked_points_per_s": npts / (ms * 1e-3), "schedule": sched, "ok_fraction": ok,
+            "tracking_stage_ms": trk_ms,
+            "roofline": {"bound": "alu", "kernel": "k_lk_batch<7,21,4,1,1> + k_batch_box",
+                         "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP32_TFLOPS,
+                         "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+                         "flop_per_tick": flops}}
 
 
 def bench_served(a):
@@ -653,16 +686,18 @@ def bench_served(a):
 
 def bench_video(a):
     """One stream tracked frame by frame from pinned host frames, at the
-    working level of its resolution, with and without the prefetch of the
-    next frame's upload and pyramid on a second stream (Sec. V-B): the 2K
-    (2560x1280, level 1) and 4K (4096x2048, level 2) sizes of the paper's
-    runtime experiment, each a 12-frame cycle played 5 times (60 frames,
-    re-seeded every 10th)."""
+    working level of its resolution: everything on one stream; the next
+    frame's upload and pyramid prefetched on a second stream (Sec. V-B); and
+    prefetched with the points tracked longest-first by their iteration counts
+    in the previous pair.  SD (720x576, level 0) and the 2K (2560x1280, level
+    1) and 4K (4096x2048, level 2) sizes of the paper's runtime experiment,
+    each a 12-frame cycle played 5 times (60 frames, re-seeded every 10th)."""
     import torch
     from paper_1910_06017_amd import ops, synth, video
 
     out = {}
-    for (W, H), npts, nbox in (((2560, 1280), 8000, 12), ((4096, 2048), 12000, 16)):
+    for (W, H), npts, nbox in (((720, 576), 8000, 20), ((2560, 1280), 8000, 12),
+                               ((4096, 2048), 12000, 16)):
         s = synth.served_streams(seed=606, nstreams=1, nframes=12, npts_range=(npts, npts),
                                  nbox_range=(nbox, nbox), resolutions=((W, H),))[0]
         cyc = [_pin(f) for f in s.frames]
@@ -672,9 +707,10 @@ def bench_video(a):
         rec = {"frames": len(frames), "points": npts, "boxes": nbox, "working_level": base,
                "levels": 4}
         results = {}
-        for pf in (False, True):
+        for key, pf, order in (("one_stream", False, False), ("prefetch", True, False),
+                               ("prefetch_order", True, True)):
             trk = video.VideoTracker(W, H, levels=4, base_level=base, n_max=npts, m_max=nbox,
-                                     prefetch=pf)
+                                     prefetch=pf, order=order)
             trk.track(frames[:12], seeds)           # warm-up
             torch.cuda.synchronize()
             best = None
@@ -683,14 +719,16 @@ def bench_video(a):
                 res = trk.track(frames, seeds)
                 dt = time.perf_counter() - t0
                 best = dt if best is None else min(best, dt)
-            results[pf] = res
-            key = "prefetch" if pf else "one_stream"
+            results[key] = res
             rec[key] = {"ms_per_frame": 1e3 * best / (len(frames) - 1),
                         "frames_per_s": (len(frames) - 1) / best,
                         "tracked_points_per_s": npts * (len(frames) - 1) / best}
         rec["identical"] = all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
-                               for x, y in zip(results[False], results[True]))
-        rec["speedup"] = rec["one_stream"]["ms_per_frame"] / rec["prefetch"]["ms_per_frame"]
+                               for k in ("prefetch", "prefetch_order")
+                               for x, y in zip(results["one_stream"], results[k]))
+        base_ms = rec["one_stream"]["ms_per_frame"]
+        rec["speedup_prefetch"] = base_ms / rec["prefetch"]["ms_per_frame"]
+        rec["speedup_prefetch_order"] = base_ms / rec["prefetch_order"]["ms_per_frame"]
         out[f"{W}x{H}"] = rec
     return out
 

@@ -144,7 +144,24 @@ typedef struct {
                            next_pts stay level-0 pixels (scaled by 2^-base_level in and
                            2^base_level out, exactly), the in-frame test and err refer to
                            level base_level.  See ot_working_level. */
+    const int32_t* order; /* device n, or NULL: the k-th wave tracks point order[k] instead
+                             of point k, so the caller can start long tracks first (see
+                             ot_lk_order); a permutation of 0..n-1 (entries outside [0, n)
+                             are skipped).  Results stay at the points' own indices and do
+                             not depend on the order. */
 } ot_lk_opts;
+
+/* A processing order for ot_lk_opts.order: the n points by descending total
+ * iterations over `levels` levels of `iters` (device n x levels uint8, e.g.
+ * ot_lk_opts.iters_out of an earlier pair of the same points, such as the
+ * previous frame pair of a stream), ties in any order.  The cost of a point
+ * changes little from one frame pair to the next, and a launch whose long
+ * tracks start first ends sooner.  order: device n int32 (a permutation of
+ * 0..n-1).  One workgroup.  n == 0 is a no-op.
+ * Errors: OT_E_INVAL (n < 0 or > 2^24, levels outside 1..OT_MAX_LEVELS, null
+ * pointers with n > 0), OT_E_LAUNCH. */
+OT_API ot_err ot_lk_order(const uint8_t* iters, int32_t n, int32_t levels, int32_t* order,
+                          void* stream);
 
 /* (host) Working-level policy for a frame of W x H pixels: the smallest
  * level l >= 0 whose width w_l (w_0 = W, w_l = ceil(w_{l-1} / 2)) is at most

@@ -179,7 +179,7 @@ ot_err ot_lk_track_ex(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const floa
     if (!pts || !next_pts || !status) return OT_E_INVAL;
     if (launch_lk(to_dev(*prev_pyr, base), to_dev(*next_pyr, base), pts, n, prm, next_pts, status, err,
                   opts ? opts->iters_out : nullptr, opts ? opts->lam_out : nullptr,
-                  static_cast<hipStream_t>(stream)) != hipSuccess)
+                  opts ? opts->order : nullptr, static_cast<hipStream_t>(stream)) != hipSuccess)
         return OT_E_LAUNCH;
     return OT_OK;
 }
@@ -189,6 +189,16 @@ ot_err ot_lk_track(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* 
                    uint8_t* status, float* err, void* stream) {
     return ot_lk_track_ex(prev_pyr, next_pyr, pts, n, win, levels, iters, eps, next_pts, status,
                           err, nullptr, stream);
+}
+
+ot_err ot_lk_order(const uint8_t* iters, int32_t n, int32_t levels, int32_t* order,
+                   void* stream) {
+    if (n < 0 || n > (1 << 24) || levels < 1 || levels > OT_MAX_LEVELS) return OT_E_INVAL;
+    if (n == 0) return OT_OK;
+    if (!iters || !order) return OT_E_INVAL;
+    if (launch_lk_order(iters, n, levels, order, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return OT_E_LAUNCH;
+    return OT_OK;
 }
 
 int32_t ot_working_level(int32_t W, int32_t H, int32_t max_width) {

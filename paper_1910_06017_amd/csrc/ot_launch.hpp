@@ -18,7 +18,12 @@ int lk_template_rows(int win);
 
 hipError_t launch_lk(const DevPyr& prev, const DevPyr& next, const float* pts, int n,
                      const LkParams& prm, float* next_pts, uint8_t* status, float* err,
-                     uint8_t* iters_out, float* lam_out, hipStream_t stream);
+                     uint8_t* iters_out, float* lam_out, const int32_t* order,
+                     hipStream_t stream);
+
+// Points by descending total iteration count (one workgroup, counting sort).
+hipError_t launch_lk_order(const uint8_t* iters, int n, int levels, int32_t* order,
+                           hipStream_t stream);
 
 hipError_t launch_box(const float* boxes, int m, const int32_t* box_id, const float* pts,
                       const float* next_pts, const uint8_t* status, int n, float* out_boxes,

@@ -11,10 +11,15 @@ __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restr
                                                  uint8_t* __restrict__ status,
                                                  float* __restrict__ err,
                                                  uint8_t* __restrict__ iters_out,
-                                                 float* __restrict__ lam_out) {
+                                                 float* __restrict__ lam_out,
+                                                 const int32_t* __restrict__ order) {
     extern __shared__ __align__(16) unsigned char lk_smem[];
-    const int i = lk_item(blockIdx.x, gridDim.x);
+    int i = lk_item(blockIdx.x, gridDim.x);
     if (i >= n) return;
+    if (order) {
+        i = order[i];
+        if ((unsigned)i >= (unsigned)n) return;
+    }
     const float ux = uniform_f(pts[2 * i]) * prm.pscale, uy = uniform_f(pts[2 * i + 1]) * prm.pscale;
     const LkGeom g(WIN > 0 ? WIN : prm.win, R, MARGIN > 0 ? MARGIN : prm.margin);
     const int L = prm.levels;
@@ -39,13 +44,14 @@ int lk_template_rows(int win) {
 
 hipError_t launch_lk(const DevPyr& prev, const DevPyr& next, const float* pts, int n,
                      const LkParams& prm, float* next_pts, uint8_t* status, float* err,
-                     uint8_t* iters_out, float* lam_out, hipStream_t stream) {
+                     uint8_t* iters_out, float* lam_out, const int32_t* order,
+                     hipStream_t stream) {
     const int R = lk_template_rows(prm.win);
     const size_t lds = lk_lds_bytes(prm.win, R, prm.margin);
     const bool grads = (prev.flags & OT_PYR_GRADS) != 0;
 #define OT_LAUNCH(...)                                                                           \
     hipLaunchKernelGGL((k_lk_track<__VA_ARGS__>), dim3(n), dim3(64), lds, stream, prev, next, pts, \
-                       n, prm, next_pts, status, err, iters_out, lam_out)
+                       n, prm, next_pts, status, err, iters_out, lam_out, order)
     if (R == 7 && prm.win == 21 && (prm.margin == 4 || prm.margin == 6)) {
         if (prm.margin == 4) {
             if (grads) OT_LAUNCH(7, 21, 4, true); else OT_LAUNCH(7, 21, 4, false);

@@ -206,6 +206,55 @@ hipError_t launch_box_scaled_noalloc(const float* boxes, int m, const int32_t* b
                              out_scale, ws, stream);
 }
 
+// Points by descending total iterations: a counting sort in one workgroup.
+// Key k = sum of a point's per-level counts (<= 8 * 255 < ORD_BINS); bin
+// ORD_BINS-1-k holds key k, so an ascending scan of the bins lists the
+// largest keys first.  Slots within a bin are taken with LDS atomics (ties in
+// any order).
+constexpr int ORD_THREADS = 1024, ORD_BINS = 2048;
+
+__device__ __forceinline__ int ord_key(const uint8_t* __restrict__ iters, int i, int levels) {
+    int k = 0;
+    for (int l = 0; l < levels; ++l) k += iters[(size_t)i * levels + l];
+    return min(k, ORD_BINS - 1);
+}
+
+__global__ __launch_bounds__(ORD_THREADS) void k_lk_order(const uint8_t* __restrict__ iters, int n,
+                                                          int levels, int32_t* __restrict__ order) {
+    __shared__ uint32_t bin[ORD_BINS];
+    __shared__ uint32_t wsum[ORD_THREADS / 64];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < ORD_BINS; b += ORD_THREADS) bin[b] = 0u;
+    __syncthreads();
+    for (int i = tid; i < n; i += ORD_THREADS)
+        atomicAdd(&bin[ORD_BINS - 1 - ord_key(iters, i, levels)], 1u);
+    __syncthreads();
+    // exclusive scan of the bins: each thread owns two consecutive bins
+    const uint32_t a = bin[2 * tid], b = bin[2 * tid + 1];
+    const uint32_t incl = wave_incl_scan_u32(a + b);
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0u;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    const uint32_t ex = before + incl - (a + b);
+    __syncthreads();
+    bin[2 * tid] = ex;
+    bin[2 * tid + 1] = ex + a;
+    __syncthreads();
+    for (int i = tid; i < n; i += ORD_THREADS) {
+        const uint32_t pos = atomicAdd(&bin[ORD_BINS - 1 - ord_key(iters, i, levels)], 1u);
+        order[pos] = i;
+    }
+}
+
+hipError_t launch_lk_order(const uint8_t* iters, int n, int levels, int32_t* order,
+                           hipStream_t stream) {
+    static_assert(2 * ORD_THREADS == ORD_BINS, "two bins per thread");
+    hipLaunchKernelGGL(k_lk_order, dim3(1), dim3(ORD_THREADS), 0, stream, iters, n, levels, order);
+    return hipGetLastError();
+}
+
 constexpr int FB_THREADS = 256;
 
 __global__ __launch_bounds__(FB_THREADS) void k_fb_gate(const float* __restrict__ pts,

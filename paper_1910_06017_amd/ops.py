@@ -22,7 +22,7 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 
 # Every symbol the header declares.
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
-           "ot_lk_track_ex", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled", "ot_box_scaled_bytes",
+           "ot_lk_track_ex", "ot_lk_order", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled", "ot_box_scaled_bytes",
            "ot_box_update_scaled_noalloc",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
            "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_box_mean_flow",
@@ -51,7 +51,7 @@ class OtPyr(C.Structure):
 
 class OtLkOpts(C.Structure):
     _fields_ = [("min_eig", C.c_float), ("iters_out", C.c_void_p), ("lam_out", C.c_void_p),
-                ("margin", C.c_int32), ("base_level", C.c_int32)]
+                ("margin", C.c_int32), ("base_level", C.c_int32), ("order", C.c_void_p)]
 
 
 class OtTvl1Params(C.Structure):
@@ -102,6 +102,8 @@ def lib():
         L.ot_lk_track_ex.argtypes = [PP, PP, P, i32, i32, i32, i32, f32, P, P, P,
                                      C.POINTER(OtLkOpts), P]
         L.ot_lk_track_ex.restype = i32
+        L.ot_lk_order.argtypes = [P, i32, i32, P, P]
+        L.ot_lk_order.restype = i32
         L.ot_box_update.argtypes = [P, i32, P, P, P, P, i32, P, P, P]
         L.ot_box_update.restype = i32
         L.ot_fb_gate.argtypes = [P, P, P, P, i32, f32, P, P, P]
@@ -249,10 +251,12 @@ def pyramid_layout(frame, levels: int, ws, grads: bool = False) -> Pyramid:
 def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None = None,
              iters: int = 30, eps: float = 0.01, min_eig: float = OT_DEFAULT_MIN_EIG,
              margin: int = 0, want_err: bool = True, want_diag: bool = False, out=None,
-             stream=None, base_level: int = 0):
+             stream=None, base_level: int = 0, order=None, iters_out=None):
     """Track (n, 2) float32 points.  Returns (next_pts, status, err[, iters, lam]).
     base_level > 0 tracks at that working level (levels base_level.. of both
-    pyramids); points stay in level-0 pixels."""
+    pyramids); points stay in level-0 pixels.  order: (n,) int32 processing
+    order (see lk_order); iters_out: (n, levels) uint8 receiving the per-level
+    iteration counts (without the other diagnostics)."""
     torch = _torch()
     _need(pts, torch.float32, 2, "pts")
     n = pts.shape[0]
@@ -264,7 +268,17 @@ def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None
         err = torch.empty(n, dtype=torch.float32, device=dev) if want_err else None
     else:
         next_pts, status, err = out
-    opts = OtLkOpts(min_eig, None, None, margin, base_level)
+    opts = OtLkOpts(min_eig, None, None, margin, base_level, None)
+    if order is not None:
+        _need(order, torch.int32, None, "order")
+        if order.numel() != n:
+            raise ValueError("order must hold n entries")
+        opts.order = _ptr(order)
+    if iters_out is not None:
+        _need(iters_out, torch.uint8, L, "iters_out")
+        if iters_out.shape[0] != n:
+            raise ValueError("iters_out must be (n, levels)")
+        opts.iters_out = _ptr(iters_out)
     it = lam = None
     if want_diag:
         it = torch.zeros((n, L), dtype=torch.uint8, device=dev)
@@ -276,6 +290,21 @@ def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None
     if want_diag:
         return next_pts, status, err, it, lam
     return next_pts, status, err
+
+
+def lk_order(iters, out=None, stream=None):
+    """Processing order of lk_track: the points of an (n, levels) uint8 table
+    of iteration counts (an earlier pair of the same points) by descending
+    total count; (n,) int32."""
+    torch = _torch()
+    _need(iters, torch.uint8, None, "iters")
+    if iters.dim() != 2:
+        raise ValueError("iters must be (n, levels)")
+    n, L = iters.shape
+    order = out if out is not None else torch.empty(n, dtype=torch.int32, device=iters.device)
+    check(lib().ot_lk_order(_ptr(iters), n, L, _ptr(order), _stream_handle(stream)),
+          "ot_lk_order")
+    return order
 
 
 def box_update(boxes, box_id, pts, next_pts, status, out=None, stream=None):

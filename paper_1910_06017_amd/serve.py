@@ -406,7 +406,7 @@ class GpuExecutor:
         self.table_bytes = nb
         self.depth = depth
         self.solo = solo     # one-frame ticks through the per-stream calls
-        self.opts = ops.OtLkOpts(float(self.cfg.min_eig), None, None, self.cfg.margin, 0)
+        self.opts = ops.OtLkOpts(float(self.cfg.min_eig), None, None, self.cfg.margin, 0, None)
         self.host_tab = [torch.empty(nb, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
         self.dev_tab = [torch.empty(nb, dtype=torch.uint8, device=self.device) for _ in range(2)]
         self.arena = _Arena(torch, self.device, max_slots, m_chunk)
@@ -661,7 +661,7 @@ class PlainExecutor:
         self.slots: dict = {}
         self.stream = torch.cuda.Stream(self.device)
         self.sh = int(self.stream.cuda_stream)
-        self.opts = ops.OtLkOpts(ops.OT_DEFAULT_MIN_EIG, None, None, 0)
+        self.opts = ops.OtLkOpts(ops.OT_DEFAULT_MIN_EIG, None, None, 0, 0, None)
         self.ticks = 0
 
     def admit(self, spec: StreamSpec):

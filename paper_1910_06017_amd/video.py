@@ -11,8 +11,11 @@ the next frame is tracked, as the matching and update phases need them.
 With `prefetch`, frame t+1's upload and pyramid are enqueued on a second HIP
 stream as soon as frame t's tracking has been, so they run while frame t is
 tracked and its boxes come back; an event orders frame t+1's tracking after
-its pyramid.  Without it, every step runs on one stream.  The kernels and
-their inputs are the same either way, so the results are identical.
+its pyramid.  Without it, every step runs on one stream.  With `order`, the
+points of a pair are tracked longest-first by their iteration counts in the
+previous pair (a point keeps its index from frame to frame until the next
+re-seed), which shortens the launch's tail.  The kernels and their inputs are
+the same either way, so the results are identical.
 
 Frame buffers and pyramid workspaces form a ring of three: frame t lives in
 slot t % 3, which the pairs (t - 1, t) and (t, t + 1) read; frame t + 3
@@ -37,7 +40,7 @@ class VideoTracker:
 
     def __init__(self, W: int, H: int, levels: int, base_level: int = 0, n_max: int = 20000,
                  m_max: int = 64, win: int = 21, iters: int = 30, eps: float = 0.01,
-                 prefetch: bool = True, device="cuda"):
+                 prefetch: bool = True, order: bool = False, device="cuda"):
         import torch
 
         from .serve import _copy  # noqa: F401  (host<->device copies without the dispatcher)
@@ -60,6 +63,12 @@ class VideoTracker:
         self.box_id = torch.zeros(n, dtype=torch.int32, device=self.dev)
         self.boxes = [torch.zeros((m, 4), dtype=torch.float32, device=self.dev) for _ in range(2)]
         self.count = torch.zeros(m, dtype=torch.int32, device=self.dev)
+        # per-point iteration counts of the last pair (two buffers) and the
+        # processing order derived from them
+        self.order = order
+        self.iters_buf = [torch.zeros((n, levels), dtype=torch.uint8, device=self.dev)
+                          for _ in range(2)]
+        self.order_buf = torch.zeros(n, dtype=torch.int32, device=self.dev)
         self.host_boxes = torch.zeros((m, 4), dtype=torch.float32, pin_memory=True)
         self.host_count = torch.zeros(m, dtype=torch.int32, pin_memory=True)
         # both streams at the default priority
@@ -105,9 +114,11 @@ class VideoTracker:
         n = m = 0
         st = self.s_trk
         sh = int(st.cuda_stream)
+        counts_valid = False   # iters_buf[cur] holds the last pair's counts of these points
         for t in range(1, T + 1):
             cur = (t - 1) & 1      # point / box buffers of frame t-1
             if t - 1 in seeds:
+                counts_valid = False
                 pts, bid, bx = (np.ascontiguousarray(a) for a in seeds[t - 1])
                 n, m = len(pts), len(bx)
                 if n > self.n_max or m > self.m_max:
@@ -127,9 +138,15 @@ class VideoTracker:
             st.wait_event(pre_ev[t])
             P, Q = self.pyr[(t - 1) % 3], self.pyr[t % 3]
             nxt = 1 - cur
+            order = None
+            if self.order and counts_valid and n:
+                # long tracks of the last pair first (the points keep their indices)
+                order = ops.lk_order(self.iters_buf[cur][:n], out=self.order_buf[:n], stream=st)
             ops.lk_track(P, Q, self.pts[cur][:n], win=self.win, levels=self.levels,
                          iters=self.iters, eps=self.eps, stream=st, base_level=self.base,
-                         out=(self.pts[nxt][:n], self.status[:n], self.err[:n]))
+                         out=(self.pts[nxt][:n], self.status[:n], self.err[:n]), order=order,
+                         iters_out=self.iters_buf[nxt][:n] if self.order else None)
+            counts_valid = True
             ops.box_update(self.boxes[cur][:m], self.box_id[:n], self.pts[cur][:n],
                            self.pts[nxt][:n], self.status[:n],
                            out=(self.boxes[nxt][:m], self.count[:m]), stream=st)

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 24
+    assert len(syms) == 25
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -186,6 +186,17 @@ def test_box_scaled_validation(L):
     assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, ws + 16, need, None) == Wk
     assert u(FAKE, 3, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, FAKE, None, need, None) == Wk
     assert u(None, 0, None, None, None, None, 5, None, None, None, None, 0, None) == 0
+
+
+def test_lk_order_validation(L):
+    E = ops_err("OT_E_INVAL")
+    o = L.ot_lk_order
+    assert o(FAKE, -1, 4, FAKE, None) == E
+    assert o(FAKE, 10, 0, FAKE, None) == E
+    assert o(FAKE, 10, 9, FAKE, None) == E
+    assert o(None, 10, 4, FAKE, None) == E
+    assert o(FAKE, 10, 4, None, None) == E
+    assert o(None, 0, 4, None, None) == 0
 
 
 def test_box_scaled_noalloc_validation(L):

@@ -223,6 +223,28 @@ def test_margin_does_not_change_results(ops, margin):
     assert np.array_equal(a[0], b[0])
 
 
+def test_order_does_not_change_results(ops):
+    """Tracking the points in any processing order gives the same bits at
+    the points' own indices; lk_order lists every point once, by descending
+    total iterations."""
+    w = synth.sd_boxes_workload()
+    P = ops.pyramid_build(dev(w.frame0), 4)
+    Q = ops.pyramid_build(dev(w.frame1), 4)
+    pts = dev(w.pts)
+    a = ops.lk_track(P, Q, pts, win=21, levels=4, want_diag=True)
+    perm = dev(np.random.default_rng(8).permutation(w.n).astype(np.int32))
+    b = ops.lk_track(P, Q, pts, win=21, levels=4, want_diag=True, order=perm)
+    order = ops.lk_order(a[3])
+    c = ops.lk_track(P, Q, pts, win=21, levels=4, want_diag=True, order=order)
+    torch.cuda.synchronize()
+    for x, y, z in zip(a, b, c):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    o = order.cpu().numpy()
+    assert np.array_equal(np.sort(o), np.arange(w.n))
+    cost = a[3].cpu().numpy().astype(np.int64).sum(1)[o]
+    assert np.all(np.diff(cost) <= 0)
+
+
 def test_deterministic(ops):
     w = synth.sd_boxes_workload()
     a = run_gpu(ops, w.frame0, w.frame1, w.pts, 21, 4, 30, 0.01)

@@ -1,9 +1,10 @@
 """One video stream tracked frame by frame at its working level, with and
-without the prefetch of the next frame's preprocessing (Sec. V-B): the two
-give identical boxes and counts on every frame (same kernels, same inputs,
-only the streams differ), and the frames right after a re-seed match the
-oracle's tracker and box update at the working level (counts equal, every
-box within 0.01 px)."""
+without the prefetch of the next frame's preprocessing (Sec. V-B) and the
+longest-first order from the previous pair's iteration counts: all give
+identical boxes and counts on every frame (same kernels, same inputs, only
+the streams and the order of the points differ), and the frames right after
+a re-seed match the oracle's tracker and box update at the working level
+(counts equal, every box within 0.01 px)."""
 import numpy as np
 import pytest
 
@@ -32,18 +33,19 @@ def env():
     return ops, video, s, frames, seeds
 
 
-def test_prefetch_gives_identical_results(env):
+def test_prefetch_and_order_give_identical_results(env):
     ops, video, s, frames, seeds = env
     base = ops.working_level(s.W, s.H)
     assert base == 1
     runs = []
-    for pf in (False, True):
+    for pf, order in ((False, False), (True, False), (True, True)):
         trk = video.VideoTracker(s.W, s.H, levels=4, base_level=base, n_max=4000, m_max=16,
-                                 prefetch=pf)
+                                 prefetch=pf, order=order)
         runs.append(trk.track(frames, seeds))
     assert len(runs[0]) == len(frames) - 1
-    for (b0, c0), (b1, c1) in zip(*runs):
-        assert np.array_equal(b0, b1) and np.array_equal(c0, c1)
+    for other in runs[1:]:
+        for (b0, c0), (b1, c1) in zip(runs[0], other):
+            assert np.array_equal(b0, b1) and np.array_equal(c0, c1)
 
 
 def test_reseeded_frames_match_oracle(env):
