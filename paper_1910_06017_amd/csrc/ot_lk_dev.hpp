@@ -286,21 +286,15 @@ __device__ __forceinline__ void lk_sync() {
 // offset: a level coordinate of ~2000 px held in one float has a spacing of
 // 1.2e-4 px, which a non-contracting iterate amplifies, while an offset of a
 // few pixels keeps ~1e-7 px.  split_pos gives the integer floor and the
-// fraction of anchor + t, the position clamped to [lo, hi] (a clamped
-// position has fraction 0; past the bounds every tap reads the level's edge).
-__device__ __forceinline__ void split_pos(int anchor, float t, int lo, int hi, int& ip, float& f) {
+// fraction of anchor + t.  The offset is bounded to +-2^20 px so the integer
+// cannot overflow; a position past the level's edge needs no other bound,
+// since every tap of a region staged there reads the edge (the staging
+// clamps each index), the value the oracle's clamped taps give as well.
+__device__ __forceinline__ void split_pos(int anchor, float t, int& ip, float& f) {
     t = __builtin_amdgcn_fmed3f(t, -1048576.0f, 1048576.0f);
     const float ft = floorf(t);
     ip = anchor + (int)ft;
     f = t - ft;
-    if (ip < lo) {
-        ip = lo;
-        f = 0.0f;
-    }
-    if (ip >= hi) {
-        ip = hi;
-        f = 0.0f;
-    }
 }
 
 // g <- 2 (g + nu) on the split form g = gi + gf, gf in [0, 1): the doubling
@@ -549,7 +543,6 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
 
         // Positions are clamped before the integer conversion; past the bounds
         // every tap already reads the level's edge, so the samples are unchanged.
-        const int lo = -(g.win + 8), hix = w + g.win + 8, hiy = h + g.win + 8;
         // target position c + g + nu = (floor(c) + gi) + (frac(c) + gf + nu)
         const int ancx = (int)flx + gix, ancy = (int)fly + giy;
         const float f0x = ax + gfx, f0y = ay + gfy;
@@ -558,8 +551,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         {
             int qx, qy;
             float unusedx, unusedy;
-            split_pos(ancx, f0x, lo, hix, qx, unusedx);
-            split_pos(ancy, f0y, lo, hiy, qy, unusedy);
+            split_pos(ancx, f0x, qx, unusedx);
+            split_pos(ancy, f0y, qy, unusedy);
             sx0 = qx - g.r - g.M;
             sy0 = qy - g.r - g.M;
             stage_target(Jl, w, h, jp, sx0, sy0, g.SR, g.SC, g.SP, jr, lane);
@@ -582,8 +575,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         while (it < iters) {
             int ifx, ify;
             float bxw, byw;
-            split_pos(ancx, f0x + nux, lo, hix, ifx, bxw);
-            split_pos(ancy, f0y + nuy, lo, hiy, ify, byw);
+            split_pos(ancx, f0x + nux, ifx, bxw);
+            split_pos(ancy, f0y + nuy, ify, byw);
             int ox = ifx - g.r - sx0, oy = ify - g.r - sy0;
             if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
                 lk_sync<WSYNC>();
@@ -653,8 +646,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
     {
         int qx, qy;
         float bxw, byw;
-        split_pos(fix0, ffx0, INT32_MIN / 2, INT32_MAX / 2, qx, bxw);
-        split_pos(fiy0, ffy0, INT32_MIN / 2, INT32_MAX / 2, qy, byw);
+        split_pos(fix0, ffx0, qx, bxw);
+        split_pos(fiy0, ffy0, qy, byw);
         int ox = qx - g.r - sx0, oy = qy - g.r - sy0;
         if (ox < 0 || oy < 0 || ox > 2 * g.M || oy > 2 * g.M) {
             lk_sync<WSYNC>();

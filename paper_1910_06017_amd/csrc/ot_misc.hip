@@ -210,12 +210,16 @@ hipError_t launch_box_scaled_noalloc(const float* boxes, int m, const int32_t* b
 // Key k = sum of a point's per-level counts (<= 8 * 255 < ORD_BINS); bin
 // ORD_BINS-1-k holds key k, so an ascending scan of the bins lists the
 // largest keys first.  Slots within a bin are taken with LDS atomics (ties in
-// any order).
-constexpr int ORD_THREADS = 1024, ORD_BINS = 2048;
+// any order).  Each thread keeps the keys of its first ORD_KEEP points in
+// registers between the two passes (points past that are read again).
+constexpr int ORD_THREADS = 1024, ORD_BINS = 2048, ORD_KEEP = 16;
 
 __device__ __forceinline__ int ord_key(const uint8_t* __restrict__ iters, int i, int levels) {
+    const uint8_t* p = iters + (size_t)i * levels;
     int k = 0;
-    for (int l = 0; l < levels; ++l) k += iters[(size_t)i * levels + l];
+#pragma unroll
+    for (int l = 0; l < OT_MAX_LEVELS; ++l)
+        if (l < levels) k += p[l];
     return min(k, ORD_BINS - 1);
 }
 
@@ -225,8 +229,17 @@ __global__ __launch_bounds__(ORD_THREADS) void k_lk_order(const uint8_t* __restr
     __shared__ uint32_t wsum[ORD_THREADS / 64];
     const int tid = threadIdx.x;
     for (int b = tid; b < ORD_BINS; b += ORD_THREADS) bin[b] = 0u;
+    int key[ORD_KEEP];
+#pragma unroll
+    for (int q = 0; q < ORD_KEEP; ++q) {
+        const int i = tid + q * ORD_THREADS;
+        key[q] = i < n ? ord_key(iters, i, levels) : 0;
+    }
     __syncthreads();
-    for (int i = tid; i < n; i += ORD_THREADS)
+#pragma unroll
+    for (int q = 0; q < ORD_KEEP; ++q)
+        if (tid + q * ORD_THREADS < n) atomicAdd(&bin[ORD_BINS - 1 - key[q]], 1u);
+    for (int i = tid + ORD_KEEP * ORD_THREADS; i < n; i += ORD_THREADS)
         atomicAdd(&bin[ORD_BINS - 1 - ord_key(iters, i, levels)], 1u);
     __syncthreads();
     // exclusive scan of the bins: each thread owns two consecutive bins
@@ -242,10 +255,13 @@ __global__ __launch_bounds__(ORD_THREADS) void k_lk_order(const uint8_t* __restr
     bin[2 * tid] = ex;
     bin[2 * tid + 1] = ex + a;
     __syncthreads();
-    for (int i = tid; i < n; i += ORD_THREADS) {
-        const uint32_t pos = atomicAdd(&bin[ORD_BINS - 1 - ord_key(iters, i, levels)], 1u);
-        order[pos] = i;
+#pragma unroll
+    for (int q = 0; q < ORD_KEEP; ++q) {
+        const int i = tid + q * ORD_THREADS;
+        if (i < n) order[atomicAdd(&bin[ORD_BINS - 1 - key[q]], 1u)] = i;
     }
+    for (int i = tid + ORD_KEEP * ORD_THREADS; i < n; i += ORD_THREADS)
+        order[atomicAdd(&bin[ORD_BINS - 1 - ord_key(iters, i, levels)], 1u)] = i;
 }
 
 hipError_t launch_lk_order(const uint8_t* iters, int n, int levels, int32_t* order,
