@@ -416,7 +416,10 @@ ot_err ot_batch_run_stages(const void* table_host, void* table_dev, size_t table
     memcpy(&hd, table_host, sizeof(hd));
     const bool exact = cfg->exact_grids != 0;
     if (stages & OT_STAGE_PYRAMID) {
-        if (hipMemcpyAsync(table_dev, table_host, T.bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        // an eager tick copies what it packed; a graph-capturable one the whole table
+        const size_t nb = exact && hd.njobs >= 0 && hd.njobs <= cfg->max_jobs ? T.used(hd.njobs)
+                                                                                 : T.bytes;
+        if (hipMemcpyAsync(table_dev, table_host, nb, hipMemcpyHostToDevice, s) != hipSuccess)
             return OT_E_LAUNCH;
         for (int l0 = 0; l0 < cfg->max_levels - 1; l0 += PYR_FUSE) {
             const int grid = exact ? hd.total_tiles[l0 + 1] : cfg->max_tiles;

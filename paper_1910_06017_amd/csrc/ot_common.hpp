@@ -109,11 +109,11 @@ struct TableHdr {
 // box_prefix | tile_prefix[levels][njobs_cap + 1] | tile_cols[levels][njobs_cap].
 struct TableLayout {
     size_t jobs, pt_prefix, box_prefix, tile_prefix, tile_cols, bytes;
+    // The job records come last, so an eager tick copies the header, the
+    // prefix sums and only the records of its packed jobs.
     OT_HD static TableLayout make(int32_t cap) {
         TableLayout t;
         size_t off = (sizeof(TableHdr) + 255) & ~size_t(255);
-        t.jobs = off;
-        off += sizeof(DevJob) * (size_t)cap;
         t.pt_prefix = off;
         off += sizeof(int32_t) * (size_t)(cap + 1);
         t.box_prefix = off;
@@ -122,9 +122,13 @@ struct TableLayout {
         off += sizeof(int32_t) * (size_t)(cap + 1) * OT_MAX_LEVELS;
         t.tile_cols = off;
         off += sizeof(int32_t) * (size_t)cap * OT_MAX_LEVELS;
+        t.jobs = (off + 15) & ~size_t(15);
+        off = t.jobs + sizeof(DevJob) * (size_t)cap;
         t.bytes = (off + 255) & ~size_t(255);
         return t;
     }
+    // Bytes a tick of njobs jobs reads: everything up to its last job record.
+    OT_HD size_t used(int32_t njobs) const { return jobs + sizeof(DevJob) * (size_t)njobs; }
 };
 
 // Rows per lane strip for a window: the wave's 64 lanes cover the window as
