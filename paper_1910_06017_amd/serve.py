@@ -384,7 +384,7 @@ class GpuExecutor:
 
     def __init__(self, win=21, iters=30, eps=0.01, max_jobs=64, max_points=1 << 21,
                  max_boxes=4096, max_levels=5, schedule=None, device="cuda", max_slots=128,
-                 m_chunk=64, depth=2, solo=True):
+                 m_chunk=64, depth=2, solo=True, solo_overlap=True):
         import torch
 
         from . import batch, ops
@@ -406,6 +406,9 @@ class GpuExecutor:
         self.table_bytes = nb
         self.depth = depth
         self.solo = solo     # one-frame ticks through the per-stream calls
+        # a one-frame tick submitted while another runs: preprocessing on the
+        # other stream (True) or everything behind it on the tracking stream
+        self.solo_overlap = solo_overlap
         self.opts = ops.OtLkOpts(float(self.cfg.min_eig), None, None, self.cfg.margin, 0, None)
         self.host_tab = [torch.empty(nb, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
         self.dev_tab = [torch.empty(nb, dtype=torch.uint8, device=self.device) for _ in range(2)]
@@ -426,6 +429,7 @@ class GpuExecutor:
         self.trk_events: dict = {}   # tick index -> tracking-stage event
         self.ready: list = []        # results collected outside poll
         self.ticks = 0
+        self._now = time.perf_counter
         torch.cuda.synchronize(self.device)  # the arena's fills precede both streams' work
 
     # -------------------------------------------------------------- slots
@@ -449,8 +453,21 @@ class GpuExecutor:
     def can_submit(self) -> bool:
         return len(self.inflight) < self.depth
 
-    def submit(self, frames: list):
-        """Enqueue one tick of frames (at most one per stream)."""
+    def _observe(self):
+        """Stamp the completion of the ticks in flight that have completed
+        (tracking stages complete in submission order).  Called between the
+        enqueue steps of a submit, so that a tick that completes while the
+        host enqueues the next one is seen then, not when the submit returns."""
+        for tk in self.inflight:
+            if tk.t_done is not None:
+                continue
+            if not tk.ev_trk.query():
+                return
+            tk.t_done = self._now()
+
+    def submit(self, frames: list, now=time.perf_counter):
+        """Enqueue one tick of frames (at most one per stream).  `now` is the
+        clock the completion times of the ticks in flight are read from."""
         import ctypes as C
 
         from . import ops
@@ -458,6 +475,7 @@ class GpuExecutor:
         torch = self.torch
         if not self.can_submit():
             raise RuntimeError("too many ticks in flight")
+        self._now = now
         if len(frames) == 1 and self.solo:
             self._submit_one(frames[0])
             return
@@ -483,10 +501,12 @@ class GpuExecutor:
             self.s_pre.wait_event(prior)
         for fr, slot, f, _ in metas:
             slot.upload(fr, f, self.h_pre)
+        self._observe()
         ops.check(L.ot_batch_run_stages(int(self.host_tab[t].data_ptr()),
                                         int(self.dev_tab[t].data_ptr()), self.table_bytes,
                                         C.byref(self.ccfg), OT_STAGE_PYRAMID, self.h_pre),
                   "ot_batch_run_stages(pyramid)")
+        self._observe()
         ev_pre = torch.cuda.Event()
         ev_pre.record(self.s_pre)
         # ---- tracking stage
@@ -495,6 +515,7 @@ class GpuExecutor:
                                         int(self.dev_tab[t].data_ptr()), self.table_bytes,
                                         C.byref(self.ccfg), OT_STAGE_TRACK, self.h_trk),
                   "ot_batch_run_stages(track)")
+        self._observe()
         r = k % (self.depth + 1)
         a = self.arena
         mc = a.m_chunk
@@ -512,6 +533,7 @@ class GpuExecutor:
         if chi > clo:
             _copy(self.ring_count[r][clo:].data_ptr(), a.dev_count[clo:].data_ptr(),
                   (chi - clo) * 4, _D2H, self.h_trk)
+        self._observe()
         for fr, slot, f, _ in metas:
             slot.reseed(fr, f, self.h_trk)
             slot.f = f
@@ -539,16 +561,18 @@ class GpuExecutor:
         NF, NP = _Slot.NF, _Slot.NP
         fi, fq, p, q = f % NF, (f - 1) % NF, f % NP, (f - 1) % NP
         sp = slot.spec
-        idle = not self.inflight
+        idle = not self.inflight or not self.solo_overlap
         prior = self.trk_events.pop(k - self.depth, None)
         s_pre, h_pre = (self.s_trk, self.h_trk) if idle else (self.s_pre, self.h_pre)
         if prior is not None and not idle:
             s_pre.wait_event(prior)
         slot.upload(fr, f, h_pre)
+        self._observe()
         d = ops.OtPyr()
         ops.check(L.ot_pyramid_build(slot.frames[fi].data_ptr(), sp.W, sp.H, sp.W, sp.levels,
                                      slot.ws[fi].data_ptr(), slot.ws[fi].numel(), 0, C.byref(d),
                                      h_pre), "ot_pyramid_build")
+        self._observe()
         ev_pre = None
         if not idle:
             ev_pre = torch.cuda.Event()
@@ -563,16 +587,19 @@ class GpuExecutor:
                                        self.cfg.iters, self.cfg.eps, slot.pts[p].data_ptr(),
                                        slot.status.data_ptr(), slot.err.data_ptr(),
                                        C.byref(self.opts), self.h_trk), "ot_lk_track")
+            self._observe()
             ops.check(L.ot_box_update(slot.boxes[q].data_ptr(), m, slot.box_id.data_ptr(),
                                       slot.pts[q].data_ptr(), slot.pts[p].data_ptr(),
                                       slot.status.data_ptr(), n, slot.boxes[p].data_ptr(),
                                       slot.count.data_ptr(), self.h_trk), "ot_box_update")
+            self._observe()
             if m:
                 _copy(self.ring_boxes[r][p][slot.c0:].data_ptr(), slot.boxes[p].data_ptr(),
                       m * 16, _D2H, self.h_trk)
                 _copy(self.ring_count[r][slot.c0:].data_ptr(), slot.count.data_ptr(), m * 4,
                       _D2H, self.h_trk)
                 spans[p] = (slot.c0, slot.c0 + m)
+        self._observe()
         slot.reseed(fr, f, self.h_trk)
         slot.f = f
         ev_trk = torch.cuda.Event()
@@ -639,7 +666,7 @@ class GpuExecutor:
         """One tick, blocking: submit and wait (results of any earlier ticks
         in flight come first)."""
         out = self.drain(now)
-        self.submit(frames)
+        self.submit(frames, now)
         return out + self.drain(now)
 
 
@@ -741,15 +768,30 @@ def make_trace(nstreams: int, duration: float, fps: float, seed: int, rate_scale
     return out
 
 
+# the OS wakes a sleeping thread up to this late: waits end in a spin
+_SPIN_S = 1e-3
+
+
+def _wait(clock, dt: float):
+    """Wait dt seconds: sleep while more than the OS's wake-up slack remains,
+    then spin to the exact time (an arrival is noticed within microseconds,
+    not at the next scheduler wake-up)."""
+    end = clock() + dt
+    if dt > 2 * _SPIN_S:
+        time.sleep(dt - _SPIN_S)
+    while clock() < end:
+        pass
+
+
 def run_trace(trace, frame_fn, specs, scheduler: Scheduler, executor, clock=None,
               sleep=None, max_wall: float | None = None, batched: bool = True):
     """Drive arrivals against a clock.  `frame_fn(sid, k, t)` returns a Frame.
-    With the real clock, arrivals are released when their time has come and
-    the loop sleeps while nothing waits; with a fake clock, `sleep` advances
-    it.  `batched=False` processes waiting frames one at a time (FIFO over
+    With the real clock, arrivals are released when their time has come and,
+    while nothing waits, the loop sleeps and then spins to the next arrival;
+    with a fake clock, `sleep` advances it.  `batched=False` processes waiting frames one at a time (FIFO over
     all streams).  Returns the list of Results."""
     clock = clock or time.perf_counter
-    sleep = sleep or (lambda dt: time.sleep(max(0.0, dt)))
+    sleep = sleep or (lambda dt: _wait(clock, dt))
     for sp in specs:
         scheduler.register(sp)
     # Python's cycle collector stops the loop for tens of milliseconds once
@@ -801,7 +843,7 @@ def _run_trace(trace, frame_fn, scheduler, executor, clock, sleep, max_wall, bat
             wake += scheduler.eviction_times(now)
         if not wake:
             break  # frames wait for streams that can never be admitted
-        sleep(min(wake) - (clock() - t0) + 1e-4)
+        sleep(min(wake) - (clock() - t0) + 1e-6)
     return results
 
 
@@ -833,7 +875,7 @@ def _run_trace_pipelined(trace, frame_fn, scheduler, executor, clock, sleep, max
         if executor.can_submit():
             frames = scheduler.next_batch()
             if frames:
-                executor.submit(frames)
+                executor.submit(frames, now)
                 continue
         if executor.busy():
             due = trace[i][0] if i < n else math.inf
@@ -844,7 +886,7 @@ def _run_trace_pipelined(trace, frame_fn, scheduler, executor, clock, sleep, max
             wake += scheduler.eviction_times(t)
         if not wake:
             break
-        sleep(min(wake) - now() + 1e-4)
+        sleep(min(wake) - now() + 1e-6)
     results += executor.poll(now)
     results += executor.drain(now)
     return results

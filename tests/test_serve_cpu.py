@@ -179,7 +179,7 @@ class FakePipelinedExecutor:
     def can_submit(self):
         return len(self.inflight) < self.depth
 
-    def submit(self, frames):
+    def submit(self, frames, now=None):
         assert self.can_submit() and all(f.sid in self.live for f in frames)
         t = self.clock.t
         start = max(t, self.inflight[-1][2] if self.inflight else t)
