@@ -397,35 +397,45 @@ def bench_scaled_scenes(ops, dev, cs, reps, krep):
 def bench_dense(ops, wl, f0, f1, boxes, cs):
     """The dense variant on the same frame pair: TV-L1 flow with the default
     parameters (both frames' structure-texture split, 5 levels, 5 warps x 30
-    iterations) and the mean-flow box prediction, one graph replay."""
+    iterations) and the mean-flow box prediction, one graph replay; with the
+    structure-texture split on a second stream ahead of the flow (the
+    default), and with everything on one stream."""
     import torch
     p = ops.tvl1_params()
     H, W = wl.frame0.shape
     P = ops.pyramid_build(f0, p.levels)
     Q = ops.pyramid_build(f1, p.levels)
     ws = torch.empty(int(ops.lib().ot_tvl1_bytes(W, H)), dtype=torch.uint8, device=f0.device)
-    flow = torch.empty((H, W, 2), dtype=torch.float32, device=f0.device)
-    ob = torch.empty_like(boxes)
-    oc = torch.empty(boxes.shape[0], dtype=torch.int32, device=f0.device)
+    aux = torch.cuda.Stream(f0.device)  # default priority
+    res, flows = {}, {}
+    for name, a in (("two_streams", aux), ("one_stream", None)):
+        flow = torch.empty((H, W, 2), dtype=torch.float32, device=f0.device)
+        ob = torch.empty_like(boxes)
+        oc = torch.empty(boxes.shape[0], dtype=torch.int32, device=f0.device)
 
-    def step():
-        ops.tvl1_flow(P, Q, p, ws=ws, out=flow)
-        ops.box_mean_flow(flow, boxes, out=(ob, oc))
+        def step():
+            ops.tvl1_flow(P, Q, p, ws=ws, out=flow, stream=cs, aux_stream=a)
+            ops.box_mean_flow(flow, boxes, out=(ob, oc), stream=cs)
 
-    with torch.cuda.stream(cs):
-        step()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=cs):
-        step()
-    ms = _graph_ms(torch, g, cs, 10)
+        with torch.cuda.stream(cs):
+            step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            step()
+        res[name] = _graph_ms(torch, g, cs, 10)
+        flows[name] = flow.clone()
+    ms = res["two_streams"]
     px = W * H
     # one iteration kernel at level 0: read u 8 B, p 16 B, data 16 B; write u 8 B, p 16 B
     it_bytes = px * 64
     return {"ms_per_step": ms, "frames_per_s": 1e3 / ms, "pixels_per_s": px / (ms * 1e-3),
+            "ms_per_step_one_stream": res["one_stream"],
+            "identical": bool(torch.equal(flows["two_streams"], flows["one_stream"])),
             "levels": p.levels, "warps": p.warps, "iters": p.iters, "iters_s": p.iters_s,
             "iter_bytes_level0": it_bytes,
-            "step": "TV-L1 flow (structure-texture of both frames, all levels) + box mean"}
+            "step": "TV-L1 flow (structure-texture of both frames, all levels, on a second "
+                    "stream ahead of the flow) + box mean"}
 
 
 def bench_working_level(ops, cs):

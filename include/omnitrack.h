@@ -21,7 +21,7 @@
  * gate and scaled boxes (ot_fb_gate, ot_box_update_scaled); the matching and
  * update phases (ot_iou_matrix, ot_assign, ot_track_update); and the
  * paper's own dense engine, TV-L1 flow with the mean-flow box prediction
- * (ot_tvl1_flow, ot_box_mean_flow).
+ * (ot_tvl1_flow, ot_tvl1_flow_async, ot_box_mean_flow).
  *
  * Conventions shared by every call
  *   - Pointers are DEVICE pointers unless marked (host).
@@ -38,9 +38,12 @@
  *   - The library allocates no device memory, keeps no pointer after a call
  *     returns and has no global stream, handle or mutable state: calls are
  *     thread-safe and may run concurrently on different streams (each
- *     caller thread owns its own stream, the lesson of Sec. III-B).  The one
- *     exception is ot_box_update_scaled_noalloc, whose scratch is a static
- *     device array per GPU shared by all its calls (see there).
+ *     caller thread owns its own stream, the lesson of Sec. III-B).  Two
+ *     exceptions: ot_box_update_scaled_noalloc, whose scratch is a static
+ *     device array per GPU shared by all its calls (see there), and
+ *     ot_tvl1_flow_async, which keeps a set of HIP events per GPU for its
+ *     fork and join (created on first use, never freed; the enqueue sequence
+ *     that uses them is serialised by a lock).
  *   - The caller owns every buffer and keeps it (and any frame a pyramid
  *     aliases as its level 0) alive until the enqueued work has finished.
  */
@@ -357,7 +360,11 @@ typedef struct {
  * iterations. */
 OT_API void ot_tvl1_default_params(ot_tvl1_params* p);
 
-/* Workspace bytes of ot_tvl1_flow for a W x H level 0 (0 if invalid). */
+/* Workspace bytes of ot_tvl1_flow / ot_tvl1_flow_async for a W x H level 0
+ * (0 if invalid): level-0 planes for the structure duals, the linearised
+ * data term, the flow and its dual, and per level the two textures and the
+ * second texture's gradient, for pyramids of up to OT_MAX_LEVELS levels of
+ * the usual sizes. */
 OT_API size_t ot_tvl1_bytes(int32_t W, int32_t H);
 
 /* Dense flow from prev_pyr to next_pyr.  Every level l < p->levels (coarse
@@ -380,6 +387,23 @@ OT_API size_t ot_tvl1_bytes(int32_t W, int32_t H);
 OT_API ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
                     const ot_tvl1_params* prm, void* ws, size_t ws_bytes, float* flow,
                     void* stream);
+
+/* ot_tvl1_flow with the structure-texture split and the texture gradients of
+ * every level enqueued on aux_stream, ahead of the flow on `stream` (Sec.
+ * V-B: independent phases run side by side).  The split of level l depends
+ * only on the frames, not on the flow of the coarser levels, so it runs while
+ * the latency-bound coarse levels leave most of the GPU idle; level l's flow
+ * waits for an event recorded on aux_stream after its planes.  aux_stream
+ * starts after an event recorded on `stream` (all work enqueued there
+ * before the call) and is joined back into `stream` before the call's last
+ * launch, so the call also works under graph capture of `stream`.  Same
+ * kernels and inputs: the flow is bit for bit that of ot_tvl1_flow.  Both
+ * streams must belong to one device; aux_stream == stream is ot_tvl1_flow.
+ * Errors: those of ot_tvl1_flow; OT_E_INVAL also for streams of different
+ * devices, OT_E_LAUNCH if an event cannot be created or recorded. */
+OT_API ot_err ot_tvl1_flow_async(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
+                          const ot_tvl1_params* prm, void* ws, size_t ws_bytes, float* flow,
+                          void* stream, void* aux_stream);
 
 /* Box prediction from a dense field (Sec. V-A): for box b, (mx, my) = the
  * mean of flow over the pixels (x, y) with integer x in [ceil(x0),

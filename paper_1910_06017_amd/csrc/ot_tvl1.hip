@@ -14,6 +14,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "omnitrack.h"
 
@@ -403,36 +404,87 @@ inline dim3 grid2(int W, int H) { return dim3((W + TV_BX - 1) / TV_BX, (H + TV_B
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace: textures T0, T1 (float), structure duals (2 x 2 x float2), image
-// gradient (float2), data (float4), flow (2 x float2), dual (2 x float4),
-// each sized for level 0 and reused by the coarser levels.
+// Workspace: structure duals (2 x 2 x float2), data (float4), flow (2 x
+// float2) and dual (2 x float4) sized for level 0 and reused by the coarser
+// levels; then, per level, the two frames' textures (float) and the second
+// texture's gradient (float2), so the structure-texture passes of every level
+// can run ahead of the flow.
 struct TvLayout {
-    size_t t0, t1, r0, r1, r2, r3, g, d, u0, u1, p0, p1, bytes;
-    static TvLayout make(int W, int H) {
-        const size_t n = (size_t)W * H;
-        TvLayout L;
+    size_t r0, r1, r2, r3, d, u0, u1, p0, p1;
+    size_t t0[OT_MAX_LEVELS], t1[OT_MAX_LEVELS], g[OT_MAX_LEVELS];
+    size_t bytes;
+    // w, h: sizes of levels 0 .. L-1
+    static TvLayout make(const int32_t* w, const int32_t* h, int L) {
+        const size_t n = (size_t)w[0] * h[0];
+        TvLayout T{};
         size_t o = 0;
         auto take = [&](size_t b) {
             const size_t at = o;
             o += al256(b);
             return at;
         };
-        L.t0 = take(n * 4);
-        L.t1 = take(n * 4);
-        L.r0 = take(n * 8);
-        L.r1 = take(n * 8);
-        L.r2 = take(n * 8);
-        L.r3 = take(n * 8);
-        L.g = take(n * 8);
-        L.d = take(n * 16);
-        L.u0 = take(n * 8);
-        L.u1 = take(n * 8);
-        L.p0 = take(n * 16);
-        L.p1 = take(n * 16);
-        L.bytes = o;
-        return L;
+        T.r0 = take(n * 8);
+        T.r1 = take(n * 8);
+        T.r2 = take(n * 8);
+        T.r3 = take(n * 8);
+        T.d = take(n * 16);
+        T.u0 = take(n * 8);
+        T.u1 = take(n * 8);
+        T.p0 = take(n * 16);
+        T.p1 = take(n * 16);
+        for (int l = 0; l < L; ++l) {
+            const size_t nl = (size_t)w[l] * h[l];
+            T.t0[l] = take(nl * 4);
+            T.t1[l] = take(nl * 4);
+            T.g[l] = take(nl * 8);
+        }
+        T.bytes = o;
+        return T;
+    }
+    // the layout for a pyramid of OT_MAX_LEVELS levels of the usual sizes
+    // (w_l = ceil(w_{l-1} / 2)), which covers every pyramid built for W x H
+    static size_t bound(int32_t W, int32_t H) {
+        int32_t w[OT_MAX_LEVELS], h[OT_MAX_LEVELS];
+        w[0] = W;
+        h[0] = H;
+        for (int l = 1; l < OT_MAX_LEVELS; ++l) {
+            w[l] = (w[l - 1] + 1) / 2;
+            h[l] = (h[l - 1] + 1) / 2;
+        }
+        return make(w, h, OT_MAX_LEVELS).bytes;
     }
 };
+
+// Fork/join events of ot_tvl1_flow_async, one set per device, created on first
+// use and kept; the enqueue sequence that records and waits on them holds the
+// mutex, so concurrent callers cannot interleave on a shared event.
+constexpr int TV_DEVICES = 64;
+std::mutex tv_ev_mu;
+hipEvent_t tv_ev[TV_DEVICES][OT_MAX_LEVELS + 1];
+bool tv_ev_ready[TV_DEVICES];
+
+hipError_t tv_events(int dev, hipEvent_t** out) {
+    if (dev < 0 || dev >= TV_DEVICES) return hipErrorInvalidDevice;
+    if (!tv_ev_ready[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        int made = 0;
+        for (; made <= OT_MAX_LEVELS && e == hipSuccess; ++made)
+            e = hipEventCreateWithFlags(&tv_ev[dev][made], hipEventDisableTiming);
+        if (e != hipSuccess)
+            for (int i = 0; i < made - 1; ++i) (void)hipEventDestroy(tv_ev[dev][i]);
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        tv_ev_ready[dev] = true;
+    }
+    *out = tv_ev[dev];
+    return hipSuccess;
+}
 
 bool params_ok(const ot_tvl1_params* p) {
     return p && p->levels >= 1 && p->levels <= OT_MAX_LEVELS && p->warps >= 1 && p->iters >= 1 &&
@@ -474,11 +526,20 @@ void ot_tvl1_default_params(ot_tvl1_params* p) {
 
 size_t ot_tvl1_bytes(int32_t W, int32_t H) {
     if (W < 1 || H < 1 || W > 16384 || H > 16384) return 0;
-    return TvLayout::make(W, H).bytes;
+    return TvLayout::bound(W, H);
 }
 
-ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_params* prm,
-                    void* ws, size_t ws_bytes, float* flow, void* stream) {
+}  // extern "C"
+
+namespace ot {
+namespace {
+
+// The structure-texture passes and gradients of every level (coarse to fine)
+// on stream a, the flow on stream s; with a != s, level l's flow waits for an
+// event recorded on a after level l's planes, and a starts after an event of
+// s (everything the caller enqueued before).  The last wait joins a into s.
+ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_params* prm,
+                void* ws, size_t ws_bytes, float* flow, hipStream_t s, hipStream_t a) {
     if (!pyr_ok(prev_pyr) || !pyr_ok(next_pyr) || !params_ok(prm) || !flow || !ws) return OT_E_INVAL;
     const int L = prm->levels;
     if (L > prev_pyr->levels || L > next_pyr->levels) return OT_E_INVAL;
@@ -486,29 +547,46 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
         if (prev_pyr->w[l] != next_pyr->w[l] || prev_pyr->h[l] != next_pyr->h[l]) return OT_E_SHAPE;
     const int W0 = prev_pyr->w[0], H0 = prev_pyr->h[0];
     if (W0 > 16384 || H0 > 16384) return OT_E_INVAL;
-    const TvLayout T = TvLayout::make(W0, H0);
-    if (ws_bytes < T.bytes || ((uintptr_t)ws & 255) || ((uintptr_t)flow & 7)) return OT_E_WORKSPACE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    const TvLayout T = TvLayout::make(prev_pyr->w, prev_pyr->h, L);
+    // the documented size, and what this pyramid's levels take
+    if (ws_bytes < TvLayout::bound(W0, H0) || ws_bytes < T.bytes || ((uintptr_t)ws & 255) ||
+        ((uintptr_t)flow & 7))
+        return OT_E_WORKSPACE;
+    const bool two = a != s;
+    hipEvent_t* ev = nullptr;
+    std::unique_lock<std::mutex> lock(tv_ev_mu, std::defer_lock);
+    if (two) {
+        hipDevice_t ds = -1, da = -1;
+        if (hipStreamGetDevice(s, &ds) != hipSuccess || hipStreamGetDevice(a, &da) != hipSuccess ||
+            ds != da)
+            return OT_E_INVAL;
+        lock.lock();
+        if (tv_events(ds, &ev) != hipSuccess) return OT_E_LAUNCH;
+    }
     uint8_t* base = static_cast<uint8_t*>(ws);
-    float* T0 = reinterpret_cast<float*>(base + T.t0);
-    float* T1 = reinterpret_cast<float*>(base + T.t1);
-    // structure duals: frame f ping-pongs between R[f][0] and R[f][1]
     float2* R[2][2] = {{reinterpret_cast<float2*>(base + T.r0), reinterpret_cast<float2*>(base + T.r1)},
                        {reinterpret_cast<float2*>(base + T.r2), reinterpret_cast<float2*>(base + T.r3)}};
-    float2* G = reinterpret_cast<float2*>(base + T.g);
     float4* D = reinterpret_cast<float4*>(base + T.d);
     float2* U[2] = {reinterpret_cast<float2*>(base + T.u0), reinterpret_cast<float2*>(base + T.u1)};
     float4* Pd[2] = {reinterpret_cast<float4*>(base + T.p0), reinterpret_cast<float4*>(base + T.p1)};
+    auto T0 = [&](int l) { return reinterpret_cast<float*>(base + T.t0[l]); };
+    auto T1 = [&](int l) { return reinterpret_cast<float*>(base + T.t1[l]); };
+    auto G = [&](int l) { return reinterpret_cast<float2*>(base + T.g[l]); };
     const float lt = prm->lam * prm->theta, k = prm->tau / prm->theta;
     const float inv_shrink = 1.0f / (1.0f + prm->tau * prm->eps / prm->theta);
-    int cu = 0;  // index of the current flow buffer
+    if (two) {
+        if (hipEventRecord(ev[OT_MAX_LEVELS], s) != hipSuccess ||
+            hipStreamWaitEvent(a, ev[OT_MAX_LEVELS], 0) != hipSuccess)
+            return OT_E_LAUNCH;
+    }
+    // ---- structure-texture split and texture gradient of every level, on a
     for (int l = L - 1; l >= 0; --l) {
         const int W = prev_pyr->w[l], H = prev_pyr->h[l];
         const dim3 gr = grid2(W, H), bl(TV_BX, TV_BY);
         const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
         const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
         const bool large = gbl.x * gbl.y >= 256;
-        // textures of both frames, the two frames side by side in every launch
+        // both frames side by side in every launch
         int cr = 0;
         for (int it = 0; it < prm->iters_s; it += TV_K) {
             const int nb = prm->iters_s - it < TV_K ? prm->iters_s - it : TV_K;
@@ -522,22 +600,33 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
             }
             if (large)
                 hipLaunchKernelGGL((k_rof_block<TV_K, TBL_X, TBL_Y, TBL_T>), dim3(gbl.x, gbl.y, 2), dim3(TBL_T), 0,
-                                   s, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+                                   a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
             else
                 hipLaunchKernelGGL((k_rof_block<TV_K, TBS_X, TBS_Y, TBS_T>), dim3(gbs.x, gbs.y, 2), dim3(TBS_T), 0,
-                                   s, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+                                   a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
             cr ^= 1;
         }
         if (prm->iters_s == 0) {
             // no structure iterations: p = 0
             for (int f = 0; f < 2; ++f)
-                hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0, s,
+                hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0, a,
                                    R[f][cr], (size_t)W * H);
         }
-        hipLaunchKernelGGL(k_texture, dim3(gr.x, gr.y, 2), bl, 0, s, prev_pyr->level[l], prev_pyr->pitch[l],
-                           next_pyr->level[l], next_pyr->pitch[l], W, H, R[0][cr], R[1][cr], T0, T1,
+        hipLaunchKernelGGL(k_texture, dim3(gr.x, gr.y, 2), bl, 0, a, prev_pyr->level[l], prev_pyr->pitch[l],
+                           next_pyr->level[l], next_pyr->pitch[l], W, H, R[0][cr], R[1][cr], T0(l), T1(l),
                            prm->theta_s, prm->alpha);
-        hipLaunchKernelGGL(k_central_grad, gr, bl, 0, s, T1, W, H, G);
+        hipLaunchKernelGGL(k_central_grad, gr, bl, 0, a, T1(l), W, H, G(l));
+        if (two && hipEventRecord(ev[l], a) != hipSuccess) return OT_E_LAUNCH;
+    }
+    // ---- flow, coarse to fine, on s
+    int cu = 0;  // index of the current flow buffer
+    for (int l = L - 1; l >= 0; --l) {
+        const int W = prev_pyr->w[l], H = prev_pyr->h[l];
+        const dim3 gr = grid2(W, H), bl(TV_BX, TV_BY);
+        const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
+        const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
+        const bool large = gbl.x * gbl.y >= 256;
+        if (two && hipStreamWaitEvent(s, ev[l], 0) != hipSuccess) return OT_E_LAUNCH;
         // initial flow: zero at the coarsest level, else the coarser flow doubled
         if (l == L - 1) {
             hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0, s,
@@ -550,7 +639,7 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
         int cp = 0;
         bool first = true;
         for (int wv = 0; wv < prm->warps; ++wv) {
-            hipLaunchKernelGGL(k_warp, gr, bl, 0, s, T0, T1, G, W, H, U[cu], D);
+            hipLaunchKernelGGL(k_warp, gr, bl, 0, s, T0(l), T1(l), G(l), W, H, U[cu], D);
             for (int it = 0; it < prm->iters; it += TV_K) {
                 const int nb = prm->iters - it < TV_K ? prm->iters - it : TV_K;
                 if (large)
@@ -572,6 +661,24 @@ ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl
         hipSuccess)
         return OT_E_LAUNCH;
     return OT_OK;
+}
+
+}  // namespace
+}  // namespace ot
+
+extern "C" {
+
+ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_params* prm,
+                    void* ws, size_t ws_bytes, float* flow, void* stream) {
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    return tvl1_run(prev_pyr, next_pyr, prm, ws, ws_bytes, flow, s, s);
+}
+
+ot_err ot_tvl1_flow_async(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
+                          const ot_tvl1_params* prm, void* ws, size_t ws_bytes, float* flow,
+                          void* stream, void* aux_stream) {
+    return tvl1_run(prev_pyr, next_pyr, prm, ws, ws_bytes, flow, static_cast<hipStream_t>(stream),
+                    static_cast<hipStream_t>(aux_stream));
 }
 
 ot_err ot_box_mean_flow(const float* flow, int32_t W, int32_t H, const float* boxes, int32_t m,

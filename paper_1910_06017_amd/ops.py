@@ -25,7 +25,8 @@ EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_t
            "ot_lk_track_ex", "ot_lk_order", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled", "ot_box_scaled_bytes",
            "ot_box_update_scaled_noalloc",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
-           "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_box_mean_flow",
+           "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_tvl1_flow_async",
+           "ot_box_mean_flow",
            "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_batch_run_stages",
            "ot_strerror", "ot_version"]
 
@@ -120,6 +121,8 @@ def lib():
         L.ot_tvl1_bytes.restype = sz
         L.ot_tvl1_flow.argtypes = [PP, PP, C.POINTER(OtTvl1Params), P, sz, P, P]
         L.ot_tvl1_flow.restype = i32
+        L.ot_tvl1_flow_async.argtypes = [PP, PP, C.POINTER(OtTvl1Params), P, sz, P, P, P]
+        L.ot_tvl1_flow_async.restype = i32
         L.ot_box_mean_flow.argtypes = [P, i32, i32, P, i32, P, P, P]
         L.ot_box_mean_flow.restype = i32
         L.ot_working_level.argtypes = [i32, i32, i32]
@@ -426,8 +429,10 @@ def tvl1_params(**kw) -> OtTvl1Params:
 
 
 def tvl1_flow(prev: Pyramid, nxt: Pyramid, params: OtTvl1Params | None = None, ws=None,
-              out=None, stream=None):
-    """Dense TV-L1 flow at level 0: (H, W, 2) float32 (u_x, u_y) per pixel."""
+              out=None, stream=None, aux_stream=None):
+    """Dense TV-L1 flow at level 0: (H, W, 2) float32 (u_x, u_y) per pixel.
+    With aux_stream, the structure-texture split runs there, ahead of the
+    flow on `stream` (ot_tvl1_flow_async; the same result)."""
     torch = _torch()
     p = tvl1_params() if params is None else params
     W, H = prev.desc.w[0], prev.desc.h[0]
@@ -435,9 +440,12 @@ def tvl1_flow(prev: Pyramid, nxt: Pyramid, params: OtTvl1Params | None = None, w
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=prev.frame.device)
     flow = torch.empty((H, W, 2), dtype=torch.float32, device=prev.frame.device) if out is None else out
-    check(lib().ot_tvl1_flow(C.byref(prev.desc), C.byref(nxt.desc), C.byref(p), _ptr(ws),
-                             ws.numel() * ws.element_size(), _ptr(flow), _stream_handle(stream)),
-          "ot_tvl1_flow")
+    args = (C.byref(prev.desc), C.byref(nxt.desc), C.byref(p), _ptr(ws),
+            ws.numel() * ws.element_size(), _ptr(flow), _stream_handle(stream))
+    if aux_stream is None:
+        check(lib().ot_tvl1_flow(*args), "ot_tvl1_flow")
+    else:
+        check(lib().ot_tvl1_flow_async(*args, _stream_handle(aux_stream)), "ot_tvl1_flow_async")
     return flow
 
 

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 25
+    assert len(syms) == 26
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -316,7 +316,13 @@ def test_tvl1_validation(L):
     assert (p.levels, p.warps, p.iters, p.iters_s) == (5, 5, 30, 50)
     n = 720 * 576
     al = lambda v: (v + 255) // 256 * 256
-    assert L.ot_tvl1_bytes(720, 576) == 2 * al(4 * n) + 5 * al(8 * n) + al(16 * n) + 2 * al(8 * n) + 2 * al(16 * n)
+    # level-0 planes (4 structure duals, data, 2 flows, 2 flow duals), then per
+    # level of an 8-level pyramid two textures and a gradient
+    per_level, w, h = 0, 720, 576
+    for _ in range(8):
+        per_level += 2 * al(4 * w * h) + al(8 * w * h)
+        w, h = (w + 1) // 2, (h + 1) // 2
+    assert L.ot_tvl1_bytes(720, 576) == 4 * al(8 * n) + al(16 * n) + 2 * al(8 * n) + 2 * al(16 * n) + per_level
     assert L.ot_tvl1_bytes(0, 5) == 0
     _, P = layout(L, levels=5)
     need = L.ot_tvl1_bytes(720, 576)
@@ -331,6 +337,15 @@ def test_tvl1_validation(L):
     assert call(p, wsb=need - 1) == Wk
     assert call(p, ws=FAKE + 16) == Wk
     assert call(p, flow=None) == E
+    # the async form validates the same way before it touches either stream
+    acall = lambda prm, ws=FAKE, wsb=need, flow=FAKE: L.ot_tvl1_flow_async(
+        C.byref(P), C.byref(P), C.byref(prm), ws, wsb, flow, None, None)
+    q = ops.OtTvl1Params()
+    C.memmove(C.byref(q), C.byref(p), C.sizeof(p))
+    q.levels = 0
+    assert acall(q) == E
+    assert acall(p, wsb=need - 1) == Wk
+    assert acall(p, flow=None) == E
     assert L.ot_box_mean_flow(FAKE, 10, 10, FAKE, -1, FAKE, FAKE, None) == E
     assert L.ot_box_mean_flow(FAKE + 4, 10, 10, FAKE, 3, FAKE, FAKE, None) == E
     assert L.ot_box_mean_flow(None, 10, 10, None, 0, None, None, None) == 0

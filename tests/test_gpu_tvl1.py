@@ -177,3 +177,66 @@ def test_box_mean_flow_edges(ops):
     e = torch.zeros((0, 4), dtype=torch.float32, device="cuda")
     ob, oc = ops.box_mean_flow(flow, e)
     assert ob.shape == (0, 4)
+
+
+@pytest.mark.parametrize("W,H,kw", [
+    (720, 576, dict()),                                          # the box scene's defaults
+    (160, 128, dict(iters_s=0)),                                 # no structure iterations
+    (33, 17, dict(levels=3, warps=3, iters=7, iters_s=5)),       # ragged, tiny coarse levels
+])
+def test_tvl1_async_matches_one_stream(ops, W, H, kw):
+    """The structure-texture split on a second stream (ot_tvl1_flow_async)
+    gives the one-stream flow bit for bit: same kernels, same inputs."""
+    if W == 720:
+        w = synth.sd_boxes_workload()
+        f0, f1 = w.frame0, w.frame1
+    else:
+        f0, f1, _ = synth.shifted_pair(W + H, W=W, H=H, shift=(1.3, -0.7))
+    p = ops.tvl1_params(**kw)
+    P = ops.pyramid_build(dev(f0), p.levels)
+    Q = ops.pyramid_build(dev(f1), p.levels)
+    ref = ops.tvl1_flow(P, Q, p)
+    torch.cuda.synchronize()
+    s, a = torch.cuda.Stream(), torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.empty_like(ref)
+    for _ in range(2):       # the second call reuses the workspace and the events
+        g.fill_(float("nan"))
+        torch.cuda.current_stream().synchronize()
+        s.wait_stream(torch.cuda.current_stream())
+        ops.tvl1_flow(P, Q, p, out=g, stream=s, aux_stream=a)
+        s.synchronize()
+        assert torch.equal(g, ref)
+
+
+def test_tvl1_async_graph_replays(ops):
+    """ot_tvl1_flow_async captured in a HIP graph (the auxiliary stream forks
+    from and joins the captured stream): every replay, with eager work and
+    synchronisations between replays, gives the eager flow bit for bit."""
+    f0, f1, _ = synth.shifted_pair(77, W=200, H=150, shift=(-2.2, 1.6))
+    p = ops.tvl1_params(levels=4, warps=3, iters=10, iters_s=15)
+    P = ops.pyramid_build(dev(f0), p.levels)
+    Q = ops.pyramid_build(dev(f1), p.levels)
+    ref = ops.tvl1_flow(P, Q, p)
+    torch.cuda.synchronize()
+    s, a = torch.cuda.Stream(), torch.cuda.Stream()
+    ws = torch.empty(int(ops.lib().ot_tvl1_bytes(200, 150)), dtype=torch.uint8, device="cuda")
+    g = torch.empty_like(ref)
+    with torch.cuda.stream(s):
+        ops.tvl1_flow(P, Q, p, ws=ws, out=g, stream=s, aux_stream=a)   # warm-up
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        ops.tvl1_flow(P, Q, p, ws=ws, out=g, stream=s, aux_stream=a)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(g, ref), k
+        # eager work on both streams between replays
+        with torch.cuda.stream(s):
+            ops.tvl1_flow(Q, P, p, ws=ws, stream=s, aux_stream=a)
+        torch.cuda.synchronize()
