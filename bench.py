@@ -429,8 +429,23 @@ def bench_dense(ops, wl, f0, f1, boxes, cs):
     px = W * H
     # one iteration kernel at level 0: read u 8 B, p 16 B, data 16 B; write u 8 B, p 16 B
     it_bytes = px * 64
+    # Algorithmic bytes of the step's passes over every level, counted per
+    # iteration as if each read its inputs from and wrote its outputs to HBM:
+    # TV-L1 iteration 64 B/pixel; structure dual iteration per frame: p in and
+    # out 16 B + the uint8 level 1 B; warp: I0, I1 4 B each, gradient 8 B,
+    # flow 8 B, data out 16 B = 40 B; texture per frame: level 1 B, p 8 B,
+    # texture out 4 B; gradient: texture 4 B in, 8 B out.
+    alg = 0
+    for l in range(p.levels):
+        n = P.desc.w[l] * P.desc.h[l]
+        alg += n * (p.warps * p.iters * 64 + p.iters_s * 2 * 17 + p.warps * 40 + 2 * 13 + 12)
+    achieved = alg / (ms * 1e-3) / 1e9
     return {"ms_per_step": ms, "frames_per_s": 1e3 / ms, "pixels_per_s": px / (ms * 1e-3),
             "ms_per_step_one_stream": res["one_stream"],
+            "roofline": {"bound": "hbm", "kernel": "whole dense step (all levels' passes)",
+                         "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                         "frac": achieved / 8000.0, "traffic": None,
+                         "algorithmic_bytes_per_step": alg},
             "identical": bool(torch.equal(flows["two_streams"], flows["one_stream"])),
             "levels": p.levels, "warps": p.warps, "iters": p.iters, "iters_s": p.iters_s,
             "iter_bytes_level0": it_bytes,
