@@ -152,6 +152,15 @@ constexpr int TBL_X = 64, TBL_Y = 16, TBL_T = 1024;
 #define OT_TVS_X 16
 #endif
 constexpr int TBS_X = OT_TVS_X, TBS_Y = OT_TVS_Y, TBS_T = OT_TVS_T;
+// Levels whose small-tile grid would still leave most compute units idle
+// (fewer than 256 workgroups) are bound by each launch's fixed cost (the
+// loads, the stores, the dispatch): their TV-L1 iterations run OT_TV_KT per
+// launch on the same tiles with an OT_TV_KT-pixel halo, one region pixel per
+// thread.
+#ifndef OT_TV_KT
+#define OT_TV_KT 10
+#endif
+constexpr int TBT_T = 1024;
 
 // n (<= K) TV-L1 iterations: v = data step of u, u = v + theta div p (both
 // flow components), p = projection onto the unit ball of (p + (tau/theta)
@@ -399,6 +408,8 @@ __global__ __launch_bounds__(BM_THREADS) void k_box_mean(const float2* __restric
 // ------------------------------------------------------------------ host side
 // iterations per blocked launch (the halo width)
 constexpr int TV_K = OT_TV_K;
+constexpr int TV_KT = OT_TV_KT;
+static_assert(TileGeom<TV_KT, TBS_X, TBS_Y, TBT_T>::RN <= TBT_T, "one region pixel per thread");
 
 inline dim3 grid2(int W, int H) { return dim3((W + TV_BX - 1) / TV_BX, (H + TV_BY - 1) / TV_BY); }
 
@@ -638,12 +649,18 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
         }
         int cp = 0;
         bool first = true;
+        const bool tiny = !large && gbs.x * gbs.y < 256;
+        const int kb = tiny ? TV_KT : TV_K;  // iterations per launch
         for (int wv = 0; wv < prm->warps; ++wv) {
             hipLaunchKernelGGL(k_warp, gr, bl, 0, s, T0(l), T1(l), G(l), W, H, U[cu], D);
-            for (int it = 0; it < prm->iters; it += TV_K) {
-                const int nb = prm->iters - it < TV_K ? prm->iters - it : TV_K;
+            for (int it = 0; it < prm->iters; it += kb) {
+                const int nb = prm->iters - it < kb ? prm->iters - it : kb;
                 if (large)
                     hipLaunchKernelGGL((k_tvl1_block<TV_K, TBL_X, TBL_Y, TBL_T>), gbl, dim3(TBL_T), 0, s, D,
+                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       inv_shrink, first ? 1 : 0, nb);
+                else if (tiny)
+                    hipLaunchKernelGGL((k_tvl1_block<TV_KT, TBS_X, TBS_Y, TBT_T>), gbs, dim3(TBT_T), 0, s, D,
                                        U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 else
