@@ -161,6 +161,18 @@ constexpr int TBS_X = OT_TVS_X, TBS_Y = OT_TVS_Y, TBS_T = OT_TVS_T;
 #define OT_TV_KT 10
 #endif
 constexpr int TBT_T = 1024;
+// Levels between: the TV-L1 iterations on wider tiles (less halo per output)
+// when those still give 256 workgroups.
+#ifndef OT_TVM_X
+#define OT_TVM_X 16
+#endif
+#ifndef OT_TVM_Y
+#define OT_TVM_Y 16
+#endif
+#ifndef OT_TVM_T
+#define OT_TVM_T 676
+#endif
+constexpr int TBM_X = OT_TVM_X, TBM_Y = OT_TVM_Y, TBM_T = OT_TVM_T;
 
 // n (<= K) TV-L1 iterations: v = data step of u, u = v + theta div p (both
 // flow components), p = projection onto the unit ball of (p + (tau/theta)
@@ -410,6 +422,7 @@ __global__ __launch_bounds__(BM_THREADS) void k_box_mean(const float2* __restric
 constexpr int TV_K = OT_TV_K;
 constexpr int TV_KT = OT_TV_KT;
 static_assert(TileGeom<TV_KT, TBS_X, TBS_Y, TBT_T>::RN <= TBT_T, "one region pixel per thread");
+static_assert(TileGeom<TV_K, TBM_X, TBM_Y, TBM_T>::RN <= TBM_T, "one region pixel per thread");
 
 inline dim3 grid2(int W, int H) { return dim3((W + TV_BX - 1) / TV_BX, (H + TV_BY - 1) / TV_BY); }
 
@@ -650,6 +663,8 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
         int cp = 0;
         bool first = true;
         const bool tiny = !large && gbs.x * gbs.y < 256;
+        const dim3 gbm((W + TBM_X - 1) / TBM_X, (H + TBM_Y - 1) / TBM_Y);
+        const bool mid = !large && !tiny && gbm.x * gbm.y >= 256;
         const int kb = tiny ? TV_KT : TV_K;  // iterations per launch
         for (int wv = 0; wv < prm->warps; ++wv) {
             hipLaunchKernelGGL(k_warp, gr, bl, 0, s, T0(l), T1(l), G(l), W, H, U[cu], D);
@@ -661,6 +676,10 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
                                        inv_shrink, first ? 1 : 0, nb);
                 else if (tiny)
                     hipLaunchKernelGGL((k_tvl1_block<TV_KT, TBS_X, TBS_Y, TBT_T>), gbs, dim3(TBT_T), 0, s, D,
+                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       inv_shrink, first ? 1 : 0, nb);
+                else if (mid)
+                    hipLaunchKernelGGL((k_tvl1_block<TV_K, TBM_X, TBM_Y, TBM_T>), gbm, dim3(TBM_T), 0, s, D,
                                        U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 else
