@@ -142,6 +142,14 @@ struct TileGeom {
 // Large tiles for large levels; small ones where large tiles would leave
 // most compute units idle (each workgroup's critical path is its region).
 constexpr int TBL_X = 64, TBL_Y = 16, TBL_T = 1024;
+// tiles of the TV-L1 iterations on large levels
+#ifndef OT_TVF_X
+#define OT_TVF_X 32
+#endif
+#ifndef OT_TVF_Y
+#define OT_TVF_Y 32
+#endif
+constexpr int TBF_X = OT_TVF_X, TBF_Y = OT_TVF_Y, TBF_T = 1024;
 #ifndef OT_TVS_T
 #define OT_TVS_T 512
 #endif
@@ -662,6 +670,7 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
         }
         int cp = 0;
         bool first = true;
+        const dim3 gbf((W + TBF_X - 1) / TBF_X, (H + TBF_Y - 1) / TBF_Y);
         const bool tiny = !large && gbs.x * gbs.y < 256;
         const dim3 gbm((W + TBM_X - 1) / TBM_X, (H + TBM_Y - 1) / TBM_Y);
         const bool mid = !large && !tiny && gbm.x * gbm.y >= 256;
@@ -671,7 +680,7 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
             for (int it = 0; it < prm->iters; it += kb) {
                 const int nb = prm->iters - it < kb ? prm->iters - it : kb;
                 if (large)
-                    hipLaunchKernelGGL((k_tvl1_block<TV_K, TBL_X, TBL_Y, TBL_T>), gbl, dim3(TBL_T), 0, s, D,
+                    hipLaunchKernelGGL((k_tvl1_block<TV_K, TBF_X, TBF_Y, TBF_T>), gbf, dim3(TBF_T), 0, s, D,
                                        U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 else if (tiny)
