@@ -87,24 +87,28 @@ __device__ __forceinline__ T bilin(float x, float y, int W, int H, Get&& get) {
            (1.0f - a) * b * get(x0, y1) + a * b * get(x1, y1);
 }
 
-// Linearisation of the data term at the current flow u0:
+// Linearisation of the data term at pixel (x, y) and the current flow u0:
 // data = (gx, gy, rho0, gx^2 + gy^2) with rho(u) = rho0 + g . u.
-__global__ __launch_bounds__(TV_BX* TV_BY) void k_warp(const float* __restrict__ I0,
-                                                       const float* __restrict__ I1,
-                                                       const float2* __restrict__ G1, int W, int H,
-                                                       const float2* __restrict__ u,
-                                                       float4* __restrict__ data) {
-    const int x = blockIdx.x * TV_BX + threadIdx.x, y = blockIdx.y * TV_BY + threadIdx.y;
-    if (x >= W || y >= H) return;
-    const size_t i = (size_t)y * W + x;
-    const float2 u0 = u[i];
+__device__ __forceinline__ float4 warp_data(const float* __restrict__ I0,
+                                            const float* __restrict__ I1,
+                                            const float2* __restrict__ G1, int W, int H, int x,
+                                            int y, float2 u0) {
     const float wx = (float)x + u0.x, wy = (float)y + u0.y;
     const float I1w = bilin<float>(wx, wy, W, H, [&](int a, int b) { return I1[(size_t)b * W + a]; });
     const float gx = bilin<float>(wx, wy, W, H, [&](int a, int b) { return G1[(size_t)b * W + a].x; });
     const float gy = bilin<float>(wx, wy, W, H, [&](int a, int b) { return G1[(size_t)b * W + a].y; });
-    const float rho0 = I1w - gx * u0.x - gy * u0.y - I0[i];
-    data[i] = make_float4(gx, gy, rho0, gx * gx + gy * gy);
+    const float rho0 = I1w - gx * u0.x - gy * u0.y - I0[(size_t)y * W + x];
+    return make_float4(gx, gy, rho0, gx * gx + gy * gy);
 }
+
+// Where the first launch of a warp takes the data term from: the textures and
+// the gradient of the second (I0 == nullptr: read `data` as written before).
+struct WarpSrc {
+    const float* I0;
+    const float* I1;
+    const float2* G1;
+    float4* data_out;  // the tile's own pixels' data, for the warp's later launches
+};
 
 // Pointwise L1 data step: v minimising |v - u|^2 / (2 theta) + lam |rho(v)|.
 __device__ __forceinline__ float2 data_step(float2 u, float4 d, float lt) {
@@ -186,8 +190,11 @@ constexpr int TBM_X = OT_TVM_X, TBM_Y = OT_TVM_Y, TBM_T = OT_TVM_T;
 // flow components), p = projection onto the unit ball of (p + (tau/theta)
 // grad u) / (1 + tau eps / theta); p is (p1x, p1y, p2x, p2y) per pixel and
 // taken as 0 when `first`.
+// With ws.I0 set (the first launch of a warp) the data term of every region
+// pixel is computed from the flow the launch reads, and the tile's own
+// pixels' terms are stored for the warp's later launches.
 template <int K, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_tvl1_block(const float4* __restrict__ data,
+__global__ __launch_bounds__(NT) void k_tvl1_block(const float4* __restrict__ data, WarpSrc ws,
                                                            const float2* __restrict__ u_in,
                                                            const float4* __restrict__ p_in,
                                                            float2* __restrict__ u_out,
@@ -204,12 +211,19 @@ __global__ __launch_bounds__(NT) void k_tvl1_block(const float4* __restrict__ da
     for (int q = 0; q < G::PER; ++q) {
         const int r = tid + q * NT;
         if (r >= G::RN) break;
-        const int gx = ox + r % G::RX, gy = oy + r / G::RX;
+        const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
         const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
         const size_t i = in ? (size_t)gy * W + gx : 0;
-        su[r] = in ? u_in[i] : make_float2(0.0f, 0.0f);
+        const float2 u0 = in ? u_in[i] : make_float2(0.0f, 0.0f);
+        su[r] = u0;
         sp[r] = (in && !first) ? p_in[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        dat[q] = in ? data[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (ws.I0) {
+            dat[q] = in ? warp_data(ws.I0, ws.I1, ws.G1, W, H, gx, gy, u0)
+                        : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (in && lx >= K && lx < K + TX && ly >= K && ly < K + TY) ws.data_out[i] = dat[q];
+        } else {
+            dat[q] = in ? data[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
     }
     __syncthreads();
     for (int it = 0; it < n; ++it) {
@@ -618,10 +632,13 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
         const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
         const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
         const bool large = gbl.x * gbl.y >= 256;
-        // both frames side by side in every launch
+        // both frames side by side in every launch; levels whose small-tile
+        // grid stays under 256 workgroups take OT_TV_KT steps per launch
+        const bool tiny_s = !large && gbs.x * gbs.y < 256;
+        const int kr = tiny_s ? TV_KT : TV_K;
         int cr = 0;
-        for (int it = 0; it < prm->iters_s; it += TV_K) {
-            const int nb = prm->iters_s - it < TV_K ? prm->iters_s - it : TV_K;
+        for (int it = 0; it < prm->iters_s; it += kr) {
+            const int nb = prm->iters_s - it < kr ? prm->iters_s - it : kr;
             FramePair fp;
             for (int f = 0; f < 2; ++f) {
                 const ot_pyr* py = f == 0 ? prev_pyr : next_pyr;
@@ -632,6 +649,9 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
             }
             if (large)
                 hipLaunchKernelGGL((k_rof_block<TV_K, TBL_X, TBL_Y, TBL_T>), dim3(gbl.x, gbl.y, 2), dim3(TBL_T), 0,
+                                   a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+            else if (tiny_s)
+                hipLaunchKernelGGL((k_rof_block<TV_KT, TBS_X, TBS_Y, TBT_T>), dim3(gbs.x, gbs.y, 2), dim3(TBT_T), 0,
                                    a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
             else
                 hipLaunchKernelGGL((k_rof_block<TV_K, TBS_X, TBS_Y, TBS_T>), dim3(gbs.x, gbs.y, 2), dim3(TBS_T), 0,
@@ -676,24 +696,29 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
         const bool mid = !large && !tiny && gbm.x * gbm.y >= 256;
         const int kb = tiny ? TV_KT : TV_K;  // iterations per launch
         for (int wv = 0; wv < prm->warps; ++wv) {
-            hipLaunchKernelGGL(k_warp, gr, bl, 0, s, T0(l), T1(l), G(l), W, H, U[cu], D);
             for (int it = 0; it < prm->iters; it += kb) {
                 const int nb = prm->iters - it < kb ? prm->iters - it : kb;
+                // the warp's first launch linearises the data term at the flow it reads
+                const WarpSrc wsrc = it == 0 ? WarpSrc{T0(l), T1(l), G(l), D}
+                                             : WarpSrc{nullptr, nullptr, nullptr, nullptr};
+                // the last launch of level 0 writes the caller's flow
+                const bool last = l == 0 && wv == prm->warps - 1 && it + kb >= prm->iters;
+                float2* uo = last ? reinterpret_cast<float2*>(flow) : U[cu ^ 1];
                 if (large)
                     hipLaunchKernelGGL((k_tvl1_block<TV_K, TBF_X, TBF_Y, TBF_T>), gbf, dim3(TBF_T), 0, s, D,
-                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       wsrc, U[cu], Pd[cp], uo, Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 else if (tiny)
                     hipLaunchKernelGGL((k_tvl1_block<TV_KT, TBS_X, TBS_Y, TBT_T>), gbs, dim3(TBT_T), 0, s, D,
-                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       wsrc, U[cu], Pd[cp], uo, Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 else if (mid)
                     hipLaunchKernelGGL((k_tvl1_block<TV_K, TBM_X, TBM_Y, TBM_T>), gbm, dim3(TBM_T), 0, s, D,
-                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       wsrc, U[cu], Pd[cp], uo, Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 else
                     hipLaunchKernelGGL((k_tvl1_block<TV_K, TBS_X, TBS_Y, TBS_T>), gbs, dim3(TBS_T), 0, s, D,
-                                       U[cu], Pd[cp], U[cu ^ 1], Pd[cp ^ 1], W, H, lt, prm->theta, k,
+                                       wsrc, U[cu], Pd[cp], uo, Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 cu ^= 1;
                 cp ^= 1;
@@ -702,9 +727,6 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
         }
     }
     if (hipGetLastError() != hipSuccess) return OT_E_LAUNCH;
-    if (hipMemcpyAsync(flow, U[cu], (size_t)W0 * H0 * sizeof(float2), hipMemcpyDeviceToDevice, s) !=
-        hipSuccess)
-        return OT_E_LAUNCH;
     return OT_OK;
 }
 
