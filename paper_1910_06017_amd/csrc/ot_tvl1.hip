@@ -101,13 +101,27 @@ __device__ __forceinline__ float4 warp_data(const float* __restrict__ I0,
     return make_float4(gx, gy, rho0, gx * gx + gy * gy);
 }
 
+// Flow of a finer level at (x, y) from the coarser one (Wc x Hc): 2 u(x / 2).
+__device__ __forceinline__ float2 upsample_at(const float2* __restrict__ uc, int Wc, int Hc, int x,
+                                              int y) {
+    const float sx = 0.5f * (float)x, sy = 0.5f * (float)y;
+    const float a = bilin<float>(sx, sy, Wc, Hc, [&](int i, int j) { return uc[(size_t)j * Wc + i].x; });
+    const float b = bilin<float>(sx, sy, Wc, Hc, [&](int i, int j) { return uc[(size_t)j * Wc + i].y; });
+    return make_float2(2.0f * a, 2.0f * b);
+}
+
 // Where the first launch of a warp takes the data term from: the textures and
-// the gradient of the second (I0 == nullptr: read `data` as written before).
+// the gradient of the second (I0 == nullptr: read `data` as written before);
+// and where the first launch of a level takes the flow from: init 0 reads
+// u_in, 1 starts from zero (the coarsest level), 2 upsamples the coarser
+// level's flow uc (Wc x Hc).
 struct WarpSrc {
     const float* I0;
     const float* I1;
     const float2* G1;
     float4* data_out;  // the tile's own pixels' data, for the warp's later launches
+    const float2* uc;
+    int Wc, Hc, init;
 };
 
 // Pointwise L1 data step: v minimising |v - u|^2 / (2 theta) + lam |rho(v)|.
@@ -153,7 +167,10 @@ constexpr int TBL_X = 64, TBL_Y = 16, TBL_T = 1024;
 #ifndef OT_TVF_Y
 #define OT_TVF_Y 32
 #endif
-constexpr int TBF_X = OT_TVF_X, TBF_Y = OT_TVF_Y, TBF_T = 1024;
+#ifndef OT_TVF_K
+#define OT_TVF_K 5
+#endif
+constexpr int TBF_X = OT_TVF_X, TBF_Y = OT_TVF_Y, TBF_T = 1024, TV_KF = OT_TVF_K;
 #ifndef OT_TVS_T
 #define OT_TVS_T 512
 #endif
@@ -214,7 +231,9 @@ __global__ __launch_bounds__(NT) void k_tvl1_block(const float4* __restrict__ da
         const int lx = r % G::RX, ly = r / G::RX, gx = ox + lx, gy = oy + ly;
         const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
         const size_t i = in ? (size_t)gy * W + gx : 0;
-        const float2 u0 = in ? u_in[i] : make_float2(0.0f, 0.0f);
+        float2 u0 = make_float2(0.0f, 0.0f);
+        if (in && ws.init == 0) u0 = u_in[i];
+        else if (in && ws.init == 2) u0 = upsample_at(ws.uc, ws.Wc, ws.Hc, gx, gy);
         su[r] = u0;
         sp[r] = (in && !first) ? p_in[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (ws.I0) {
@@ -367,17 +386,6 @@ __global__ __launch_bounds__(NT) void k_rof_block(FramePair fp, int W, int H, fl
         if (lx < K || lx >= K + TX || ly < K || ly >= K + TY || gx >= W || gy >= H) continue;
         p_out[(size_t)gy * W + gx] = sp[r];
     }
-}
-
-// Flow of a finer level (W x H) from the coarser one (Wc x Hc): 2 u(x / 2).
-__global__ __launch_bounds__(TV_BX* TV_BY) void k_upsample(const float2* __restrict__ uc, int Wc, int Hc,
-                                                           float2* __restrict__ uf, int W, int H) {
-    const int x = blockIdx.x * TV_BX + threadIdx.x, y = blockIdx.y * TV_BY + threadIdx.y;
-    if (x >= W || y >= H) return;
-    const float sx = 0.5f * (float)x, sy = 0.5f * (float)y;
-    const float a = bilin<float>(sx, sy, Wc, Hc, [&](int i, int j) { return uc[(size_t)j * Wc + i].x; });
-    const float b = bilin<float>(sx, sy, Wc, Hc, [&](int i, int j) { return uc[(size_t)j * Wc + i].y; });
-    uf[(size_t)y * W + x] = make_float2(2.0f * a, 2.0f * b);
 }
 
 // Zero flow (the coarsest level's start).
@@ -674,38 +682,41 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
     int cu = 0;  // index of the current flow buffer
     for (int l = L - 1; l >= 0; --l) {
         const int W = prev_pyr->w[l], H = prev_pyr->h[l];
-        const dim3 gr = grid2(W, H), bl(TV_BX, TV_BY);
         const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
         const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
         const bool large = gbl.x * gbl.y >= 256;
         if (two && hipStreamWaitEvent(s, ev[l], 0) != hipSuccess) return OT_E_LAUNCH;
-        // initial flow: zero at the coarsest level, else the coarser flow doubled
-        if (l == L - 1) {
-            hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0, s,
-                               U[cu], (size_t)W * H);
-        } else {
-            hipLaunchKernelGGL(k_upsample, gr, bl, 0, s, U[cu], prev_pyr->w[l + 1], prev_pyr->h[l + 1],
-                               U[cu ^ 1], W, H);
-            cu ^= 1;
-        }
+        // initial flow (in the level's first launch): zero at the coarsest
+        // level, else the coarser flow doubled; U[cu] holds the coarser flow
         int cp = 0;
         bool first = true;
         const dim3 gbf((W + TBF_X - 1) / TBF_X, (H + TBF_Y - 1) / TBF_Y);
         const bool tiny = !large && gbs.x * gbs.y < 256;
         const dim3 gbm((W + TBM_X - 1) / TBM_X, (H + TBM_Y - 1) / TBM_Y);
         const bool mid = !large && !tiny && gbm.x * gbm.y >= 256;
-        const int kb = tiny ? TV_KT : TV_K;  // iterations per launch
+        const int kb = tiny ? TV_KT : large ? TV_KF : TV_K;  // iterations per launch
         for (int wv = 0; wv < prm->warps; ++wv) {
             for (int it = 0; it < prm->iters; it += kb) {
                 const int nb = prm->iters - it < kb ? prm->iters - it : kb;
                 // the warp's first launch linearises the data term at the flow it reads
-                const WarpSrc wsrc = it == 0 ? WarpSrc{T0(l), T1(l), G(l), D}
-                                             : WarpSrc{nullptr, nullptr, nullptr, nullptr};
+                WarpSrc wsrc{};
+                if (it == 0) {
+                    wsrc.I0 = T0(l);
+                    wsrc.I1 = T1(l);
+                    wsrc.G1 = G(l);
+                    wsrc.data_out = D;
+                }
+                if (wv == 0 && it == 0) {
+                    wsrc.init = l == L - 1 ? 1 : 2;
+                    wsrc.uc = U[cu];
+                    wsrc.Wc = l + 1 < L ? prev_pyr->w[l + 1] : 0;
+                    wsrc.Hc = l + 1 < L ? prev_pyr->h[l + 1] : 0;
+                }
                 // the last launch of level 0 writes the caller's flow
                 const bool last = l == 0 && wv == prm->warps - 1 && it + kb >= prm->iters;
                 float2* uo = last ? reinterpret_cast<float2*>(flow) : U[cu ^ 1];
                 if (large)
-                    hipLaunchKernelGGL((k_tvl1_block<TV_K, TBF_X, TBF_Y, TBF_T>), gbf, dim3(TBF_T), 0, s, D,
+                    hipLaunchKernelGGL((k_tvl1_block<TV_KF, TBF_X, TBF_Y, TBF_T>), gbf, dim3(TBF_T), 0, s, D,
                                        wsrc, U[cu], Pd[cp], uo, Pd[cp ^ 1], W, H, lt, prm->theta, k,
                                        inv_shrink, first ? 1 : 0, nb);
                 else if (tiny)
