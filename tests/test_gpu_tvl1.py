@@ -183,6 +183,7 @@ def test_box_mean_flow_edges(ops):
     (720, 576, dict()),                                          # the box scene's defaults
     (160, 128, dict(iters_s=0)),                                 # no structure iterations
     (33, 17, dict(levels=3, warps=3, iters=7, iters_s=5)),       # ragged, tiny coarse levels
+    (97, 61, dict(levels=1, warps=2, iters=12, iters_s=7)),      # one level
 ])
 def test_tvl1_async_matches_one_stream(ops, W, H, kw):
     """The structure-texture split on a second stream (ot_tvl1_flow_async)
@@ -207,6 +208,13 @@ def test_tvl1_async_matches_one_stream(ops, W, H, kw):
         ops.tvl1_flow(P, Q, p, out=g, stream=s, aux_stream=a)
         s.synchronize()
         assert torch.equal(g, ref)
+    # the auxiliary stream being the stream itself is the one-stream call
+    g.fill_(float("nan"))
+    torch.cuda.current_stream().synchronize()
+    s.wait_stream(torch.cuda.current_stream())
+    ops.tvl1_flow(P, Q, p, out=g, stream=s, aux_stream=s)
+    s.synchronize()
+    assert torch.equal(g, ref)
 
 
 def test_tvl1_async_graph_replays(ops):
