@@ -562,8 +562,10 @@ def bench_batched(a):
     jobs = batch.jobs_from_workloads(ws, "cuda:0")
     npts = sum(w.n for w in ws)
     sched = batch.default_schedule(batch.bucket_key(jobs))
-    cfg = batch.BatchConfig(max_jobs=32, max_points=npts, max_boxes=2048, max_tiles=1 << 15,
-                            max_levels=5, **sched)
+    # the graph's capacities fitted to the tick (jobs, points, boxes, pyramid
+    # tiles): a graph sized past them dispatches idle workgroups every replay
+    cfg = batch.fit_capacities(batch.BatchConfig(max_jobs=32, max_points=npts, max_boxes=2048,
+                                                 max_tiles=1 << 15, max_levels=5, **sched), jobs)
     runner = batch.BatchRunner(cfg, tables=1)
     runner.pack(jobs, table=0)
     g = runner.capture(0)
@@ -607,7 +609,9 @@ def bench_batched(a):
             flops += lk_kernel_flops(it.cpu().numpy(), lam.cpu().numpy())
     achieved = flops / (trk_ms * 1e-3) / 1e12
     return {"streams": len(ws), "points_per_tick": npts, "ms_per_tick": ms,
-            "tracked_points_per_s": npts / (ms * 1e-3), "schedule": sched, "ok_fraction": ok,
+            "tracked_points_per_s": npts / (ms * 1e-3), "schedule": sched,
+            "capacities": {"jobs": cfg.max_jobs, "points": cfg.max_points,
+                           "boxes": cfg.max_boxes, "tiles": cfg.max_tiles}, "ok_fraction": ok,
             "tracking_stage_ms": trk_ms,
             "roofline": {"bound": "alu", "kernel": "k_lk_batch<7,21,4,1,1> + k_batch_box",
                          "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

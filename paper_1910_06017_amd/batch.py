@@ -111,6 +111,64 @@ def jobs_from_workloads(workloads: list, device="cuda") -> list:
     return jobs
 
 
+def _c_jobs(jobs: list):
+    """The ot_job array for `jobs` (device pointers only; nothing is copied)."""
+    arr = (ops.OtJob * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        o = arr[i]
+        o.prev = j.prev.desc
+        o.next_frame = _ptr(j.next_frame)
+        o.next_pitch = int(j.next_frame.stride(0))
+        o.next_ws = _ptr(j.next_ws)
+        o.next_ws_bytes = int(j.next_ws.numel()) if j.next_ws is not None else 0
+        o.levels = j.levels
+        o.pts, o.n = _ptr(j.pts), j.n
+        o.next_pts, o.status, o.err = _ptr(j.next_pts), _ptr(j.status), _ptr(j.err)
+        o.boxes, o.m, o.box_id = _ptr(j.boxes), j.m, _ptr(j.box_id)
+        o.out_boxes, o.out_count = _ptr(j.out_boxes), _ptr(j.out_count)
+    return arr
+
+
+_E_WORKSPACE = next(k for k, v in ops.ERRORS.items() if v == "OT_E_WORKSPACE")
+
+
+def fit_capacities(cfg: BatchConfig, jobs: list) -> BatchConfig:
+    """cfg with the smallest capacities `jobs` fit: jobs, points and boxes
+    are their totals, and the pyramid tiles are found by bisection with
+    ot_batch_pack (host only), which refuses a table whose fused pyramid
+    stages need more tiles than max_tiles.  A graph captured for a bucket of
+    ticks with these capacities launches no idle workgroups for them."""
+    import dataclasses
+
+    import torch
+
+    arr = _c_jobs(jobs)
+    base = dataclasses.replace(cfg, max_jobs=max(1, len(jobs)),
+                               max_points=max(1, sum(j.n for j in jobs)),
+                               max_boxes=max(1, sum(j.m for j in jobs)))
+
+    def fits(tiles: int) -> bool:
+        c = dataclasses.replace(base, max_tiles=tiles).to_c()
+        nb = int(ops.lib().ot_batch_table_bytes(C.byref(c)))
+        host = torch.empty(nb, dtype=torch.uint8)
+        e = int(ops.lib().ot_batch_pack(arr, len(jobs), C.byref(c), int(host.data_ptr()), nb, None))
+        if e not in (0, _E_WORKSPACE):
+            ops.check(e, "ot_batch_pack")
+        return e == 0
+
+    hi = max(1, cfg.max_tiles)
+    if not fits(hi):
+        raise ValueError("the jobs need more pyramid tiles than cfg.max_tiles")
+    lo = 0  # fits(lo) is false for any non-empty pyramid stage; hi fits
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if fits(mid):
+            hi = mid
+        else:
+            lo = mid
+    return dataclasses.replace(base, max_tiles=hi)
+
+
 class BatchRunner:
     """Owns the pinned host table and the device table for one capacity."""
 
@@ -137,19 +195,7 @@ class BatchRunner:
         ev = self.events[t]
         if ev is not None:
             ev.synchronize()  # the copy that last read this host table has executed
-        arr = (ops.OtJob * max(1, len(jobs)))()
-        for i, j in enumerate(jobs):
-            o = arr[i]
-            o.prev = j.prev.desc
-            o.next_frame = _ptr(j.next_frame)
-            o.next_pitch = int(j.next_frame.stride(0))
-            o.next_ws = _ptr(j.next_ws)
-            o.next_ws_bytes = int(j.next_ws.numel()) if j.next_ws is not None else 0
-            o.levels = j.levels
-            o.pts, o.n = _ptr(j.pts), j.n
-            o.next_pts, o.status, o.err = _ptr(j.next_pts), _ptr(j.status), _ptr(j.err)
-            o.boxes, o.m, o.box_id = _ptr(j.boxes), j.m, _ptr(j.box_id)
-            o.out_boxes, o.out_count = _ptr(j.out_boxes), _ptr(j.out_count)
+        arr = _c_jobs(jobs)
         nxt = (ops.OtPyr * max(1, len(jobs)))()
         ops.check(ops.lib().ot_batch_pack(arr, len(jobs), C.byref(self.ccfg),
                                           int(self.host[t].data_ptr()), self.table_bytes, nxt),

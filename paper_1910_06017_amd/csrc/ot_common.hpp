@@ -105,8 +105,8 @@ struct TableHdr {
     uint32_t pad[4];
 };
 
-// Table layout for capacities (njobs_cap): header | jobs | pt_prefix |
-// box_prefix | tile_prefix[levels][njobs_cap + 1] | tile_cols[levels][njobs_cap].
+// Table layout for capacities (njobs_cap): header | pt_prefix | box_prefix |
+// tile_prefix[levels][njobs_cap + 1] | tile_cols[levels][njobs_cap] | jobs.
 struct TableLayout {
     size_t jobs, pt_prefix, box_prefix, tile_prefix, tile_cols, bytes;
     // The job records come last, so an eager tick copies the header, the

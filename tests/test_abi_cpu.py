@@ -349,3 +349,49 @@ def test_tvl1_validation(L):
     assert L.ot_box_mean_flow(FAKE, 10, 10, FAKE, -1, FAKE, FAKE, None) == E
     assert L.ot_box_mean_flow(FAKE + 4, 10, 10, FAKE, 3, FAKE, FAKE, None) == E
     assert L.ot_box_mean_flow(None, 10, 10, None, 0, None, None, None) == 0
+
+
+class _FakeDev:
+    """Stands in for a device tensor: an address, a shape and a row stride
+    (ot_batch_pack reads only these and never dereferences them)."""
+
+    def __init__(self, addr, shape, stride0=1, nbytes=None):
+        self.addr, self.shape, self._s0 = addr, shape, stride0
+        self._numel = nbytes if nbytes is not None else int(np.prod(shape))
+
+    def data_ptr(self):
+        return self.addr
+
+    def stride(self, i):
+        return self._s0
+
+    def numel(self):
+        return self._numel
+
+
+def test_fit_capacities_finds_the_smallest_tiles(L):
+    """batch.fit_capacities: totals for jobs, points and boxes, and the
+    smallest tile capacity the fused pyramid stages fit (bisection with
+    ot_batch_pack): the same three jobs as above need 54 + 255 + 120 = 429
+    tiles in their first stage and 72 in the second."""
+    from types import SimpleNamespace
+    from paper_1910_06017_amd import batch
+
+    def job(W, H, levels, n, m, base):
+        _, prev = layout(L, W=W, H=H, pitch=W, levels=levels)
+        return batch.Job(prev=SimpleNamespace(desc=prev),
+                         next_frame=_FakeDev(base, (H, W), W),
+                         next_ws=_FakeDev(base + (1 << 24), (1,),
+                                          nbytes=ops.pyramid_bytes(W, H, levels)),
+                         levels=levels, pts=_FakeDev(base + 256, (n, 2)),
+                         next_pts=_FakeDev(base + 512, (n, 2)), status=_FakeDev(base + 768, (n,)),
+                         err=None, boxes=_FakeDev(base + 1024, (m, 4)),
+                         box_id=_FakeDev(base + 1280, (n,)), out_boxes=_FakeDev(base + 1536, (m, 4)),
+                         out_count=_FakeDev(base + 1792, (m,)))
+
+    jobs = [job(720, 576, 4, 100, 3, FAKE), job(1920, 1080, 5, 0, 0, FAKE + (1 << 28)),
+            job(1280, 720, 4, 2500, 7, FAKE + (2 << 28))]
+    cfg = batch.fit_capacities(batch.BatchConfig(max_tiles=1 << 15), jobs)
+    assert (cfg.max_jobs, cfg.max_points, cfg.max_boxes, cfg.max_tiles) == (3, 2600, 10, 429)
+    with pytest.raises(ValueError):
+        batch.fit_capacities(batch.BatchConfig(max_tiles=400), jobs)
