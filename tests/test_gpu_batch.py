@@ -117,6 +117,36 @@ def test_graph_replay_with_new_tables(mods):
                 assert torch.equal(j.out_boxes, ob) and torch.equal(j.out_count, oc)
 
 
+def test_graph_with_fitted_capacities(mods):
+    """A tick captured with capacities fitted to its jobs (no idle workgroups
+    in any stage) gives the per-stream results bit for bit, on every replay;
+    a tick that needs more than the fitted capacities is refused at packing."""
+    ops, batch = mods
+    jobs = [make_job(ops, batch, w) for w in small_mix(seed=31, nstreams=5)]
+    cfg = batch.fit_capacities(batch.BatchConfig(max_jobs=16, max_points=1 << 16,
+                                                 max_boxes=512, max_tiles=1 << 14,
+                                                 max_levels=5), jobs)
+    assert cfg.max_points == sum(j.n for j in jobs) and cfg.max_boxes == sum(j.m for j in jobs)
+    runner = batch.BatchRunner(cfg, tables=1)
+    runner.pack(jobs, table=0)
+    g = runner.capture(0)
+    refs = [reference(ops, j, cfg) for j in jobs]
+    for rep in range(3):
+        for j in jobs:
+            j.next_pts.fill_(-7.0)
+            j.out_count.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for j, (Q, nx, st, er, ob, oc) in zip(jobs, refs):
+            assert torch.equal(j.next_pts, nx), rep
+            assert torch.equal(j.status, st)
+            assert torch.equal(j.out_boxes, ob) and torch.equal(j.out_count, oc)
+    bigger = jobs + [make_job(ops, batch, synth.batched_streams(seed=32, nstreams=1)[0])]
+    with pytest.raises(ops.OtError):
+        runner.pack(bigger, table=0)
+
+
 def test_batched_full_tick_vs_oracle(mods):
     """The 32-stream mixed tick (~170k points) in the persistent launch against
     the oracle: every point of four streams (the largest stream, a 1080p, a
