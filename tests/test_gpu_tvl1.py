@@ -125,7 +125,8 @@ def test_box_mean_flow_matches_oracle(ops):
     print(f"mean-flow boxes vs truth: median {np.median(err):.3f} px, max {err.max():.3f} px "
           f"(unmoved boxes: median {np.median(still):.3f} px)")
     # small boxes moving up to 20 px in front of a static background: the
-    # regularised field follows most boxes only partly (see DESIGN)
+    # total-variation term smooths the field across the boxes' edges, so the
+    # mean inside a box follows its motion only partly
     assert np.median(err) < 0.6 * np.median(still)
 
 
