@@ -21,7 +21,8 @@
  * gate and scaled boxes (ot_fb_gate, ot_box_update_scaled); the matching and
  * update phases (ot_iou_matrix, ot_assign, ot_track_update); and the
  * paper's own dense engine, TV-L1 flow with the mean-flow box prediction
- * (ot_tvl1_flow, ot_tvl1_flow_async, ot_box_mean_flow).
+ * (ot_tvl1_flow, ot_tvl1_flow_async, ot_tvl1_texture, ot_tvl1_flow_tex,
+ * ot_box_mean_flow).
  *
  * Conventions shared by every call
  *   - Pointers are DEVICE pointers unless marked (host).
@@ -404,6 +405,34 @@ OT_API ot_err ot_tvl1_flow(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
 OT_API ot_err ot_tvl1_flow_async(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
                           const ot_tvl1_params* prm, void* ws, size_t ws_bytes, float* flow,
                           void* stream, void* aux_stream);
+
+/* One video stream, frame by frame (Sec. V-B): a frame's structure-texture
+ * split is the same whether it is the second frame of a pair or the first of
+ * the next, so it can be computed once per frame, ahead of the flow (the
+ * prefetch of the next frame's preprocessing).  ot_tvl1_texture_bytes: bytes
+ * of one frame's texture buffer for a W x H level 0 (0 if invalid): the
+ * split's scratch (two level-0 float2 planes) and, per level, the texture
+ * (float) and its central-difference gradient (float2 pairs). */
+OT_API size_t ot_tvl1_texture_bytes(int32_t W, int32_t H);
+
+/* The structure-texture split of every level l < prm->levels of one frame's
+ * pyramid (as ot_tvl1_flow does for each frame: iters_s dual steps from p = 0,
+ * texture = f - alpha * structure) and the texture's clamped central-difference
+ * gradient, into tex: ot_tvl1_texture_bytes(W0, H0) bytes, 256-byte aligned,
+ * owned by the caller, opaque (read by ot_tvl1_flow_tex with the same levels
+ * and level sizes).  Errors: OT_E_INVAL, OT_E_WORKSPACE, OT_E_LAUNCH. */
+OT_API ot_err ot_tvl1_texture(const ot_pyr* pyr, const ot_tvl1_params* prm, void* tex,
+                       size_t tex_bytes, void* stream);
+
+/* ot_tvl1_flow from two frames' texture buffers (ot_tvl1_texture with the same
+ * prm->levels, iters_s, theta_s, tau_s and alpha): prev_pyr and next_pyr give
+ * the level sizes only.  The flow is bit for bit that of ot_tvl1_flow on the
+ * two pyramids.  ws as ot_tvl1_flow.  Errors: those of ot_tvl1_flow, and
+ * OT_E_WORKSPACE for a texture buffer that is not 256-byte aligned. */
+OT_API ot_err ot_tvl1_flow_tex(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
+                        const void* prev_tex, const void* next_tex,
+                        const ot_tvl1_params* prm, void* ws, size_t ws_bytes, float* flow,
+                        void* stream);
 
 /* Box prediction from a dense field (Sec. V-A): for box b, (mx, my) = the
  * mean of flow over the pixels (x, y) with integer x in [ceil(x0),

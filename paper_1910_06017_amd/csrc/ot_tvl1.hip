@@ -588,104 +588,120 @@ size_t ot_tvl1_bytes(int32_t W, int32_t H) {
 namespace ot {
 namespace {
 
-// The structure-texture passes and gradients of every level (coarse to fine)
-// on stream a, the flow on stream s; with a != s, level l's flow waits for an
-// event recorded on a after level l's planes, and a starts after an event of
-// s (everything the caller enqueued before).  The last wait joins a into s.
-ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_params* prm,
-                void* ws, size_t ws_bytes, float* flow, hipStream_t s, hipStream_t a) {
-    if (!pyr_ok(prev_pyr) || !pyr_ok(next_pyr) || !params_ok(prm) || !flow || !ws) return OT_E_INVAL;
-    const int L = prm->levels;
-    if (L > prev_pyr->levels || L > next_pyr->levels) return OT_E_INVAL;
-    for (int l = 0; l < L; ++l)
-        if (prev_pyr->w[l] != next_pyr->w[l] || prev_pyr->h[l] != next_pyr->h[l]) return OT_E_SHAPE;
-    const int W0 = prev_pyr->w[0], H0 = prev_pyr->h[0];
-    if (W0 > 16384 || H0 > 16384) return OT_E_INVAL;
-    const TvLayout T = TvLayout::make(prev_pyr->w, prev_pyr->h, L);
-    // the documented size, and what this pyramid's levels take
-    if (ws_bytes < TvLayout::bound(W0, H0) || ws_bytes < T.bytes || ((uintptr_t)ws & 255) ||
-        ((uintptr_t)flow & 7))
-        return OT_E_WORKSPACE;
-    const bool two = a != s;
-    hipEvent_t* ev = nullptr;
-    std::unique_lock<std::mutex> lock(tv_ev_mu, std::defer_lock);
-    if (two) {
-        hipDevice_t ds = -1, da = -1;
-        if (hipStreamGetDevice(s, &ds) != hipSuccess || hipStreamGetDevice(a, &da) != hipSuccess ||
-            ds != da)
-            return OT_E_INVAL;
-        lock.lock();
-        if (tv_events(ds, &ev) != hipSuccess) return OT_E_LAUNCH;
+// One frame's structure-texture pyramid for ot_tvl1_texture: the structure
+// dual's ping-pong planes (level 0 sized) and, per level, the texture (float)
+// and its central-difference gradient (float2).
+struct TexLayout {
+    size_t r0, r1;
+    size_t t[OT_MAX_LEVELS], g[OT_MAX_LEVELS];
+    size_t bytes;
+    static TexLayout make(const int32_t* w, const int32_t* h, int L) {
+        const size_t n = (size_t)w[0] * h[0];
+        TexLayout T{};
+        size_t o = 0;
+        auto take = [&](size_t b) {
+            const size_t at = o;
+            o += al256(b);
+            return at;
+        };
+        T.r0 = take(n * 8);
+        T.r1 = take(n * 8);
+        for (int l = 0; l < L; ++l) {
+            const size_t nl = (size_t)w[l] * h[l];
+            T.t[l] = take(nl * 4);
+            T.g[l] = take(nl * 8);
+        }
+        T.bytes = o;
+        return T;
     }
-    uint8_t* base = static_cast<uint8_t*>(ws);
-    float2* R[2][2] = {{reinterpret_cast<float2*>(base + T.r0), reinterpret_cast<float2*>(base + T.r1)},
-                       {reinterpret_cast<float2*>(base + T.r2), reinterpret_cast<float2*>(base + T.r3)}};
+    static size_t bound(int32_t W, int32_t H) {
+        int32_t w[OT_MAX_LEVELS], h[OT_MAX_LEVELS];
+        w[0] = W;
+        h[0] = H;
+        for (int l = 1; l < OT_MAX_LEVELS; ++l) {
+            w[l] = (w[l - 1] + 1) / 2;
+            h[l] = (h[l - 1] + 1) / 2;
+        }
+        return make(w, h, OT_MAX_LEVELS).bytes;
+    }
+};
+
+// The structure-texture split of level l of nf (1 or 2) frames, side by side
+// in every launch (grid z): iters_s dual steps on the ping-pong planes R[f],
+// the textures tex[f], and the central-difference gradient of the last
+// frame's texture into grad.
+hipError_t split_level(const ot_pyr* const* pyr, int nf, int l, const ot_tvl1_params* prm,
+                       float2* const (*R)[2], float* const* tex, float2* grad, hipStream_t a) {
+    const int W = pyr[0]->w[l], H = pyr[0]->h[l];
+    const dim3 gr = grid2(W, H), bl(TV_BX, TV_BY);
+    const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
+    const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
+    const bool large = gbl.x * gbl.y >= 256;
+    // levels whose small-tile grid stays under 256 workgroups take OT_TV_KT
+    // steps per launch
+    const bool tiny_s = !large && gbs.x * gbs.y < 256;
+    const int kr = tiny_s ? TV_KT : TV_K;
+    int cr = 0;
+    for (int it = 0; it < prm->iters_s; it += kr) {
+        const int nb = prm->iters_s - it < kr ? prm->iters_s - it : kr;
+        FramePair fp;
+        for (int f = 0; f < 2; ++f) {
+            const int ff = f < nf ? f : 0;
+            fp.img[f] = pyr[ff]->level[l];
+            fp.pitch[f] = pyr[ff]->pitch[l];
+            fp.p_in[f] = R[ff][cr];
+            fp.p_out[f] = R[ff][cr ^ 1];
+        }
+        if (large)
+            hipLaunchKernelGGL((k_rof_block<TV_K, TBL_X, TBL_Y, TBL_T>), dim3(gbl.x, gbl.y, nf), dim3(TBL_T), 0,
+                               a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+        else if (tiny_s)
+            hipLaunchKernelGGL((k_rof_block<TV_KT, TBS_X, TBS_Y, TBT_T>), dim3(gbs.x, gbs.y, nf), dim3(TBT_T), 0,
+                               a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+        else
+            hipLaunchKernelGGL((k_rof_block<TV_K, TBS_X, TBS_Y, TBS_T>), dim3(gbs.x, gbs.y, nf), dim3(TBS_T), 0,
+                               a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
+        cr ^= 1;
+    }
+    if (prm->iters_s == 0) {
+        // no structure iterations: p = 0
+        for (int f = 0; f < nf; ++f)
+            hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0, a,
+                               R[f][cr], (size_t)W * H);
+    }
+    const int f1 = nf - 1;
+    hipLaunchKernelGGL(k_texture, dim3(gr.x, gr.y, nf), bl, 0, a, pyr[0]->level[l], pyr[0]->pitch[l],
+                       pyr[f1]->level[l], pyr[f1]->pitch[l], W, H, R[0][cr], R[f1][cr], tex[0],
+                       tex[f1], prm->theta_s, prm->alpha);
+    hipLaunchKernelGGL(k_central_grad, gr, bl, 0, a, tex[f1], W, H, grad);
+    return hipGetLastError();
+}
+
+// The flow of levels L-1 .. 0 on s from per-level planes: planes(l, I0, I1,
+// G1) gives level l's first and second texture and the second's gradient.
+// With ev, level l's flow first waits for ev[l].  ws holds the level-0 sized
+// data term, flow and dual planes of T.
+template <class Planes>
+ot_err flow_levels(const ot_pyr* shape, const ot_tvl1_params* prm, uint8_t* base,
+                   const TvLayout& T, Planes&& planes, float* flow, hipStream_t s,
+                   const hipEvent_t* ev) {
+    const int L = prm->levels;
     float4* D = reinterpret_cast<float4*>(base + T.d);
     float2* U[2] = {reinterpret_cast<float2*>(base + T.u0), reinterpret_cast<float2*>(base + T.u1)};
     float4* Pd[2] = {reinterpret_cast<float4*>(base + T.p0), reinterpret_cast<float4*>(base + T.p1)};
-    auto T0 = [&](int l) { return reinterpret_cast<float*>(base + T.t0[l]); };
-    auto T1 = [&](int l) { return reinterpret_cast<float*>(base + T.t1[l]); };
-    auto G = [&](int l) { return reinterpret_cast<float2*>(base + T.g[l]); };
     const float lt = prm->lam * prm->theta, k = prm->tau / prm->theta;
     const float inv_shrink = 1.0f / (1.0f + prm->tau * prm->eps / prm->theta);
-    if (two) {
-        if (hipEventRecord(ev[OT_MAX_LEVELS], s) != hipSuccess ||
-            hipStreamWaitEvent(a, ev[OT_MAX_LEVELS], 0) != hipSuccess)
-            return OT_E_LAUNCH;
-    }
-    // ---- structure-texture split and texture gradient of every level, on a
-    for (int l = L - 1; l >= 0; --l) {
-        const int W = prev_pyr->w[l], H = prev_pyr->h[l];
-        const dim3 gr = grid2(W, H), bl(TV_BX, TV_BY);
-        const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
-        const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
-        const bool large = gbl.x * gbl.y >= 256;
-        // both frames side by side in every launch; levels whose small-tile
-        // grid stays under 256 workgroups take OT_TV_KT steps per launch
-        const bool tiny_s = !large && gbs.x * gbs.y < 256;
-        const int kr = tiny_s ? TV_KT : TV_K;
-        int cr = 0;
-        for (int it = 0; it < prm->iters_s; it += kr) {
-            const int nb = prm->iters_s - it < kr ? prm->iters_s - it : kr;
-            FramePair fp;
-            for (int f = 0; f < 2; ++f) {
-                const ot_pyr* py = f == 0 ? prev_pyr : next_pyr;
-                fp.img[f] = py->level[l];
-                fp.pitch[f] = py->pitch[l];
-                fp.p_in[f] = R[f][cr];
-                fp.p_out[f] = R[f][cr ^ 1];
-            }
-            if (large)
-                hipLaunchKernelGGL((k_rof_block<TV_K, TBL_X, TBL_Y, TBL_T>), dim3(gbl.x, gbl.y, 2), dim3(TBL_T), 0,
-                                   a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
-            else if (tiny_s)
-                hipLaunchKernelGGL((k_rof_block<TV_KT, TBS_X, TBS_Y, TBT_T>), dim3(gbs.x, gbs.y, 2), dim3(TBT_T), 0,
-                                   a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
-            else
-                hipLaunchKernelGGL((k_rof_block<TV_K, TBS_X, TBS_Y, TBS_T>), dim3(gbs.x, gbs.y, 2), dim3(TBS_T), 0,
-                                   a, fp, W, H, 1.0f / prm->theta_s, prm->tau_s, it == 0 ? 1 : 0, nb);
-            cr ^= 1;
-        }
-        if (prm->iters_s == 0) {
-            // no structure iterations: p = 0
-            for (int f = 0; f < 2; ++f)
-                hipLaunchKernelGGL(k_zero2, dim3((unsigned)(((size_t)W * H + 255) / 256)), dim3(256), 0, a,
-                                   R[f][cr], (size_t)W * H);
-        }
-        hipLaunchKernelGGL(k_texture, dim3(gr.x, gr.y, 2), bl, 0, a, prev_pyr->level[l], prev_pyr->pitch[l],
-                           next_pyr->level[l], next_pyr->pitch[l], W, H, R[0][cr], R[1][cr], T0(l), T1(l),
-                           prm->theta_s, prm->alpha);
-        hipLaunchKernelGGL(k_central_grad, gr, bl, 0, a, T1(l), W, H, G(l));
-        if (two && hipEventRecord(ev[l], a) != hipSuccess) return OT_E_LAUNCH;
-    }
-    // ---- flow, coarse to fine, on s
     int cu = 0;  // index of the current flow buffer
     for (int l = L - 1; l >= 0; --l) {
-        const int W = prev_pyr->w[l], H = prev_pyr->h[l];
+        const int W = shape->w[l], H = shape->h[l];
         const dim3 gbl((W + TBL_X - 1) / TBL_X, (H + TBL_Y - 1) / TBL_Y);
         const dim3 gbs((W + TBS_X - 1) / TBS_X, (H + TBS_Y - 1) / TBS_Y);
         const bool large = gbl.x * gbl.y >= 256;
-        if (two && hipStreamWaitEvent(s, ev[l], 0) != hipSuccess) return OT_E_LAUNCH;
+        if (ev && hipStreamWaitEvent(s, ev[l], 0) != hipSuccess) return OT_E_LAUNCH;
+        const float* I0 = nullptr;
+        const float* I1 = nullptr;
+        const float2* G1 = nullptr;
+        planes(l, I0, I1, G1);
         // initial flow (in the level's first launch): zero at the coarsest
         // level, else the coarser flow doubled; U[cu] holds the coarser flow
         int cp = 0;
@@ -701,16 +717,16 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
                 // the warp's first launch linearises the data term at the flow it reads
                 WarpSrc wsrc{};
                 if (it == 0) {
-                    wsrc.I0 = T0(l);
-                    wsrc.I1 = T1(l);
-                    wsrc.G1 = G(l);
+                    wsrc.I0 = I0;
+                    wsrc.I1 = I1;
+                    wsrc.G1 = G1;
                     wsrc.data_out = D;
                 }
                 if (wv == 0 && it == 0) {
                     wsrc.init = l == L - 1 ? 1 : 2;
                     wsrc.uc = U[cu];
-                    wsrc.Wc = l + 1 < L ? prev_pyr->w[l + 1] : 0;
-                    wsrc.Hc = l + 1 < L ? prev_pyr->h[l + 1] : 0;
+                    wsrc.Wc = l + 1 < L ? shape->w[l + 1] : 0;
+                    wsrc.Hc = l + 1 < L ? shape->h[l + 1] : 0;
                 }
                 // the last launch of level 0 writes the caller's flow
                 const bool last = l == 0 && wv == prm->warps - 1 && it + kb >= prm->iters;
@@ -741,6 +757,74 @@ ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_pa
     return OT_OK;
 }
 
+// Common checks of the flow calls: the parameters, the level sizes of the
+// pyramids (equal on every level used) and the workspace.
+ot_err flow_args(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_params* prm,
+                 const void* ws, size_t ws_bytes, const float* flow, TvLayout* T) {
+    if (!pyr_ok(prev_pyr) || !pyr_ok(next_pyr) || !params_ok(prm) || !flow || !ws) return OT_E_INVAL;
+    const int L = prm->levels;
+    if (L > prev_pyr->levels || L > next_pyr->levels) return OT_E_INVAL;
+    for (int l = 0; l < L; ++l)
+        if (prev_pyr->w[l] != next_pyr->w[l] || prev_pyr->h[l] != next_pyr->h[l]) return OT_E_SHAPE;
+    const int W0 = prev_pyr->w[0], H0 = prev_pyr->h[0];
+    if (W0 > 16384 || H0 > 16384) return OT_E_INVAL;
+    *T = TvLayout::make(prev_pyr->w, prev_pyr->h, L);
+    // the documented size, and what this pyramid's levels take
+    if (ws_bytes < TvLayout::bound(W0, H0) || ws_bytes < T->bytes || ((uintptr_t)ws & 255) ||
+        ((uintptr_t)flow & 7))
+        return OT_E_WORKSPACE;
+    return OT_OK;
+}
+
+// The structure-texture passes and gradients of every level (coarse to fine)
+// on stream a, the flow on stream s; with a != s, level l's flow waits for an
+// event recorded on a after level l's planes, and a starts after an event of
+// s (everything the caller enqueued before).  The last wait joins a into s.
+ot_err tvl1_run(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const ot_tvl1_params* prm,
+                void* ws, size_t ws_bytes, float* flow, hipStream_t s, hipStream_t a) {
+    TvLayout T;
+    const ot_err e0 = flow_args(prev_pyr, next_pyr, prm, ws, ws_bytes, flow, &T);
+    if (e0 != OT_OK) return e0;
+    const int L = prm->levels;
+    const bool two = a != s;
+    hipEvent_t* ev = nullptr;
+    std::unique_lock<std::mutex> lock(tv_ev_mu, std::defer_lock);
+    if (two) {
+        hipDevice_t ds = -1, da = -1;
+        if (hipStreamGetDevice(s, &ds) != hipSuccess || hipStreamGetDevice(a, &da) != hipSuccess ||
+            ds != da)
+            return OT_E_INVAL;
+        lock.lock();
+        if (tv_events(ds, &ev) != hipSuccess) return OT_E_LAUNCH;
+    }
+    uint8_t* base = static_cast<uint8_t*>(ws);
+    float2* const R[2][2] = {{reinterpret_cast<float2*>(base + T.r0), reinterpret_cast<float2*>(base + T.r1)},
+                             {reinterpret_cast<float2*>(base + T.r2), reinterpret_cast<float2*>(base + T.r3)}};
+    if (two) {
+        if (hipEventRecord(ev[OT_MAX_LEVELS], s) != hipSuccess ||
+            hipStreamWaitEvent(a, ev[OT_MAX_LEVELS], 0) != hipSuccess)
+            return OT_E_LAUNCH;
+    }
+    // ---- structure-texture split and texture gradient of every level, on a
+    const ot_pyr* const pyrs[2] = {prev_pyr, next_pyr};
+    for (int l = L - 1; l >= 0; --l) {
+        float* const tex[2] = {reinterpret_cast<float*>(base + T.t0[l]),
+                               reinterpret_cast<float*>(base + T.t1[l])};
+        if (split_level(pyrs, 2, l, prm, R, tex, reinterpret_cast<float2*>(base + T.g[l]), a) !=
+            hipSuccess)
+            return OT_E_LAUNCH;
+        if (two && hipEventRecord(ev[l], a) != hipSuccess) return OT_E_LAUNCH;
+    }
+    // ---- flow, coarse to fine, on s
+    return flow_levels(prev_pyr, prm, base, T,
+                       [&](int l, const float*& I0, const float*& I1, const float2*& G1) {
+                           I0 = reinterpret_cast<const float*>(base + T.t0[l]);
+                           I1 = reinterpret_cast<const float*>(base + T.t1[l]);
+                           G1 = reinterpret_cast<const float2*>(base + T.g[l]);
+                       },
+                       flow, s, two ? ev : nullptr);
+}
+
 }  // namespace
 }  // namespace ot
 
@@ -757,6 +841,54 @@ ot_err ot_tvl1_flow_async(const ot_pyr* prev_pyr, const ot_pyr* next_pyr,
                           void* stream, void* aux_stream) {
     return tvl1_run(prev_pyr, next_pyr, prm, ws, ws_bytes, flow, static_cast<hipStream_t>(stream),
                     static_cast<hipStream_t>(aux_stream));
+}
+
+size_t ot_tvl1_texture_bytes(int32_t W, int32_t H) {
+    if (W < 1 || H < 1 || W > 16384 || H > 16384) return 0;
+    return TexLayout::bound(W, H);
+}
+
+ot_err ot_tvl1_texture(const ot_pyr* pyr, const ot_tvl1_params* prm, void* tex, size_t tex_bytes,
+                       void* stream) {
+    if (!pyr_ok(pyr) || !params_ok(prm) || !tex) return OT_E_INVAL;
+    const int L = prm->levels;
+    if (L > pyr->levels) return OT_E_INVAL;
+    const int W0 = pyr->w[0], H0 = pyr->h[0];
+    if (W0 > 16384 || H0 > 16384) return OT_E_INVAL;
+    const TexLayout X = TexLayout::make(pyr->w, pyr->h, L);
+    if (tex_bytes < TexLayout::bound(W0, H0) || tex_bytes < X.bytes || ((uintptr_t)tex & 255))
+        return OT_E_WORKSPACE;
+    uint8_t* base = static_cast<uint8_t*>(tex);
+    float2* const R[1][2] = {{reinterpret_cast<float2*>(base + X.r0), reinterpret_cast<float2*>(base + X.r1)}};
+    const ot_pyr* const pyrs[1] = {pyr};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int l = L - 1; l >= 0; --l) {
+        float* const t[1] = {reinterpret_cast<float*>(base + X.t[l])};
+        if (split_level(pyrs, 1, l, prm, R, t, reinterpret_cast<float2*>(base + X.g[l]), s) !=
+            hipSuccess)
+            return OT_E_LAUNCH;
+    }
+    return OT_OK;
+}
+
+ot_err ot_tvl1_flow_tex(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const void* prev_tex,
+                        const void* next_tex, const ot_tvl1_params* prm, void* ws,
+                        size_t ws_bytes, float* flow, void* stream) {
+    TvLayout T;
+    const ot_err e0 = flow_args(prev_pyr, next_pyr, prm, ws, ws_bytes, flow, &T);
+    if (e0 != OT_OK) return e0;
+    if (!prev_tex || !next_tex) return OT_E_INVAL;
+    if (((uintptr_t)prev_tex | (uintptr_t)next_tex) & 255) return OT_E_WORKSPACE;
+    const TexLayout X = TexLayout::make(prev_pyr->w, prev_pyr->h, prm->levels);
+    const uint8_t* pb = static_cast<const uint8_t*>(prev_tex);
+    const uint8_t* nb = static_cast<const uint8_t*>(next_tex);
+    return flow_levels(prev_pyr, prm, static_cast<uint8_t*>(ws), T,
+                       [&](int l, const float*& I0, const float*& I1, const float2*& G1) {
+                           I0 = reinterpret_cast<const float*>(pb + X.t[l]);
+                           I1 = reinterpret_cast<const float*>(nb + X.t[l]);
+                           G1 = reinterpret_cast<const float2*>(nb + X.g[l]);
+                       },
+                       flow, static_cast<hipStream_t>(stream), nullptr);
 }
 
 ot_err ot_box_mean_flow(const float* flow, int32_t W, int32_t H, const float* boxes, int32_t m,

@@ -26,7 +26,7 @@ EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_t
            "ot_box_update_scaled_noalloc",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
            "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_tvl1_flow_async",
-           "ot_box_mean_flow",
+           "ot_tvl1_texture_bytes", "ot_tvl1_texture", "ot_tvl1_flow_tex", "ot_box_mean_flow",
            "ot_batch_table_bytes", "ot_batch_pack", "ot_batch_run", "ot_batch_run_stages",
            "ot_strerror", "ot_version"]
 
@@ -123,6 +123,12 @@ def lib():
         L.ot_tvl1_flow.restype = i32
         L.ot_tvl1_flow_async.argtypes = [PP, PP, C.POINTER(OtTvl1Params), P, sz, P, P, P]
         L.ot_tvl1_flow_async.restype = i32
+        L.ot_tvl1_texture_bytes.argtypes = [i32, i32]
+        L.ot_tvl1_texture_bytes.restype = sz
+        L.ot_tvl1_texture.argtypes = [PP, C.POINTER(OtTvl1Params), P, sz, P]
+        L.ot_tvl1_texture.restype = i32
+        L.ot_tvl1_flow_tex.argtypes = [PP, PP, P, P, C.POINTER(OtTvl1Params), P, sz, P, P]
+        L.ot_tvl1_flow_tex.restype = i32
         L.ot_box_mean_flow.argtypes = [P, i32, i32, P, i32, P, P, P]
         L.ot_box_mean_flow.restype = i32
         L.ot_working_level.argtypes = [i32, i32, i32]
@@ -446,6 +452,37 @@ def tvl1_flow(prev: Pyramid, nxt: Pyramid, params: OtTvl1Params | None = None, w
         check(lib().ot_tvl1_flow(*args), "ot_tvl1_flow")
     else:
         check(lib().ot_tvl1_flow_async(*args, _stream_handle(aux_stream)), "ot_tvl1_flow_async")
+    return flow
+
+
+def tvl1_texture(pyr: Pyramid, params: OtTvl1Params | None = None, out=None, stream=None):
+    """One frame's structure-texture buffer (opaque uint8 tensor) for
+    tvl1_flow_tex: the texture and its gradient on every level."""
+    torch = _torch()
+    p = tvl1_params() if params is None else params
+    W, H = pyr.desc.w[0], pyr.desc.h[0]
+    need = int(lib().ot_tvl1_texture_bytes(W, H))
+    tex = torch.empty(need, dtype=torch.uint8, device=pyr.frame.device) if out is None else out
+    check(lib().ot_tvl1_texture(C.byref(pyr.desc), C.byref(p), _ptr(tex),
+                                tex.numel() * tex.element_size(), _stream_handle(stream)),
+          "ot_tvl1_texture")
+    return tex
+
+
+def tvl1_flow_tex(prev: Pyramid, nxt: Pyramid, prev_tex, next_tex,
+                  params: OtTvl1Params | None = None, ws=None, out=None, stream=None):
+    """tvl1_flow from two frames' texture buffers (tvl1_texture with the same
+    parameters); the pyramids give the level sizes."""
+    torch = _torch()
+    p = tvl1_params() if params is None else params
+    W, H = prev.desc.w[0], prev.desc.h[0]
+    if ws is None:
+        ws = torch.empty(int(lib().ot_tvl1_bytes(W, H)), dtype=torch.uint8, device=prev.frame.device)
+    flow = torch.empty((H, W, 2), dtype=torch.float32, device=prev.frame.device) if out is None else out
+    check(lib().ot_tvl1_flow_tex(C.byref(prev.desc), C.byref(nxt.desc), _ptr(prev_tex),
+                                 _ptr(next_tex), C.byref(p), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _ptr(flow),
+                                 _stream_handle(stream)), "ot_tvl1_flow_tex")
     return flow
 
 

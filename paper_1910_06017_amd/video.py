@@ -21,6 +21,11 @@ Frame buffers and pyramid workspaces form a ring of three: frame t lives in
 slot t % 3, which the pairs (t - 1, t) and (t, t + 1) read; frame t + 3
 rewrites it only after the tracking of the pair (t, t + 1) has finished on
 the device (an event wait on the preprocessing stream).
+
+DenseVideoTracker is the same loop for the paper's dense engine (Sec. IV):
+a frame's preprocessing is its upload, pyramid and structure-texture split,
+computed once per frame, and a pair computes only the TV-L1 flow from the
+two frames' textures and the mean flow inside every box.
 """
 from __future__ import annotations
 
@@ -28,7 +33,7 @@ import numpy as np
 
 from . import ops
 
-__all__ = ["VideoTracker"]
+__all__ = ["VideoTracker", "DenseVideoTracker"]
 
 
 class VideoTracker:
@@ -158,6 +163,116 @@ class VideoTracker:
             if self.prefetch and t + 1 < T:
                 # frame t+1 goes to slot (t+1) % 3 = (t-2) % 3, last read by the
                 # tracking of the pair (t-2, t-1)
+                pre_ev[t + 1] = self._preprocess(frames[t + 1], t + 1,
+                                                 trk_ev[t - 1] if t >= 2 else None)
+            ev.synchronize()
+            out.append((self.host_boxes[:m].numpy().copy(), self.host_count[:m].numpy().copy()))
+        return out
+
+
+class DenseVideoTracker:
+    """Dense TV-L1 tracking of one video stream frame by frame (Sec. IV, V).
+
+    Each frame's preprocessing (upload, pyramid, structure-texture split of
+    every level) is computed once, when the frame arrives; the pair (t, t+1)
+    then computes only the flow from frame t's and frame t+1's texture
+    buffers, and every box moves by the mean flow inside it.  With `prefetch`,
+    frame t+1's preprocessing runs on a second HIP stream while the pair
+    (t-1, t) is tracked.  Frames, pyramids and texture buffers form a ring of
+    three, ordered as in VideoTracker.  The flow is bit for bit the pairwise
+    ot_tvl1_flow of the two frames."""
+
+    def __init__(self, W: int, H: int, params=None, m_max: int = 64, prefetch: bool = True,
+                 device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.W, self.H = W, H
+        self.p = params if params is not None else ops.tvl1_params()
+        self.prefetch = prefetch
+        self.dev = torch.device(device)
+        L = self.p.levels
+        self.L = L
+        self.frames = [torch.empty((H, W), dtype=torch.uint8, device=self.dev) for _ in range(3)]
+        self.ws = [ops.alloc_workspace(W, H, L, self.dev) for _ in range(3)]
+        self.pyr = [ops.pyramid_layout(self.frames[i], L, self.ws[i]) for i in range(3)]
+        nt = int(ops.lib().ot_tvl1_texture_bytes(W, H))
+        self.tex = [torch.empty(nt, dtype=torch.uint8, device=self.dev) for _ in range(3)]
+        self.flow_ws = torch.empty(int(ops.lib().ot_tvl1_bytes(W, H)), dtype=torch.uint8,
+                                   device=self.dev)
+        self.flow = torch.empty((H, W, 2), dtype=torch.float32, device=self.dev)
+        m = max(1, m_max)
+        self.m_max = m_max
+        self.boxes = [torch.zeros((m, 4), dtype=torch.float32, device=self.dev) for _ in range(2)]
+        self.count = torch.zeros(m, dtype=torch.int32, device=self.dev)
+        self.host_boxes = torch.zeros((m, 4), dtype=torch.float32, pin_memory=True)
+        self.host_count = torch.zeros(m, dtype=torch.int32, pin_memory=True)
+        # both streams at the default priority
+        self.s_pre = torch.cuda.Stream(self.dev)
+        self.s_trk = torch.cuda.Stream(self.dev) if prefetch else self.s_pre
+        torch.cuda.synchronize(self.dev)
+
+    def _preprocess(self, frame, t: int, after_track):
+        from .serve import _H2D, _copy
+
+        i = t % 3
+        sp = self.s_pre
+        if after_track is not None:
+            sp.wait_event(after_track)
+        _copy(self.frames[i].data_ptr(), frame.data_ptr(), frame.numel(), _H2D,
+              int(sp.cuda_stream))
+        ops.pyramid_build(self.frames[i], self.L, ws=self.ws[i], stream=sp)
+        ops.tvl1_texture(self.pyr[i], self.p, out=self.tex[i], stream=sp)
+        ev = self.torch.cuda.Event()
+        ev.record(sp)
+        return ev
+
+    def track(self, frames: list, seeds: dict) -> list:
+        """frames: (H, W) uint8 pinned host tensors.  seeds[t] = boxes (m, 4)
+        float32 at frame t, which replace the boxes tracked to frame t (frame
+        0 must have some).  Returns, for every t >= 1, (boxes (m, 4), counts
+        (m,)) predicted for frame t."""
+        from .serve import _D2H, _H2D, _copy
+
+        torch = self.torch
+        if 0 not in seeds:
+            raise ValueError("frame 0 needs detections")
+        T = len(frames)
+        out = []
+        pre_ev = [None] * T
+        trk_ev = [None] * T
+        pre_ev[0] = self._preprocess(frames[0], 0, None)
+        if self.prefetch and T > 1:
+            pre_ev[1] = self._preprocess(frames[1], 1, None)
+        m = 0
+        st = self.s_trk
+        sh = int(st.cuda_stream)
+        for t in range(1, T + 1):
+            cur = (t - 1) & 1
+            if t - 1 in seeds:
+                bx = np.ascontiguousarray(seeds[t - 1], dtype=np.float32)
+                m = len(bx)
+                if m > self.m_max:
+                    raise ValueError("detections exceed the tracker's capacity")
+                _copy(self.boxes[cur].data_ptr(), bx.ctypes.data, bx.nbytes, _H2D, sh)
+            if t == T:
+                break
+            if not self.prefetch:
+                pre_ev[t] = self._preprocess(frames[t], t, None)
+            st.wait_event(pre_ev[t])
+            a, b = (t - 1) % 3, t % 3
+            nxt = 1 - cur
+            ops.tvl1_flow_tex(self.pyr[a], self.pyr[b], self.tex[a], self.tex[b], self.p,
+                              ws=self.flow_ws, out=self.flow, stream=st)
+            ops.box_mean_flow(self.flow, self.boxes[cur][:m],
+                              out=(self.boxes[nxt][:m], self.count[:m]), stream=st)
+            _copy(self.host_boxes.data_ptr(), self.boxes[nxt].data_ptr(), m * 16, _D2H, sh)
+            _copy(self.host_count.data_ptr(), self.count.data_ptr(), m * 4, _D2H, sh)
+            ev = torch.cuda.Event()
+            ev.record(st)
+            trk_ev[t] = ev
+            if self.prefetch and t + 1 < T:
+                # frame t+1 goes to slot (t+1) % 3, last read by the pair (t-2, t-1)
                 pre_ev[t + 1] = self._preprocess(frames[t + 1], t + 1,
                                                  trk_ev[t - 1] if t >= 2 else None)
             ev.synchronize()

@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 26
+    assert len(syms) == 29
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -346,6 +346,29 @@ def test_tvl1_validation(L):
     assert acall(q) == E
     assert acall(p, wsb=need - 1) == Wk
     assert acall(p, flow=None) == E
+    # one frame's texture buffer and the flow from two of them
+    tb = L.ot_tvl1_texture_bytes(720, 576)
+    per_level, w, h = 0, 720, 576
+    for _ in range(8):
+        per_level += al(4 * w * h) + al(8 * w * h)
+        w, h = (w + 1) // 2, (h + 1) // 2
+    assert tb == 2 * al(8 * n) + per_level
+    assert L.ot_tvl1_texture_bytes(0, 3) == 0
+    tcall = lambda prm, tex=FAKE, tbytes=tb: L.ot_tvl1_texture(C.byref(P), C.byref(prm), tex,
+                                                              tbytes, None)
+    assert tcall(q) == E                     # levels 0
+    q.levels = 6                             # more levels than the pyramid holds
+    assert tcall(q) == E
+    assert tcall(p, tex=None) == E
+    assert tcall(p, tbytes=tb - 1) == Wk
+    assert tcall(p, tex=FAKE + 64) == Wk
+    fcall = lambda prm, pt=FAKE, nt=FAKE, ws=FAKE, wsb=need, flow=FAKE: L.ot_tvl1_flow_tex(
+        C.byref(P), C.byref(P), pt, nt, C.byref(prm), ws, wsb, flow, None)
+    assert fcall(q) == E
+    assert fcall(p, pt=None) == E
+    assert fcall(p, nt=FAKE + 16) == Wk
+    assert fcall(p, wsb=need - 1) == Wk
+    assert fcall(p, flow=None) == E
     assert L.ot_box_mean_flow(FAKE, 10, 10, FAKE, -1, FAKE, FAKE, None) == E
     assert L.ot_box_mean_flow(FAKE + 4, 10, 10, FAKE, 3, FAKE, FAKE, None) == E
     assert L.ot_box_mean_flow(None, 10, 10, None, 0, None, None, None) == 0

@@ -249,3 +249,58 @@ def test_tvl1_async_graph_replays(ops):
         with torch.cuda.stream(s):
             ops.tvl1_flow(Q, P, p, ws=ws, stream=s, aux_stream=a)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("W,H,kw", [
+    (720, 576, dict()),                                          # the box scene's defaults
+    (33, 17, dict(levels=3, warps=3, iters=7, iters_s=0)),       # ragged, no structure steps
+])
+def test_tvl1_flow_from_textures_matches_pair(ops, W, H, kw):
+    """Each frame's structure-texture buffer computed once (ot_tvl1_texture)
+    and the flow from two of them (ot_tvl1_flow_tex) give the pairwise flow
+    bit for bit; a frame's buffer serves as the first frame of the next pair."""
+    if W == 720:
+        w = synth.sd_boxes_workload()
+        f0, f1 = w.frame0, w.frame1
+    else:
+        f0, f1, _ = synth.shifted_pair(W * H, W=W, H=H, shift=(0.6, -1.4))
+    p = ops.tvl1_params(**kw)
+    P = ops.pyramid_build(dev(f0), p.levels)
+    Q = ops.pyramid_build(dev(f1), p.levels)
+    ref_pq = ops.tvl1_flow(P, Q, p)
+    ref_qp = ops.tvl1_flow(Q, P, p)
+    tp, tq = ops.tvl1_texture(P, p), ops.tvl1_texture(Q, p)
+    assert torch.equal(ops.tvl1_flow_tex(P, Q, tp, tq, p), ref_pq)
+    assert torch.equal(ops.tvl1_flow_tex(Q, P, tq, tp, p), ref_qp)
+
+
+def test_dense_video_prefetch_identical_and_pairwise(ops):
+    """The dense video tracker gives the same boxes with and without the
+    next frame's preprocessing prefetched, and every pair's boxes are the
+    pairwise flow's mean-flow boxes from the boxes it started from."""
+    from paper_1910_06017_amd import video
+    s = synth.served_streams(seed=93, nstreams=1, nframes=6, npts_range=(400, 400),
+                             nbox_range=(5, 5), resolutions=((320, 256),))[0]
+    frames = []
+    for f in s.frames:
+        t = torch.empty(f.shape, dtype=torch.uint8, pin_memory=True)
+        t.copy_(torch.from_numpy(f))
+        frames.append(t)
+    seeds = {k: s.seed_points(k, np.random.default_rng(700 + k))[2] for k in (0, 3)}
+    p = ops.tvl1_params(levels=4, warps=3, iters=15, iters_s=20)
+    runs = [video.DenseVideoTracker(s.W, s.H, p, m_max=8, prefetch=pf).track(frames, seeds)
+            for pf in (False, True)]
+    assert len(runs[0]) == len(frames) - 1
+    for (b0, c0), (b1, c1) in zip(*runs):
+        assert np.array_equal(b0, b1) and np.array_equal(c0, c1)
+    start = seeds[0]
+    for t in range(1, len(frames)):
+        if t - 1 in seeds:
+            start = seeds[t - 1]
+        P = ops.pyramid_build(dev(s.frames[t - 1]), p.levels)
+        Q = ops.pyramid_build(dev(s.frames[t]), p.levels)
+        ob, oc = ops.box_mean_flow(ops.tvl1_flow(P, Q, p), dev(np.asarray(start, np.float32)))
+        torch.cuda.synchronize()
+        assert np.array_equal(ob.cpu().numpy(), runs[1][t - 1][0]), t
+        assert np.array_equal(oc.cpu().numpy(), runs[1][t - 1][1]), t
+        start = runs[1][t - 1][0]
