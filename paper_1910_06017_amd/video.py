@@ -36,6 +36,24 @@ from . import ops
 __all__ = ["VideoTracker", "DenseVideoTracker"]
 
 
+def _check_frames(frames, W: int, H: int) -> None:
+    """Every frame must be a contiguous (H, W) uint8 host tensor: the upload
+    copies H * W bytes from it into a device frame of that size."""
+    import torch
+
+    for t, f in enumerate(frames):
+        if not isinstance(f, torch.Tensor) or f.dtype != torch.uint8 or f.device.type != "cpu":
+            raise ValueError(f"frame {t}: expected a uint8 host tensor")
+        if tuple(f.shape) != (H, W) or not f.is_contiguous():
+            raise ValueError(f"frame {t}: expected a contiguous ({H}, {W}) tensor, "
+                             f"got {tuple(f.shape)}")
+
+
+def _check_boxes(bx: np.ndarray, t: int) -> None:
+    if bx.ndim != 2 or bx.shape[1] != 4:
+        raise ValueError(f"seeds[{t}]: boxes must be (m, 4)")
+
+
 class VideoTracker:
     """Tracks the boxes of one stream through a sequence of frames.
 
@@ -109,6 +127,7 @@ class VideoTracker:
         torch = self.torch
         if 0 not in seeds:
             raise ValueError("frame 0 needs detections")
+        _check_frames(frames, self.W, self.H)
         T = len(frames)
         out = []
         pre_ev = [None] * T        # pyramid of frame t built
@@ -128,6 +147,9 @@ class VideoTracker:
                 n, m = len(pts), len(bx)
                 if n > self.n_max or m > self.m_max:
                     raise ValueError("detections exceed the tracker's capacity")
+                if pts.shape != (n, 2) or bid.shape != (n,):
+                    raise ValueError(f"seeds[{t - 1}]: points must be (n, 2) with (n,) box ids")
+                _check_boxes(bx, t - 1)
                 pts = pts.astype(np.float32, copy=False)
                 bid = bid.astype(np.int32, copy=False)
                 bx = bx.astype(np.float32, copy=False)
@@ -237,6 +259,7 @@ class DenseVideoTracker:
         torch = self.torch
         if 0 not in seeds:
             raise ValueError("frame 0 needs detections")
+        _check_frames(frames, self.W, self.H)
         T = len(frames)
         out = []
         pre_ev = [None] * T
@@ -251,6 +274,7 @@ class DenseVideoTracker:
             cur = (t - 1) & 1
             if t - 1 in seeds:
                 bx = np.ascontiguousarray(seeds[t - 1], dtype=np.float32)
+                _check_boxes(bx, t - 1)
                 m = len(bx)
                 if m > self.m_max:
                     raise ValueError("detections exceed the tracker's capacity")
