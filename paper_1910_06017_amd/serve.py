@@ -50,6 +50,33 @@ class Frame:
     reseed: object = None  # (pts float32 n x 2, box_id int32 n, boxes float32 m x 4) or None
 
 
+def check_frame(fr: Frame, spec: StreamSpec) -> None:
+    """A frame must carry H * W uint8 pixels in one contiguous (H, W) host
+    array, and detections of the documented shapes within the stream's
+    capacities: the uploads copy that many bytes into device buffers sized
+    by the spec.  Raises ValueError."""
+    px = fr.pixels
+    if hasattr(px, "data_ptr"):
+        import torch
+
+        ok = (px.dtype == torch.uint8 and px.device.type == "cpu" and px.is_contiguous()
+              and tuple(px.shape) == (spec.H, spec.W))
+    else:
+        ok = (isinstance(px, np.ndarray) and px.dtype == np.uint8
+              and px.shape == (spec.H, spec.W))
+    if not ok:
+        raise ValueError(f"stream {fr.sid} frame {fr.k}: pixels must be a contiguous "
+                         f"({spec.H}, {spec.W}) uint8 host array")
+    if fr.reseed is not None:
+        pts, bid, bx = (np.asarray(a) for a in fr.reseed)
+        n, m = len(pts), len(bx)
+        if pts.shape != (n, 2) or bid.shape != (n,) or bx.shape != (m, 4):
+            raise ValueError(f"stream {fr.sid} frame {fr.k}: detections must be points (n, 2), "
+                             "box ids (n,) and boxes (m, 4)")
+        if n > spec.n_max or m > spec.m_max:
+            raise ValueError(f"stream {fr.sid} frame {fr.k}: detections exceed the stream's capacity")
+
+
 @dataclass
 class Result:
     sid: int
@@ -307,6 +334,7 @@ class _Slot:
         self.arena.give(self.chunk)
 
     def upload(self, fr: Frame, f: int, stream: int):
+        check_frame(fr, self.spec)
         px = fr.pixels
         dst = self.frames[f % self.NF].data_ptr()
         if hasattr(px, "data_ptr"):
@@ -475,6 +503,8 @@ class GpuExecutor:
         torch = self.torch
         if not self.can_submit():
             raise RuntimeError("too many ticks in flight")
+        for fr in frames:
+            check_frame(fr, self.slots[fr.sid].spec)
         self._now = now
         if len(frames) == 1 and self.solo:
             self._submit_one(frames[0])
@@ -706,6 +736,8 @@ class PlainExecutor:
         from . import ops
 
         torch, L = self.torch, ops.lib()
+        for fr in frames:
+            check_frame(fr, self.slots[fr.sid].spec)
         out = []
         a = self.arena
         NF, NP = _Slot.NF, _Slot.NP

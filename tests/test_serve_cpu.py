@@ -2,6 +2,7 @@
 eviction of silent streams, capacities, plain FIFO mode -- with a fake clock
 and a fake executor (no GPU, no kernels)."""
 import numpy as np
+import pytest
 
 from paper_1910_06017_amd import serve
 
@@ -246,3 +247,29 @@ def test_pipelined_loop_depth_one_is_blocking():
                           sleep=clock.sleep)
     assert len(res) == len(trace)
     assert all(n == 0 for _, n in ex.submits)
+
+
+def test_check_frame_refuses_what_the_upload_would_overrun():
+    import torch
+
+    spec = serve.StreamSpec(sid=3, W=6, H=4, levels=2, n_max=5, m_max=2)
+    good = [torch.zeros((4, 6), dtype=torch.uint8), np.zeros((4, 6), np.uint8)]
+    seeds = (np.zeros((5, 2), np.float32), np.zeros(5, np.int32), np.zeros((2, 4), np.float32))
+    for px in good:
+        serve.check_frame(serve.Frame(3, 0, 0.0, px), spec)
+        serve.check_frame(serve.Frame(3, 0, 0.0, px, seeds), spec)
+    for px in (torch.zeros((4, 7), dtype=torch.uint8), torch.zeros((4, 6), dtype=torch.int16),
+               torch.zeros((6, 4), dtype=torch.uint8).t(), np.zeros((5, 6), np.uint8),
+               np.zeros((4, 6), np.float32), None):
+        with pytest.raises(ValueError, match="pixels"):
+            serve.check_frame(serve.Frame(3, 1, 0.0, px), spec)
+    bad_seeds = [
+        (np.zeros((5, 3), np.float32), np.zeros(5, np.int32), np.zeros((2, 4), np.float32)),
+        (np.zeros((5, 2), np.float32), np.zeros(4, np.int32), np.zeros((2, 4), np.float32)),
+        (np.zeros((5, 2), np.float32), np.zeros(5, np.int32), np.zeros((2, 5), np.float32)),
+        (np.zeros((6, 2), np.float32), np.zeros(6, np.int32), np.zeros((2, 4), np.float32)),
+        (np.zeros((5, 2), np.float32), np.zeros(5, np.int32), np.zeros((3, 4), np.float32)),
+    ]
+    for sd in bad_seeds:
+        with pytest.raises(ValueError, match="detections"):
+            serve.check_frame(serve.Frame(3, 2, 0.0, good[0], sd), spec)
