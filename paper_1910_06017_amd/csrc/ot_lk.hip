@@ -23,7 +23,7 @@ __global__ OT_LK_BOUNDS void k_lk_track(DevPyr P, DevPyr Q, const float* __restr
     const float ux = uniform_f(pts[2 * i]) * prm.pscale, uy = uniform_f(pts[2 * i + 1]) * prm.pscale;
     const LkGeom g(WIN > 0 ? WIN : prm.win, R, MARGIN > 0 ? MARGIN : prm.margin);
     const int L = prm.levels;
-    const LkResult r = lk_point<R, (WIN > 0), GRADS, DevPyr, false, true>(P, Q, ux, uy, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
+    const LkResult r = lk_point<R, (WIN > 0), GRADS, DevPyr, false, LK_PRIO_REMAINING>(P, Q, ux, uy, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
                                    iters_out ? iters_out + (size_t)i * L : nullptr,
                                    lam_out ? lam_out + (size_t)i * L : nullptr);
     if ((threadIdx.x & 63) == 0) {

@@ -27,7 +27,7 @@ __device__ __forceinline__ void lk_batch_item(const uint8_t* __restrict__ table,
     const int li = i - pt_prefix[j];
     const float ux = uniform_f(jb.pts[2 * li]), uy = uniform_f(jb.pts[2 * li + 1]);
     const LkGeom g(WIN > 0 ? WIN : hd.lk.win, R, MARGIN > 0 ? MARGIN : hd.lk.margin);
-    const LkResult r = lk_point<R, (WIN > 0), false, DevPyr, WSYNC>(jb.prev, jb.next, ux, uy, jb.levels, hd.lk.iters, hd.lk.eps2,
+    const LkResult r = lk_point<R, (WIN > 0), false, DevPyr, WSYNC, LK_PRIO_ITERATIONS>(jb.prev, jb.next, ux, uy, jb.levels, hd.lk.iters, hd.lk.eps2,
                                    hd.lk.min_eig, g, smem, nullptr, nullptr);
     if ((threadIdx.x & 63) == 0) {
         jb.next_pts[2 * li] = r.nx;

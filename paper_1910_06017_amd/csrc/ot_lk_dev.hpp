@@ -266,13 +266,19 @@ struct LkResult {
     int status;
 };
 
-// Issue priority of a wave by the work it has left.  A launch holds more
-// points than the chip has wave slots, and a point's cost is not known before
-// it is tracked, so the launch ends with a tail of long waves.  Waves on the
-// coarse levels (most of their work still ahead) outrank those on the fine
-// ones, and a level's iterations (a chain of dependent wave-uniform steps)
-// outrank the set-up work of the same level; the priority changes only which
-// ready wave of a SIMD issues first, never a result.
+// Issue priority of a wave (s_setprio), which changes only which ready wave
+// of a SIMD issues first, never a result.
+//  LK_PRIO_REMAINING: by the work the wave has left.  A launch holds more
+//   points than the chip has wave slots, and a point's cost is not known
+//   before it is tracked, so the launch ends with a tail of long waves.
+//   Waves on the coarse levels (most of their work still ahead) outrank those
+//   on the fine ones, and a level's iterations (a chain of dependent
+//   wave-uniform steps) outrank the set-up work of the same level.
+//  LK_PRIO_ITERATIONS: only the iterations are raised, for launches of many
+//   rounds of waves, where the tail is a small part and the throughput of the
+//   rounds is what counts.
+enum LkPrio { LK_PRIO_NONE = 0, LK_PRIO_REMAINING = 1, LK_PRIO_ITERATIONS = 2 };
+
 __device__ __forceinline__ void lk_priority(int p) {
     switch (p) {
         case 0: __builtin_amdgcn_s_setprio(0); break;
@@ -326,10 +332,8 @@ __device__ __forceinline__ void carry_level(int& gi, float& gf, float nu) {
 // margin are template arguments), so fixed-count loops are unrolled.
 // GRADS: the template pyramid carries materialized Scharr sums, which are
 // read (at clamped indices) instead of computed.
-// PRIO: the wave raises its issue priority by the work it has left (see
-// lk_priority); the single-call launch uses it, the batched tick does not (its
-// many rounds of waves leave little tail, and there it measured slower).
-template <int R, bool FIXED, bool GRADS, class PyrRef, bool WSYNC = false, bool PRIO = false>
+// PRIO: the wave's issue-priority rule (LkPrio).
+template <int R, bool FIXED, bool GRADS, class PyrRef, bool WSYNC = false, int PRIO = LK_PRIO_NONE>
 __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, float ux, float uy,
                                              int L, int iters, float eps2, float min_eig,
                                              const LkGeom& g, unsigned char* __restrict__ smem,
@@ -371,7 +375,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
     int soff = 0;          // sx0 & 3: column of sx0 in a staged row
 
     for (int l = L - 1; l >= 0; --l) {
-        if constexpr (PRIO) lk_priority(min(l, 2));
+        if constexpr (PRIO == LK_PRIO_REMAINING) lk_priority(min(l, 2));
+        if constexpr (PRIO == LK_PRIO_ITERATIONS) lk_priority(0);
         const uint8_t* __restrict__ Il = P.lvl[l];
         const uint8_t* __restrict__ Jl = Q.lvl[l];
         const int w = P.w[l], h = P.h[l], ip = P.pitch[l], jp = Q.pitch[l];
@@ -592,7 +597,8 @@ __device__ __forceinline__ LkResult lk_point(const PyrRef& P, const PyrRef& Q, f
         float sj0x = 0.0f, sd0x = 0.0f, sjdx = 0.0f, sddx = 0.0f;
         float sj0y = 0.0f, sd0y = 0.0f, sjdy = 0.0f, sddy = 0.0f;
         int it = 0;
-        if constexpr (PRIO) lk_priority(min(l, 2) + 1);
+        if constexpr (PRIO == LK_PRIO_REMAINING) lk_priority(min(l, 2) + 1);
+        if constexpr (PRIO == LK_PRIO_ITERATIONS) lk_priority(2);
         while (it < iters) {
             int ifx, ify;
             float bxw, byw;
