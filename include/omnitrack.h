@@ -77,6 +77,8 @@ enum {
 #define OT_MAX_LEVELS 8
 #define OT_MAX_WIN 31
 #define OT_MAX_DIM 16384
+/* Row pitch limit in bytes (8 x OT_MAX_DIM): level offsets are 32-bit. */
+#define OT_MAX_PITCH 131072
 
 /* Gate default: lambda_min(G) / win^2 below this (gray levels per pixel,
  * squared; 1e-4 on a [0,1] intensity scale) marks a point lost. */
@@ -127,8 +129,8 @@ OT_API ot_err ot_pyramid_layout(const uint8_t* frame, int32_t W, int32_t H, int3
  * frame: W x H, row pitch `pitch`; levels in [1, OT_MAX_LEVELS];
  * workspace: >= ot_pyramid_bytes(W, H, levels, flags) bytes, 256-aligned.
  * *out (host) receives the descriptor, level[0] = frame.
- * Errors: OT_E_INVAL (null pointers, W/H out of [1, OT_MAX_DIM], pitch < W,
- * levels out of range, flags not 0 or OT_PYR_GRADS), OT_E_WORKSPACE
+ * Errors: OT_E_INVAL (null pointers, W/H out of [1, OT_MAX_DIM], pitch < W
+ * or > OT_MAX_PITCH, levels out of range, flags not 0 or OT_PYR_GRADS), OT_E_WORKSPACE
  * (ws_bytes too small or misaligned), OT_E_LAUNCH.  With OT_PYR_GRADS the
  * gradient planes (see ot_pyr) are written on the same stream after the
  * levels. */

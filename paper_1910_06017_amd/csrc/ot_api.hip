@@ -42,7 +42,8 @@ bool flags_valid(int32_t flags) { return flags == 0 || flags == OT_PYR_GRADS; }
 ot_err layout(const uint8_t* frame, int32_t W, int32_t H, int32_t pitch, int32_t levels,
               void* workspace, size_t ws_bytes, int32_t flags, ot_pyr* out) {
     int32_t w[OT_MAX_LEVELS], h[OT_MAX_LEVELS];
-    if (!frame || !out || !flags_valid(flags) || pitch < W || !level_dims(W, H, levels, w, h))
+    if (!frame || !out || !flags_valid(flags) || pitch < W || pitch > OT_MAX_PITCH ||
+        !level_dims(W, H, levels, w, h))
         return OT_E_INVAL;
     const size_t need = pyr_bytes(w, h, levels, flags);
     if (need > 0 && (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255) != 0))
@@ -79,7 +80,9 @@ bool pyr_valid(const ot_pyr* p) {
     int32_t w[OT_MAX_LEVELS], h[OT_MAX_LEVELS];
     if (!level_dims(p->w[0], p->h[0], p->levels, w, h)) return false;
     for (int l = 0; l < p->levels; ++l)
-        if (!p->level[l] || p->w[l] != w[l] || p->h[l] != h[l] || p->pitch[l] < w[l]) return false;
+        if (!p->level[l] || p->w[l] != w[l] || p->h[l] != h[l] || p->pitch[l] < w[l] ||
+            p->pitch[l] > OT_MAX_PITCH)
+            return false;
     if (!flags_valid(p->flags)) return false;
     if (p->flags & OT_PYR_GRADS)
         for (int l = 0; l < p->levels; ++l)

@@ -68,6 +68,15 @@ def test_pyramid_layout(L):
     assert d.level[2] == FAKE + 4096 + 384 * 288
     assert all(d.level[l] % 256 == 0 for l in range(1, 4))
     assert layout(L, pitch=719)[0] == ops_err("OT_E_INVAL")
+    # row pitches are bounded so that the kernels' 32-bit offsets into a level
+    # (row x pitch + column) cannot overflow
+    assert layout(L, pitch=131072, levels=1, ws=0, wsb=0)[0] == 0
+    assert layout(L, pitch=131073, levels=1, ws=0, wsb=0)[0] == ops_err("OT_E_INVAL")
+    _, Q = layout(L)
+    bad = ops.OtPyr()
+    C.memmove(C.byref(bad), C.byref(Q), C.sizeof(Q))
+    bad.pitch[0] = 131073
+    assert lk_call(L, bad, Q) == ops_err("OT_E_INVAL")
     assert layout(L, ws=FAKE + 4096 + 8)[0] == ops_err("OT_E_WORKSPACE")
     assert layout(L, wsb=1000)[0] == ops_err("OT_E_WORKSPACE")
     assert layout(L, levels=1, ws=0, wsb=0)[0] == 0
