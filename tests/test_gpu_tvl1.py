@@ -82,18 +82,25 @@ def test_tvl1_matches_oracle_sd_boxes(ops):
     oracle itself moves by more than 0.01 px on a few per cent of the pixels
     when its textures change by 1.5e-7 (the size of the float32 error of the
     textures).  The GPU must agree with the oracle within 0.01 px on as many
-    pixels as that probe does (1 % margin), with a median far below it."""
+    pixels as that probe does (1 % margin), with a median far below it, and
+    its largest and 99th-percentile differences may not exceed twice the
+    probe's (the GPU's errors are of the size the oracle's own rounding-level
+    sensitivity produces, not larger)."""
     w = synth.sd_boxes_workload()
     _, (u1, u2), d = run_both(ops, w.frame0, w.frame1)
     p = oracle_params(ops.tvl1_params())
     r1, r2 = oracle.tvl1.tvl1_flow(oracle.pyramid(w.frame0, p.levels),
                                    oracle.pyramid(w.frame1, p.levels), p, perturb=1.5e-7)
-    probe = np.mean(np.hypot(r1 - u1, r2 - u2) <= FLOW_TOL)
+    dp = np.hypot(r1 - u1, r2 - u2)
+    probe = np.mean(dp <= FLOW_TOL)
     ok = np.mean(d <= FLOW_TOL)
     print(f"tvl1 sd_boxes: within {FLOW_TOL}: GPU {ok:.5f}, perturbed oracle {probe:.5f}; "
-          f"GPU median {np.median(d):.2e}, max {d.max():.2e}")
+          f"GPU median {np.median(d):.2e}, p99 {np.percentile(d, 99):.2e}, max {d.max():.2e}; "
+          f"perturbed oracle p99 {np.percentile(dp, 99):.2e}, max {dp.max():.2e}")
     assert ok >= probe - 0.01
     assert np.median(d) <= 1e-4
+    assert np.percentile(d, 99) <= 2 * max(np.percentile(dp, 99), FLOW_TOL)
+    assert d.max() <= 2 * max(dp.max(), FLOW_TOL)
 
 
 def test_tvl1_zero_motion_exact(ops):
