@@ -219,8 +219,9 @@ OT_API ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id
 /* ------------------------------------------------------------------------
  * Median Flow (Kalal, Mikolajczyk and Matas 2010), a refinement of the
  * prediction phase: points are tracked forward (I_{t-1} -> I_t) and back
- * (I_t -> I_{t-1}) with ot_lk_track, points that do not return to where they
- * started are dropped, and each box both moves and scales with its points.
+ * (I_t -> I_{t-1}) with ot_lk_track_fb (or ot_lk_track twice), points that
+ * do not return to where they started are dropped, and each box both moves
+ * and scales with its points.
  * ---------------------------------------------------------------------- */
 
 /* Points per box the scaled update takes (all gathered on chip). */
@@ -238,6 +239,23 @@ OT_API ot_err ot_box_update(const float* boxes, int32_t m, const int32_t* box_id
 OT_API ot_err ot_fb_gate(const float* pts, const float* back_pts, const uint8_t* st_fwd,
                   const uint8_t* st_bwd, int32_t n, float fb_max, float* fb_err,
                   uint8_t* status_out, void* stream);
+
+/* Forward and backward tracking in one launch (Median Flow's forward-backward
+ * check, Kalal et al. 2010; Sec. V-A feature calculation): next_pts, status
+ * and err are exactly those of ot_lk_track_ex(prev_pyr, next_pyr, pts, ...,
+ * opts), and back_pts, back_status exactly those of ot_lk_track_ex(next_pyr,
+ * prev_pyr, next_pts, ..., opts) -- each point's wave tracks it forward and
+ * then its forward result back, so the launch has one fill and one tail
+ * instead of two.  The backward pass's residuals are not returned.
+ * Arguments as ot_lk_track_ex; back_pts n x 2 float32, back_status n (the
+ * caller's device buffers); err may be NULL; opts may be NULL (defaults; its
+ * base_level, margin and min_eig apply to both directions).
+ * Errors: as ot_lk_track_ex, OT_E_INVAL for null back_pts/back_status with
+ * n > 0, OT_E_UNSUPPORTED when opts asks for iters_out, lam_out or order. */
+OT_API ot_err ot_lk_track_fb(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* pts,
+                      int32_t n, int32_t win, int32_t levels, int32_t iters, float eps,
+                      float* next_pts, uint8_t* status, float* err, float* back_pts,
+                      uint8_t* back_status, const ot_lk_opts* opts, void* stream);
 
 /* Scaled box prediction: for box b in [0, m), over its points with
  * box_id == b and status == 1 (count c): (mx, my) = component-wise median

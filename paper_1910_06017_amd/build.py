@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libomnitrack.so")
-SOURCES = ["ot_lk.hip", "ot_lk_batch.hip", "ot_misc.hip", "ot_api.hip", "ot_match.hip", "ot_tvl1.hip"]
+SOURCES = ["ot_lk.hip", "ot_lk_fb.hip", "ot_lk_batch.hip", "ot_misc.hip", "ot_api.hip", "ot_match.hip", "ot_tvl1.hip"]
 ARCH = "gfx950"
 
 CXXFLAGS = [

@@ -194,6 +194,33 @@ ot_err ot_lk_track(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* 
                           err, nullptr, stream);
 }
 
+ot_err ot_lk_track_fb(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* pts,
+                      int32_t n, int32_t win, int32_t levels, int32_t iters, float eps,
+                      float* next_pts, uint8_t* status, float* err, float* back_pts,
+                      uint8_t* back_status, const ot_lk_opts* opts, void* stream) {
+    if (n < 0) return OT_E_INVAL;
+    if (!pyr_valid(prev_pyr) || !pyr_valid(next_pyr)) return OT_E_INVAL;
+    const int base = opts ? opts->base_level : 0;
+    if (base < 0 || base >= OT_MAX_LEVELS || levels > OT_MAX_LEVELS ||
+        levels + base > prev_pyr->levels || levels + base > next_pyr->levels)
+        return OT_E_INVAL;
+    if (prev_pyr->w[0] != next_pyr->w[0] || prev_pyr->h[0] != next_pyr->h[0]) return OT_E_SHAPE;
+    if (opts && (opts->iters_out || opts->lam_out || opts->order)) return OT_E_UNSUPPORTED;
+    LkParams prm;
+    const float min_eig = opts ? opts->min_eig : OT_DEFAULT_MIN_EIG;
+    const ot_err e = lk_params(win, levels, iters, eps, min_eig, opts ? opts->margin : 0, &prm);
+    if (e != OT_OK) return e;
+    prm.pscale = ldexpf(1.0f, -base);
+    prm.pscale_inv = ldexpf(1.0f, base);
+    if (n == 0) return OT_OK;
+    if (!pts || !next_pts || !status || !back_pts || !back_status) return OT_E_INVAL;
+    if (launch_lk_fb(to_dev(*prev_pyr, base), to_dev(*next_pyr, base), pts, n, prm, next_pts,
+                     status, err, back_pts, back_status,
+                     static_cast<hipStream_t>(stream)) != hipSuccess)
+        return OT_E_LAUNCH;
+    return OT_OK;
+}
+
 ot_err ot_lk_order(const uint8_t* iters, int32_t n, int32_t levels, int32_t* order,
                    void* stream) {
     if (n < 0 || n > (1 << 24) || levels < 1 || levels > OT_MAX_LEVELS) return OT_E_INVAL;

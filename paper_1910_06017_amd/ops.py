@@ -22,7 +22,7 @@ ERRORS = {0: "OT_OK", -1: "OT_E_INVAL", -2: "OT_E_SHAPE", -3: "OT_E_WORKSPACE",
 
 # Every symbol the header declares.
 EXPORTS = ["ot_pyramid_bytes", "ot_pyramid_layout", "ot_pyramid_build", "ot_lk_track",
-           "ot_lk_track_ex", "ot_lk_order", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled", "ot_box_scaled_bytes",
+           "ot_lk_track_ex", "ot_lk_track_fb", "ot_lk_order", "ot_box_update", "ot_fb_gate", "ot_box_update_scaled", "ot_box_scaled_bytes",
            "ot_box_update_scaled_noalloc",
            "ot_iou_matrix", "ot_assign", "ot_track_update", "ot_working_level",
            "ot_tvl1_default_params", "ot_tvl1_bytes", "ot_tvl1_flow", "ot_tvl1_flow_async",
@@ -103,6 +103,9 @@ def lib():
         L.ot_lk_track_ex.argtypes = [PP, PP, P, i32, i32, i32, i32, f32, P, P, P,
                                      C.POINTER(OtLkOpts), P]
         L.ot_lk_track_ex.restype = i32
+        L.ot_lk_track_fb.argtypes = [PP, PP, P, i32, i32, i32, i32, f32, P, P, P, P, P,
+                                     C.POINTER(OtLkOpts), P]
+        L.ot_lk_track_fb.restype = i32
         L.ot_lk_order.argtypes = [P, i32, i32, P, P]
         L.ot_lk_order.restype = i32
         L.ot_box_update.argtypes = [P, i32, P, P, P, P, i32, P, P, P]
@@ -299,6 +302,35 @@ def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None
     if want_diag:
         return next_pts, status, err, it, lam
     return next_pts, status, err
+
+
+def lk_track_fb(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None = None,
+                iters: int = 30, eps: float = 0.01, min_eig: float = OT_DEFAULT_MIN_EIG,
+                margin: int = 0, want_err: bool = True, out=None, stream=None,
+                base_level: int = 0):
+    """Track (n, 2) float32 points forward (prev -> nxt) and their forward
+    results back (nxt -> prev) in one launch.  Returns (next_pts, status,
+    err, back_pts, back_status), each as lk_track would give it; out, if
+    given, is that 5-tuple of buffers (err may be None)."""
+    torch = _torch()
+    _need(pts, torch.float32, 2, "pts")
+    n = pts.shape[0]
+    L = prev.levels - base_level if levels is None else levels
+    dev = pts.device
+    if out is None:
+        next_pts = torch.empty((n, 2), dtype=torch.float32, device=dev)
+        status = torch.empty(n, dtype=torch.uint8, device=dev)
+        err = torch.empty(n, dtype=torch.float32, device=dev) if want_err else None
+        back_pts = torch.empty((n, 2), dtype=torch.float32, device=dev)
+        back_status = torch.empty(n, dtype=torch.uint8, device=dev)
+    else:
+        next_pts, status, err, back_pts, back_status = out
+    opts = OtLkOpts(min_eig, None, None, margin, base_level, None)
+    check(lib().ot_lk_track_fb(C.byref(prev.desc), C.byref(nxt.desc), _ptr(pts), n, win, L,
+                               iters, eps, _ptr(next_pts), _ptr(status), _ptr(err),
+                               _ptr(back_pts), _ptr(back_status), C.byref(opts),
+                               _stream_handle(stream)), "ot_lk_track_fb")
+    return next_pts, status, err, back_pts, back_status
 
 
 def lk_order(iters, out=None, stream=None):

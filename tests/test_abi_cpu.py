@@ -32,7 +32,7 @@ def declared_symbols():
 
 def test_header_symbols_exported(L):
     syms = declared_symbols()
-    assert len(syms) == 29
+    assert len(syms) == 30
     assert syms == sorted(ops.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
@@ -153,6 +153,34 @@ def test_lk_validation(L):
     assert L.ot_lk_track_ex(C.byref(P), C.byref(Q), FAKE, 10, 21, 4, 30, 0.01, FAKE, FAKE,
                             None, C.byref(opts), None) == E
     del U
+
+
+def test_lk_fb_validation(L):
+    """ot_lk_track_fb validates as ot_lk_track_ex and needs both outputs of
+    the backward pass; it has no per-point diagnostics or order."""
+    _, P = layout(L)
+    _, Q = layout(L)
+    E, S, U = ops_err("OT_E_INVAL"), ops_err("OT_E_SHAPE"), ops_err("OT_E_UNSUPPORTED")
+
+    def fb(P=P, Q=Q, n=10, win=21, levels=4, back=FAKE, bst=FAKE, opts=None, pts=FAKE):
+        return L.ot_lk_track_fb(C.byref(P), C.byref(Q), pts, n, win, levels, 30, 0.01, FAKE,
+                                FAKE, None, back, bst, C.byref(opts) if opts else None, None)
+
+    assert fb(n=-1) == E
+    assert fb(win=20) == E
+    assert fb(levels=5) == E
+    assert fb(back=None) == E
+    assert fb(bst=None) == E
+    assert fb(pts=None) == E
+    assert fb(n=0, back=None, bst=None, pts=None) == 0      # no-op
+    _, Q2 = layout(L, W=640)
+    assert fb(Q=Q2) == S
+    for field in ("iters_out", "lam_out", "order"):
+        opts = ops.OtLkOpts(6.5, None, None, 0, 0, None)
+        setattr(opts, field, FAKE)
+        assert fb(opts=opts) == U, field
+    opts = ops.OtLkOpts(6.5, None, None, 0, 1)             # base + levels beyond the pyramids
+    assert fb(opts=opts) == E
 
 
 def test_box_validation(L):
