@@ -274,13 +274,14 @@ def test_box_scaled_many_equal_ratios(ops):
 
 
 @pytest.mark.parametrize("case", ["sd", "sd_margin6", "sd_win15", "sd_grads", "hd_level1",
-                                  "sd_few"])
+                                  "sd_few", "sd_invalid"])
 def test_fused_forward_backward_equals_two_calls(ops, case):
     """ot_lk_track_fb gives, bit for bit, the forward results of ot_lk_track
     on (prev, next) and the backward results of ot_lk_track on (next, prev)
     from those forward positions -- on the fixed-geometry kernels (margins 4
     and 6), a generic window, a template pyramid with materialized gradients,
-    a working level, and a launch of fewer points than one XCD chunk."""
+    a working level, a launch of fewer points than one XCD chunk, and points
+    outside the image or not a number (compared as bit patterns)."""
     w = synth.hd_boxes_workload() if case == "hd_level1" else synth.sd_boxes_workload()
     base = 1 if case == "hd_level1" else 0
     L = w.levels - base
@@ -288,7 +289,12 @@ def test_fused_forward_backward_equals_two_calls(ops, case):
     margin = 6 if case == "sd_margin6" else 0
     P = ops.pyramid_build(dev(w.frame0), w.levels, grads=(case == "sd_grads"))
     Q = ops.pyramid_build(dev(w.frame1), w.levels)
-    pts = dev(w.pts[:37] if case == "sd_few" else w.pts)
+    p = w.pts[:37] if case == "sd_few" else w.pts
+    if case == "sd_invalid":
+        p = w.pts[:40].copy()
+        p[:6] = [(-5.0, 10.0), (w.W + 3.0, 5.0), (np.nan, 3.0), (10.0, np.inf),
+                 (10.0, w.H - 0.5), (w.W - 1.0, w.H - 1.0)]
+    pts = dev(p)
     kw = dict(win=win, levels=L, iters=w.iters, eps=w.eps, margin=margin, base_level=base)
     nxt, st, err = ops.lk_track(P, Q, pts, **kw)
     back, stb, _ = ops.lk_track(Q, P, nxt, **kw)
@@ -296,6 +302,9 @@ def test_fused_forward_backward_equals_two_calls(ops, case):
     torch.cuda.synchronize()
     for name, a, b in (("next_pts", nxt, f[0]), ("status", st, f[1]), ("err", err, f[2]),
                        ("back_pts", back, f[3]), ("back_status", stb, f[4])):
+        a, b = a.contiguous(), b.contiguous()
+        if a.dtype == torch.float32:
+            a, b = a.view(torch.int32), b.view(torch.int32)
         assert torch.equal(a, b), (case, name)
     print(f"fused forward-backward {case}: n={pts.shape[0]} tracked fwd {int(st.sum())}, "
           f"back {int(stb.sum())}, identical")
