@@ -787,7 +787,8 @@ def bench_video(a):
     working level of its resolution: everything on one stream; the next
     frame's upload and pyramid prefetched on a second stream (Sec. V-B); and
     prefetched with the points tracked longest-first by their iteration counts
-    in the previous pair.  SD (720x576, level 0) and the 2K (2560x1280, level
+    in the previous pair; and prefetched with each frame's Scharr planes built
+    with its pyramid.  SD (720x576, level 0) and the 2K (2560x1280, level
     1) and 4K (4096x2048, level 2) sizes of the paper's runtime experiment,
     each a 12-frame cycle played 5 times (60 frames, re-seeded every 10th)."""
     import torch
@@ -805,10 +806,12 @@ def bench_video(a):
         rec = {"frames": len(frames), "points": npts, "boxes": nbox, "working_level": base,
                "levels": 4}
         results = {}
-        for key, pf, order in (("one_stream", False, False), ("prefetch", True, False),
-                               ("prefetch_order", True, True)):
+        for key, pf, order, grads in (("one_stream", False, False, False),
+                                      ("prefetch", True, False, False),
+                                      ("prefetch_order", True, True, False),
+                                      ("prefetch_grads", True, False, True)):
             trk = video.VideoTracker(W, H, levels=4, base_level=base, n_max=npts, m_max=nbox,
-                                     prefetch=pf, order=order)
+                                     prefetch=pf, order=order, grads=grads)
             trk.track(frames[:12], seeds)           # warm-up
             torch.cuda.synchronize()
             best = None
@@ -822,11 +825,12 @@ def bench_video(a):
                         "frames_per_s": (len(frames) - 1) / best,
                         "tracked_points_per_s": npts * (len(frames) - 1) / best}
         rec["identical"] = all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
-                               for k in ("prefetch", "prefetch_order")
+                               for k in ("prefetch", "prefetch_order", "prefetch_grads")
                                for x, y in zip(results["one_stream"], results[k]))
         base_ms = rec["one_stream"]["ms_per_frame"]
         rec["speedup_prefetch"] = base_ms / rec["prefetch"]["ms_per_frame"]
         rec["speedup_prefetch_order"] = base_ms / rec["prefetch_order"]["ms_per_frame"]
+        rec["speedup_prefetch_grads"] = base_ms / rec["prefetch_grads"]["ms_per_frame"]
         out[f"{W}x{H}"] = rec
     return out
 

@@ -59,11 +59,15 @@ class VideoTracker:
 
     W, H: frame size; levels: tracking levels counted from the working
     level `base_level` (the pyramids hold base_level + levels levels);
-    n_max / m_max: point and box capacities."""
+    n_max / m_max: point and box capacities.  With `grads`, each frame's
+    pyramid also gets its Scharr planes when it is built (on the
+    preprocessing stream), and the pair that uses it as the first frame reads
+    them instead of computing them (the same results, bit for bit)."""
 
     def __init__(self, W: int, H: int, levels: int, base_level: int = 0, n_max: int = 20000,
                  m_max: int = 64, win: int = 21, iters: int = 30, eps: float = 0.01,
-                 prefetch: bool = True, order: bool = False, device="cuda"):
+                 prefetch: bool = True, order: bool = False, grads: bool = False,
+                 device="cuda"):
         import torch
 
         from .serve import _copy  # noqa: F401  (host<->device copies without the dispatcher)
@@ -76,8 +80,10 @@ class VideoTracker:
         PL = base_level + levels
         self.PL = PL
         self.frames = [torch.empty((H, W), dtype=torch.uint8, device=self.dev) for _ in range(3)]
-        self.ws = [ops.alloc_workspace(W, H, PL, self.dev) for _ in range(3)]
-        self.pyr = [ops.pyramid_layout(self.frames[i], PL, self.ws[i]) for i in range(3)]
+        self.grads = grads
+        self.ws = [ops.alloc_workspace(W, H, PL, self.dev, grads=grads) for _ in range(3)]
+        self.pyr = [ops.pyramid_layout(self.frames[i], PL, self.ws[i], grads=grads)
+                    for i in range(3)]
         n, m = max(1, n_max), max(1, m_max)
         self.n_max, self.m_max = n_max, m_max
         self.pts = [torch.zeros((n, 2), dtype=torch.float32, device=self.dev) for _ in range(2)]
@@ -111,7 +117,7 @@ class VideoTracker:
             sp.wait_event(after_track)
         _copy(self.frames[i].data_ptr(), frame.data_ptr(), frame.numel(), _H2D,
               int(sp.cuda_stream))
-        ops.pyramid_build(self.frames[i], self.PL, ws=self.ws[i], stream=sp)
+        ops.pyramid_build(self.frames[i], self.PL, ws=self.ws[i], stream=sp, grads=self.grads)
         ev = self.torch.cuda.Event()
         ev.record(sp)
         return ev

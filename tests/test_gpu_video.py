@@ -1,6 +1,7 @@
 """One video stream tracked frame by frame at its working level, with and
-without the prefetch of the next frame's preprocessing (Sec. V-B) and the
-longest-first order from the previous pair's iteration counts: all give
+without the prefetch of the next frame's preprocessing (Sec. V-B), the
+longest-first order from the previous pair's iteration counts and the
+Scharr planes built with each frame's pyramid: all give
 identical boxes and counts on every frame (same kernels, same inputs, only
 the streams and the order of the points differ), and the frames right after
 a re-seed match the oracle's tracker and box update at the working level
@@ -38,9 +39,10 @@ def test_prefetch_and_order_give_identical_results(env):
     base = ops.working_level(s.W, s.H)
     assert base == 1
     runs = []
-    for pf, order in ((False, False), (True, False), (True, True)):
+    for pf, order, grads in ((False, False, False), (True, False, False), (True, True, False),
+                             (True, False, True)):
         trk = video.VideoTracker(s.W, s.H, levels=4, base_level=base, n_max=4000, m_max=16,
-                                 prefetch=pf, order=order)
+                                 prefetch=pf, order=order, grads=grads)
         runs.append(trk.track(frames, seeds))
     assert len(runs[0]) == len(frames) - 1
     for other in runs[1:]:
