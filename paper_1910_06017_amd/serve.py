@@ -19,11 +19,10 @@ the same frames one at a time with the per-stream calls for comparison.
 from __future__ import annotations
 
 import gc
-import heapq
 import math
 import time
 from collections import deque
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
