@@ -246,16 +246,22 @@ OT_API ot_err ot_fb_gate(const float* pts, const float* back_pts, const uint8_t*
  * opts), and back_pts, back_status exactly those of ot_lk_track_ex(next_pyr,
  * prev_pyr, next_pts, ..., opts) -- each point's wave tracks it forward and
  * then its forward result back, so the launch has one fill and one tail
- * instead of two.  The backward pass's residuals are not returned.
- * Arguments as ot_lk_track_ex; back_pts n x 2 float32, back_status n (the
- * caller's device buffers); err may be NULL; opts may be NULL (defaults; its
- * base_level, margin and min_eig apply to both directions).
+ * instead of two.  The backward pass's residuals are not returned.  With
+ * kept non-NULL the forward-backward gate follows in the same launch: kept
+ * and fb_err are exactly ot_fb_gate(pts, back_pts, status, back_status, n,
+ * fb_max, fb_err, kept).
+ * Arguments as ot_lk_track_ex; back_pts n x 2 float32, back_status n, kept n,
+ * fb_err n float32 (the caller's device buffers); err and fb_err may be NULL,
+ * kept NULL skips the gate (fb_max is then ignored); opts may be NULL
+ * (defaults; its base_level, margin and min_eig apply to both directions).
  * Errors: as ot_lk_track_ex, OT_E_INVAL for null back_pts/back_status with
- * n > 0, OT_E_UNSUPPORTED when opts asks for iters_out, lam_out or order. */
+ * n > 0, fb_max negative or NaN with kept set, or fb_err not 4-byte aligned;
+ * OT_E_UNSUPPORTED when opts asks for iters_out, lam_out or order. */
 OT_API ot_err ot_lk_track_fb(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* pts,
                       int32_t n, int32_t win, int32_t levels, int32_t iters, float eps,
                       float* next_pts, uint8_t* status, float* err, float* back_pts,
-                      uint8_t* back_status, const ot_lk_opts* opts, void* stream);
+                      uint8_t* back_status, float fb_max, float* fb_err, uint8_t* kept,
+                      const ot_lk_opts* opts, void* stream);
 
 /* Scaled box prediction: for box b in [0, m), over its points with
  * box_id == b and status == 1 (count c): (mx, my) = component-wise median

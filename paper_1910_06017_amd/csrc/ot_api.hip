@@ -197,8 +197,10 @@ ot_err ot_lk_track(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* 
 ot_err ot_lk_track_fb(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const float* pts,
                       int32_t n, int32_t win, int32_t levels, int32_t iters, float eps,
                       float* next_pts, uint8_t* status, float* err, float* back_pts,
-                      uint8_t* back_status, const ot_lk_opts* opts, void* stream) {
+                      uint8_t* back_status, float fb_max, float* fb_err, uint8_t* kept,
+                      const ot_lk_opts* opts, void* stream) {
     if (n < 0) return OT_E_INVAL;
+    if (kept && !(fb_max >= 0.0f)) return OT_E_INVAL;  // also NaN
     if (!pyr_valid(prev_pyr) || !pyr_valid(next_pyr)) return OT_E_INVAL;
     const int base = opts ? opts->base_level : 0;
     if (base < 0 || base >= OT_MAX_LEVELS || levels > OT_MAX_LEVELS ||
@@ -214,8 +216,9 @@ ot_err ot_lk_track_fb(const ot_pyr* prev_pyr, const ot_pyr* next_pyr, const floa
     prm.pscale_inv = ldexpf(1.0f, base);
     if (n == 0) return OT_OK;
     if (!pts || !next_pts || !status || !back_pts || !back_status) return OT_E_INVAL;
+    if (((uintptr_t)fb_err & 3) != 0) return OT_E_INVAL;
     if (launch_lk_fb(to_dev(*prev_pyr, base), to_dev(*next_pyr, base), pts, n, prm, next_pts,
-                     status, err, back_pts, back_status,
+                     status, err, back_pts, back_status, fb_max, fb_err, kept,
                      static_cast<hipStream_t>(stream)) != hipSuccess)
         return OT_E_LAUNCH;
     return OT_OK;

@@ -1076,6 +1076,20 @@ __device__ __forceinline__ void scaled_final(const float* __restrict__ boxes, in
 
 // Forward-backward gate (Kalal et al. 2010): a point keeps status 1 when it
 // was tracked forward and back and lands within fb_max of where it started.
+// The gate of one point from its start p, its backward result q and the two
+// statuses: the forward-backward error e (-1 unless both passes tracked it)
+// and whether it is kept.
+__device__ __forceinline__ void fb_gate_value(float2 p, float2 q, unsigned sf, unsigned sb,
+                                              float fb_max, float& e, uint8_t& st) {
+    e = -1.0f;
+    st = 0;
+    if (sf == 1 && sb == 1) {
+        const float ex = p.x - q.x, ey = p.y - q.y;
+        e = __builtin_sqrtf(__builtin_fmaf(ex, ex, ey * ey));
+        st = e <= fb_max ? 1 : 0;
+    }
+}
+
 __device__ __forceinline__ void fb_gate_point(const float* __restrict__ pts,
                                               const float* __restrict__ back_pts,
                                               const uint8_t* __restrict__ st_fwd,
@@ -1084,13 +1098,9 @@ __device__ __forceinline__ void fb_gate_point(const float* __restrict__ pts,
                                               uint8_t* __restrict__ status_out) {
     const float2 p = reinterpret_cast<const float2*>(pts)[i];
     const float2 q = reinterpret_cast<const float2*>(back_pts)[i];
-    float e = -1.0f;
-    uint8_t st = 0;
-    if (st_fwd[i] == 1 && st_bwd[i] == 1) {
-        const float ex = p.x - q.x, ey = p.y - q.y;
-        e = __builtin_sqrtf(__builtin_fmaf(ex, ex, ey * ey));
-        st = e <= fb_max ? 1 : 0;
-    }
+    float e;
+    uint8_t st;
+    fb_gate_value(p, q, st_fwd[i], st_bwd[i], fb_max, e, st);
     if (fb_err) fb_err[i] = e;
     status_out[i] = st;
 }

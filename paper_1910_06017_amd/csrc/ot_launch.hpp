@@ -23,10 +23,12 @@ hipError_t launch_lk(const DevPyr& prev, const DevPyr& next, const float* pts, i
 
 // Forward then backward tracking of every point in one launch (next_pts,
 // status, err as launch_lk(prev, next); back_pts, back_status as
-// launch_lk(next, prev) on next_pts).
+// launch_lk(next, prev) on next_pts), then, with kept set, the
+// forward-backward gate (kept, fb_err as launch_fb_gate).
 hipError_t launch_lk_fb(const DevPyr& prev, const DevPyr& next, const float* pts, int n,
                         const LkParams& prm, float* next_pts, uint8_t* status, float* err,
-                        float* back_pts, uint8_t* back_status, hipStream_t stream);
+                        float* back_pts, uint8_t* back_status, float fb_max, float* fb_err,
+                        uint8_t* kept, hipStream_t stream);
 
 // Points by descending total iteration count (one workgroup, counting sort).
 hipError_t launch_lk_order(const uint8_t* iters, int n, int levels, int32_t* order,

@@ -5,7 +5,9 @@
 // the single-call tracker's per-point routine on the same inputs, so both
 // results are bit for bit those of two ot_lk_track calls; one launch holds
 // every point's whole chain, so the launch pays one fill and one tail where
-// two launches pay two.
+// two launches pay two.  Optionally the forward-backward gate of each point
+// follows, with the gate call's own arithmetic.
+#include "ot_box.hpp"
 #include "ot_launch.hpp"
 #include "ot_lk_sched.hpp"
 
@@ -18,7 +20,9 @@ __global__ __launch_bounds__(64) void k_lk_track_fb(DevPyr P, DevPyr Q, const fl
                                                     uint8_t* __restrict__ status,
                                                     float* __restrict__ err,
                                                     float* __restrict__ back_pts,
-                                                    uint8_t* __restrict__ back_status) {
+                                                    uint8_t* __restrict__ back_status,
+                                                    float fb_max, float* __restrict__ fb_err,
+                                                    uint8_t* __restrict__ kept) {
     extern __shared__ __align__(16) unsigned char lk_smem[];
     const int i = lk_item(blockIdx.x, gridDim.x);
     if (i >= n) return;
@@ -45,20 +49,31 @@ __global__ __launch_bounds__(64) void k_lk_track_fb(DevPyr P, DevPyr Q, const fl
         Q, P, fx * prm.pscale, fy * prm.pscale, L, prm.iters, prm.eps2, prm.min_eig, g, lk_smem,
         nullptr, nullptr);
     if ((threadIdx.x & 63) == 0) {
-        back_pts[2 * i] = b.nx * prm.pscale_inv;
-        back_pts[2 * i + 1] = b.ny * prm.pscale_inv;
+        const float2 q = make_float2(b.nx * prm.pscale_inv, b.ny * prm.pscale_inv);
+        back_pts[2 * i] = q.x;
+        back_pts[2 * i + 1] = q.y;
         back_status[i] = (uint8_t)b.status;
+        if (kept) {
+            float e;
+            uint8_t st;
+            fb_gate_value(make_float2(pts[2 * i], pts[2 * i + 1]), q, (unsigned)f.status,
+                          (unsigned)b.status, fb_max, e, st);
+            kept[i] = st;
+            if (fb_err) fb_err[i] = e;
+        }
     }
 }
 
 hipError_t launch_lk_fb(const DevPyr& prev, const DevPyr& next, const float* pts, int n,
                         const LkParams& prm, float* next_pts, uint8_t* status, float* err,
-                        float* back_pts, uint8_t* back_status, hipStream_t stream) {
+                        float* back_pts, uint8_t* back_status, float fb_max, float* fb_err,
+                        uint8_t* kept, hipStream_t stream) {
     const int R = lk_template_rows(prm.win);
     const size_t lds = lk_lds_bytes(prm.win, R, prm.margin);
 #define OT_LAUNCH(...)                                                                           \
     hipLaunchKernelGGL((k_lk_track_fb<__VA_ARGS__>), dim3(n), dim3(64), lds, stream, prev, next, \
-                       pts, n, prm, next_pts, status, err, back_pts, back_status)
+                       pts, n, prm, next_pts, status, err, back_pts, back_status, fb_max,   \
+                       fb_err, kept)
     if (R == 7 && prm.win == 21 && (prm.margin == 4 || prm.margin == 6)) {
         if (prm.margin == 4) OT_LAUNCH(7, 21, 4); else OT_LAUNCH(7, 21, 6);
         return hipGetLastError();

@@ -104,7 +104,7 @@ def lib():
                                      C.POINTER(OtLkOpts), P]
         L.ot_lk_track_ex.restype = i32
         L.ot_lk_track_fb.argtypes = [PP, PP, P, i32, i32, i32, i32, f32, P, P, P, P, P,
-                                     C.POINTER(OtLkOpts), P]
+                                     f32, P, P, C.POINTER(OtLkOpts), P]
         L.ot_lk_track_fb.restype = i32
         L.ot_lk_order.argtypes = [P, i32, i32, P, P]
         L.ot_lk_order.restype = i32
@@ -307,11 +307,13 @@ def lk_track(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None
 def lk_track_fb(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | None = None,
                 iters: int = 30, eps: float = 0.01, min_eig: float = OT_DEFAULT_MIN_EIG,
                 margin: int = 0, want_err: bool = True, out=None, stream=None,
-                base_level: int = 0):
+                base_level: int = 0, fb_max: float | None = None, gate_out=None):
     """Track (n, 2) float32 points forward (prev -> nxt) and their forward
     results back (nxt -> prev) in one launch.  Returns (next_pts, status,
     err, back_pts, back_status), each as lk_track would give it; out, if
-    given, is that 5-tuple of buffers (err may be None)."""
+    given, is that 5-tuple of buffers (err may be None).  With fb_max the
+    forward-backward gate follows in the same launch and (kept, fb_err), as
+    fb_gate would give them, are appended (gate_out: that pair of buffers)."""
     torch = _torch()
     _need(pts, torch.float32, 2, "pts")
     n = pts.shape[0]
@@ -325,11 +327,21 @@ def lk_track_fb(prev: Pyramid, nxt: Pyramid, pts, win: int = 21, levels: int | N
         back_status = torch.empty(n, dtype=torch.uint8, device=dev)
     else:
         next_pts, status, err, back_pts, back_status = out
+    kept = fb_err = None
+    if fb_max is not None:
+        if gate_out is None:
+            kept = torch.empty(n, dtype=torch.uint8, device=dev)
+            fb_err = torch.empty(n, dtype=torch.float32, device=dev)
+        else:
+            kept, fb_err = gate_out
     opts = OtLkOpts(min_eig, None, None, margin, base_level, None)
     check(lib().ot_lk_track_fb(C.byref(prev.desc), C.byref(nxt.desc), _ptr(pts), n, win, L,
                                iters, eps, _ptr(next_pts), _ptr(status), _ptr(err),
-                               _ptr(back_pts), _ptr(back_status), C.byref(opts),
-                               _stream_handle(stream)), "ot_lk_track_fb")
+                               _ptr(back_pts), _ptr(back_status),
+                               0.0 if fb_max is None else fb_max, _ptr(fb_err), _ptr(kept),
+                               C.byref(opts), _stream_handle(stream)), "ot_lk_track_fb")
+    if fb_max is not None:
+        return next_pts, status, err, back_pts, back_status, kept, fb_err
     return next_pts, status, err, back_pts, back_status
 
 

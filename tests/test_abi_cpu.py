@@ -156,15 +156,18 @@ def test_lk_validation(L):
 
 
 def test_lk_fb_validation(L):
-    """ot_lk_track_fb validates as ot_lk_track_ex and needs both outputs of
-    the backward pass; it has no per-point diagnostics or order."""
+    """ot_lk_track_fb validates as ot_lk_track_ex, needs both outputs of the
+    backward pass and, with the gate, a threshold as ot_fb_gate does; it has
+    no per-point diagnostics or order."""
     _, P = layout(L)
     _, Q = layout(L)
     E, S, U = ops_err("OT_E_INVAL"), ops_err("OT_E_SHAPE"), ops_err("OT_E_UNSUPPORTED")
 
-    def fb(P=P, Q=Q, n=10, win=21, levels=4, back=FAKE, bst=FAKE, opts=None, pts=FAKE):
+    def fb(P=P, Q=Q, n=10, win=21, levels=4, back=FAKE, bst=FAKE, opts=None, pts=FAKE,
+           fb_max=1.0, fb_err=None, kept=None):
         return L.ot_lk_track_fb(C.byref(P), C.byref(Q), pts, n, win, levels, 30, 0.01, FAKE,
-                                FAKE, None, back, bst, C.byref(opts) if opts else None, None)
+                                FAKE, None, back, bst, fb_max, fb_err, kept,
+                                C.byref(opts) if opts else None, None)
 
     assert fb(n=-1) == E
     assert fb(win=20) == E
@@ -181,6 +184,11 @@ def test_lk_fb_validation(L):
         assert fb(opts=opts) == U, field
     opts = ops.OtLkOpts(6.5, None, None, 0, 1)             # base + levels beyond the pyramids
     assert fb(opts=opts) == E
+    # the gate's threshold is checked only when the gate runs
+    assert fb(fb_max=-1.0, kept=FAKE) == E
+    assert fb(fb_max=float("nan"), kept=FAKE) == E
+    assert fb(kept=FAKE, fb_err=FAKE + 2) == E              # fb_err not 4-aligned
+    assert fb(n=0, back=None, bst=None, pts=None, fb_max=-1.0) == 0
 
 
 def test_box_validation(L):

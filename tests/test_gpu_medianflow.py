@@ -281,7 +281,8 @@ def test_fused_forward_backward_equals_two_calls(ops, case):
     from those forward positions -- on the fixed-geometry kernels (margins 4
     and 6), a generic window, a template pyramid with materialized gradients,
     a working level, a launch of fewer points than one XCD chunk, and points
-    outside the image or not a number (compared as bit patterns)."""
+    outside the image or not a number (compared as bit patterns); with the
+    gate in the same launch, its outputs equal ot_fb_gate's."""
     w = synth.hd_boxes_workload() if case == "hd_level1" else synth.sd_boxes_workload()
     base = 1 if case == "hd_level1" else 0
     L = w.levels - base
@@ -298,10 +299,14 @@ def test_fused_forward_backward_equals_two_calls(ops, case):
     kw = dict(win=win, levels=L, iters=w.iters, eps=w.eps, margin=margin, base_level=base)
     nxt, st, err = ops.lk_track(P, Q, pts, **kw)
     back, stb, _ = ops.lk_track(Q, P, nxt, **kw)
+    kept, fe = ops.fb_gate(pts, back, st, stb, 1.0)
     f = ops.lk_track_fb(P, Q, pts, **kw)
+    g = ops.lk_track_fb(P, Q, pts, fb_max=1.0, **kw)
     torch.cuda.synchronize()
     for name, a, b in (("next_pts", nxt, f[0]), ("status", st, f[1]), ("err", err, f[2]),
-                       ("back_pts", back, f[3]), ("back_status", stb, f[4])):
+                       ("back_pts", back, f[3]), ("back_status", stb, f[4]),
+                       ("gated next_pts", nxt, g[0]), ("gated back_pts", back, g[3]),
+                       ("kept", kept, g[5]), ("fb_err", fe, g[6])):
         a, b = a.contiguous(), b.contiguous()
         if a.dtype == torch.float32:
             a, b = a.view(torch.int32), b.view(torch.int32)
