@@ -719,6 +719,7 @@ class PlainExecutor:
         self.sh = int(self.stream.cuda_stream)
         self.opts = ops.OtLkOpts(ops.OT_DEFAULT_MIN_EIG, None, None, 0, 0, None)
         self.ticks = 0
+        torch.cuda.synchronize(self.device)  # the arena's fills precede the stream's work
 
     def admit(self, spec: StreamSpec):
         self.slots[spec.sid] = _Slot(spec, self.device, self.arena, self.stream)
